@@ -1,0 +1,205 @@
+"""Plain FP64 CPU oracle for the Z4c right-hand side + RK4 step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
+(``paper_2607_08743_amd``) never imports it and shares no code with it: the C
+source ``z4c_oracle.c`` is an independent, per-point transcription of the
+equations (paper Sec. 2.1.1 variables and gauge, Sec. 2.2 discretisation,
+Sec. 2.2.2 Sommerfeld condition) and of the readings listed in its header.
+
+Pins (each one is a test under ``tests/`` that checks the oracle against
+something other than itself):
+
+* stencils: exact on low-degree polynomials, 4th-order convergence, KO grid-mode
+  eigenvalue -64, upwind bias gives a dissipative (stable) symbol;
+* flat space: every right-hand side is exactly 0.0 and the state is unchanged;
+* Schwarzschild in Kerr-Schild coordinates (analytic, SymPy): the 17 geometric
+  right-hand sides vanish at O(h^4); gauge rows match their closed forms;
+* Brill-Lindquist: Hamiltonian constraint drives N[Theta] -> 0 at O(h^4), and
+  N[Khat] matches -D^2 alpha = -2 psi^-8 |grad psi|^2 (Laplace-Beltrami);
+* conformally-flat / general data: N[At] matches the ADM-derived trace-free
+  W^2(-D_iD_j alpha + alpha R_ij) computed from the physical metric;
+* linearised plane wave propagates one period at 4th order;
+* Z4 damping: homogeneous Theta and Z modes decay at rates kappa1(2+kappa2) and
+  kappa1 through the classical RK4 amplification polynomial;
+* Sommerfeld: F(t-r)/r gives the exact time derivative at 2nd order;
+* pi symmetry: symmetrised data stays bitwise symmetric.
+
+Parity unpinned (no physics pin distinguishes them; both paths must agree):
+the kappa3 terms (default 0), ``lapse_uses_K`` and the use of the computed
+Gamma_d in the Lie-derivative terms of the Gt equation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "z4c_oracle.c")
+LIB = os.path.join(HERE, "liboracle_z4c.so")
+
+NF = 25
+BC_PERIODIC, BC_SOMMERFELD, BC_COPY = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class OzParams(ctypes.Structure):
+    _fields_ = [("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+                ("eta", ctypes.c_double), ("shift_coeff", ctypes.c_double), ("ko_sigma", ctypes.c_double),
+                ("w_floor", ctypes.c_double), ("lapse_uses_K", ctypes.c_int)]
+
+
+def params(kappa1=0.005, kappa2=0.0, kappa3=0.0, eta=0.36, shift_coeff=0.75, ko_sigma=0.5,
+           w_floor=1e-10, lapse_uses_K=0) -> OzParams:
+    """Defaults: kappa1, kappa2, eta from the paper's run settings (Sec. 3),
+    sigma_KO = 0.5 and the 0.75 shift coefficient from Sec. 2.2 / Sec. 2.1.1."""
+    return OzParams(kappa1, kappa2, kappa3, eta, shift_coeff, ko_sigma, w_floor, lapse_uses_K)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        geo = [ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.oz_rhs.argtypes = [dp, dp] + geo + [ctypes.POINTER(OzParams), ctypes.c_int]
+        L.oz_rhs_points.argtypes = [dp] + geo + [ctypes.POINTER(OzParams), ip, ctypes.c_long, dp, ctypes.c_int]
+        L.oz_apply_ghosts.argtypes = [dp, dp, ctypes.c_long] + [ctypes.c_int] * 5
+        L.oz_enforce.argtypes = [dp, ctypes.c_long] + [ctypes.c_int] * 5
+        L.oz_stage_points.argtypes = [dp, dp, ctypes.c_double] + geo + [ctypes.POINTER(OzParams), ip,
+                                                                         ctypes.c_long, dp, ctypes.c_int]
+        L.oz_rk4.argtypes = [dp, dp] + geo + [ctypes.POINTER(OzParams), ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int]
+        L.oz_stencil_1d.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        L.oz_mixed_2d.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        for name in ("oz_rhs", "oz_rhs_points", "oz_apply_ghosts", "oz_enforce", "oz_stage_points", "oz_rk4",
+                     "oz_stencil_1d", "oz_mixed_2d"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise RuntimeError(f"oracle {name} failed with status {rc}")
+
+
+def _geo(g):
+    """g: dict with n (3), ng, h (3), x0 (3), bc -> ctypes argument tuple (without sf)."""
+    n, ng, h, x0 = g["n"], g["ng"], g["h"], g["x0"]
+    return (int(n[0]), int(n[1]), int(n[2]), int(ng), float(h[0]), float(h[1]), float(h[2]),
+            float(x0[0]), float(x0[1]), float(x0[2]), int(g["bc"]))
+
+
+def _state(u):
+    if u.dtype != np.float64 or not u.flags.c_contiguous or u.ndim != 4 or u.shape[0] != NF:
+        raise ValueError("state must be a C-contiguous float64 array of shape (25, Nz, Ny, Nx)")
+    return u
+
+
+def threads_default() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def rhs(u, g, p=None, nthreads=None) -> np.ndarray:
+    """Right-hand side on every evolved point (active; plus outer ghosts for a
+    Sommerfeld box).  Ghosts of ``u`` must already be valid."""
+    _state(u)
+    p = p or params()
+    out = np.zeros_like(u)
+    sf = u[0].size
+    _check(lib().oz_rhs(_dp(u), _dp(out), sf, *_geo(g), ctypes.byref(p), nthreads or threads_default()), "rhs")
+    return out
+
+
+def rhs_points(u, g, pts, p=None, nthreads=None) -> np.ndarray:
+    """Right-hand side at stored-index points pts (M, 3) as (i, j, k) -> (M, 25)."""
+    _state(u)
+    p = p or params()
+    pts = np.ascontiguousarray(pts, dtype=np.int32)
+    out = np.zeros((len(pts), NF))
+    _check(lib().oz_rhs_points(_dp(u), u[0].size, *_geo(g), ctypes.byref(p),
+                               pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(pts), _dp(out),
+                               nthreads or threads_default()), "rhs_points")
+    return out
+
+
+def stage_points(u_in, u_n, c_dt, g, pts, p=None, nthreads=None) -> np.ndarray:
+    """enforce(u_n + c_dt * rhs(u_in)) at points pts (M, 3) -> (M, 25)."""
+    _state(u_in)
+    _state(u_n)
+    p = p or params()
+    pts = np.ascontiguousarray(pts, dtype=np.int32)
+    out = np.zeros((len(pts), NF))
+    _check(lib().oz_stage_points(_dp(u_in), _dp(u_n), float(c_dt), u_in[0].size, *_geo(g), ctypes.byref(p),
+                                 pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(pts), _dp(out),
+                                 nthreads or threads_default()), "stage_points")
+    return out
+
+
+def apply_ghosts(u, g, shell=None) -> None:
+    _state(u)
+    n, ng = g["n"], g["ng"]
+    sh = None if shell is None else _dp(np.ascontiguousarray(shell, dtype=np.float64))
+    _check(lib().oz_apply_ghosts(_dp(u), sh, u[0].size, int(n[0]), int(n[1]), int(n[2]), int(ng), int(g["bc"])),
+           "apply_ghosts")
+
+
+def enforce(u, g) -> None:
+    _state(u)
+    n, ng = g["n"], g["ng"]
+    _check(lib().oz_enforce(_dp(u), u[0].size, int(n[0]), int(n[1]), int(n[2]), int(ng), int(g["bc"])),
+           "enforce")
+
+
+def rk4(u, g, dt, nsteps, p=None, shell=None, nthreads=None) -> None:
+    """Advance u in place by nsteps classical RK4 steps of size dt."""
+    _state(u)
+    p = p or params()
+    sh = None
+    if shell is not None:
+        shell = np.ascontiguousarray(shell, dtype=np.float64)
+        sh = _dp(shell)
+    _check(lib().oz_rk4(_dp(u), sh, u[0].size, *_geo(g), ctypes.byref(p), float(dt), int(nsteps),
+                        nthreads or threads_default()), "rk4")
+
+
+def stencil_1d(op, f, h, beta_sign=1.0) -> np.ndarray:
+    """op: 'd1', 'd2', 'up', 'ko' applied at interior points [3, n-3)."""
+    code = {"d1": 0, "d2": 1, "up": 2, "ko": 3}[op]
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    _check(lib().oz_stencil_1d(code, _dp(f), len(f), float(h), float(beta_sign), _dp(out)), "stencil_1d")
+    return out
+
+
+def mixed_2d(f, hx, hy) -> np.ndarray:
+    """D1_x(D1_y f) on a (ny, nx) array at interior points."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    _check(lib().oz_mixed_2d(_dp(f), f.shape[1], f.shape[0], float(hx), float(hy), _dp(out)), "mixed_2d")
+    return out

@@ -1,0 +1,703 @@
+/*
+ * z4c_oracle.c -- plain, slow, FP64 reference of the vacuum Z4c evolution
+ * step.  TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark are the only callers.  It shares no code,
+ * header or constant table with the HIP library; it is written straight from
+ * the equations, one grid point at a time, with full 3x3 index loops.
+ *
+ * What it computes (paper: "SACRA-K", arXiv 2607.08743):
+ *   - evolved variables W, gt_ij, Khat, At_ij, Gt^i, Theta, alpha, beta^i, B^i
+ *     (Sec. 2.1.1, conformal-variable definitions and the gauge equations);
+ *   - the Z4c right-hand side in the W form of the Z4c literature the paper
+ *     cites in Sec. 2.1.1 (Bernuzzi & Hilditch 2010; Hilditch et al. 2013),
+ *     with constraint damping kappa1, kappa2 (and kappa3, default 0);
+ *   - 1+log slicing and the Gamma-driver shift with coefficient 0.75 and
+ *     damping eta (Sec. 2.1.1, gauge equations);
+ *   - 4th-order centred first/second differences, 4th-order upwinded shift
+ *     advection biased by the sign of the shift, 6th-order Kreiss-Oliger
+ *     dissipation with sigma = 0.5 (Sec. 2.2, spatial discretisation);
+ *   - classical RK4 in method-of-lines form (Sec. 2.2);
+ *   - the Sommerfeld outgoing condition on the outer boundary (Sec. 2.2.2);
+ *   - enforcement of det gt = 1 and tr At = 0 (Sec. 2.1.1 states both hold
+ *     by construction; how they are restored is a reading, see below).
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - K in the 1+log condition is Khat unless lapse_uses_K = 1 (then Khat+2Theta);
+ *   - the mixed derivative is the tensor product D1_a(D1_b f), a < b;
+ *   - the upwind stencil is the 5-point lopsided one, shifted toward +s with
+ *     s = +1 when beta^d >= 0;
+ *   - KO acts on all 25 fields at active points, +sigma/(64 h) * delta^6;
+ *   - outer-boundary ghost points of a Sommerfeld box are evolved with
+ *     -(x^i/r) d_i f - (f - f_flat)/r, 2nd-order differences (one-sided at
+ *     the array edge), speed 1 for every field;
+ *   - enforcement: gt <- gt / cbrt(det gt), then At <- At - gt (gu.At)/3 with
+ *     gu the inverse of the rescaled gt;
+ *   - 1/W in the Gt equation uses max(W, w_floor).
+ *
+ * Data layout (numpy order [f][k][j][i], x fastest):
+ *   u[f*sf + (k*Ny + j)*Nx + i], Nx = nx + 2 ng, ..., i in [0, Nx).
+ *   Active cells are i in [ng, ng+nx); cell centre x = x0 + (i - ng) * dx.
+ *
+ * Compile: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp (no FMA
+ * contraction, so the pi-mirror pairs round identically).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NF 25
+
+/* field indices */
+enum {
+    IW = 0, IGT = 1, /* gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz : 1..6 */
+    IKH = 7, IAT = 8, /* At_xx .. At_zz : 8..13 */
+    IGAM = 14,        /* Gt^x Gt^y Gt^z : 14..16 */
+    ITH = 17, IAL = 18, IBE = 19, /* beta^x..z : 19..21 */
+    IBB = 22          /* B^x..z : 22..24 */
+};
+
+enum { BC_PERIODIC = 0, BC_SOMMERFELD = 1, BC_COPY = 2 };
+
+typedef struct {
+    double kappa1, kappa2, kappa3, eta, shift_coeff, ko_sigma, w_floor;
+    int lapse_uses_K;
+} oz_params;
+
+typedef struct {
+    int n[3];     /* active cells per direction */
+    int ng;       /* ghost width */
+    int N[3];     /* stored points per direction */
+    long sf;      /* stride between fields */
+    double h[3];  /* spacing */
+    double x0[3]; /* centre of the first active cell */
+    int bc;
+} grid;
+
+/* storage slot of the symmetric pair (a,b) inside gt_ij / At_ij */
+static const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+
+/* value at infinity (flat space) of every field */
+static double flat_value(int f)
+{
+    if (f == IW || f == IAL) return 1.0;
+    if (f == IGT + 0 || f == IGT + 3 || f == IGT + 5) return 1.0;
+    return 0.0;
+}
+
+static long lin(const grid* g, int i, int j, int k)
+{
+    return ((long)k * g->N[1] + j) * g->N[0] + i;
+}
+
+/* f at the point P shifted by s cells along direction d */
+static double fv(const double* u, const grid* g, int f, const int P[3], int d, int s)
+{
+    int Q[3] = {P[0], P[1], P[2]};
+    Q[d] += s;
+    return u[f * g->sf + lin(g, Q[0], Q[1], Q[2])];
+}
+
+/* ------------------------------------------------------------------ */
+/* Stencils (Sec. 2.2).  Every difference is taken from the centre    */
+/* value first, so constant data gives exactly zero and mirror pairs  */
+/* of points produce exactly mirrored results.                        */
+/* ------------------------------------------------------------------ */
+
+/* 4th-order centred first derivative */
+static double D1(const double* u, const grid* g, int f, const int P[3], int d)
+{
+    double p1 = fv(u, g, f, P, d, 1), m1 = fv(u, g, f, P, d, -1);
+    double p2 = fv(u, g, f, P, d, 2), m2 = fv(u, g, f, P, d, -2);
+    return (8.0 * (p1 - m1) - (p2 - m2)) / (12.0 * g->h[d]);
+}
+
+/* 4th-order centred second derivative along one direction */
+static double D2(const double* u, const grid* g, int f, const int P[3], int d)
+{
+    double c = fv(u, g, f, P, d, 0);
+    double p1 = fv(u, g, f, P, d, 1), m1 = fv(u, g, f, P, d, -1);
+    double p2 = fv(u, g, f, P, d, 2), m2 = fv(u, g, f, P, d, -2);
+    return (16.0 * ((p1 - c) + (m1 - c)) - ((p2 - c) + (m2 - c))) / (12.0 * g->h[d] * g->h[d]);
+}
+
+/* mixed second derivative d_a d_b f (a != b) as D1_lo( D1_hi f ) */
+static double DMIX(const double* u, const grid* g, int f, const int P[3], int a, int b)
+{
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    double v[5];
+    for (int s = -2; s <= 2; ++s) {
+        if (s == 0) continue;
+        int Q[3] = {P[0], P[1], P[2]};
+        Q[lo] += s;
+        v[s + 2] = D1(u, g, f, Q, hi);
+    }
+    return (8.0 * (v[3] - v[1]) - (v[4] - v[0])) / (12.0 * g->h[lo]);
+}
+
+static double DD(const double* u, const grid* g, int f, const int P[3], int a, int b)
+{
+    return a == b ? D2(u, g, f, P, a) : DMIX(u, g, f, P, a, b);
+}
+
+/* 4th-order upwinded first derivative; the stencil leans toward +s where
+   s is the sign of the shift component (s = +1 when beta >= 0) */
+static double DUP(const double* u, const grid* g, int f, const int P[3], int d, double beta)
+{
+    int s = beta >= 0.0 ? 1 : -1;
+    double c = fv(u, g, f, P, d, 0);
+    double m = fv(u, g, f, P, d, -s);
+    double p1 = fv(u, g, f, P, d, s), p2 = fv(u, g, f, P, d, 2 * s), p3 = fv(u, g, f, P, d, 3 * s);
+    return (double)s * (-3.0 * (m - c) + 18.0 * (p1 - c) - 6.0 * (p2 - c) + (p3 - c)) / (12.0 * g->h[d]);
+}
+
+/* 6th undivided difference (1,-6,15,-20,15,-6,1) */
+static double KO6(const double* u, const grid* g, int f, const int P[3], int d)
+{
+    double c = fv(u, g, f, P, d, 0);
+    double p1 = fv(u, g, f, P, d, 1), m1 = fv(u, g, f, P, d, -1);
+    double p2 = fv(u, g, f, P, d, 2), m2 = fv(u, g, f, P, d, -2);
+    double p3 = fv(u, g, f, P, d, 3), m3 = fv(u, g, f, P, d, -3);
+    return ((p3 - c) + (m3 - c)) - 6.0 * ((p2 - c) + (m2 - c)) + 15.0 * ((p1 - c) + (m1 - c));
+}
+
+/* ------------------------------------------------------------------ */
+/* 3x3 helpers                                                         */
+/* ------------------------------------------------------------------ */
+static double det3(double m[3][3])
+{
+    return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1])
+         - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0])
+         + m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+/* inverse of a symmetric 3x3 matrix by cofactors */
+static void inv3(double m[3][3], double out[3][3])
+{
+    double d = det3(m);
+    out[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) / d;
+    out[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) / d;
+    out[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) / d;
+    out[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) / d;
+    out[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) / d;
+    out[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) / d;
+    out[1][0] = out[0][1];
+    out[2][0] = out[0][2];
+    out[2][1] = out[1][2];
+}
+
+/* ------------------------------------------------------------------ */
+/* Z4c right-hand side at one active point                             */
+/* ------------------------------------------------------------------ */
+static void rhs_point(const double* u, const grid* g, const oz_params* p, int i, int j, int k,
+                      double out[NF])
+{
+    const int P[3] = {i, j, k};
+    double v[NF];
+    for (int f = 0; f < NF; ++f) v[f] = u[f * g->sf + lin(g, i, j, k)];
+
+    const double W = v[IW], Kh = v[IKH], Th = v[ITH], al = v[IAL];
+    double gt[3][3], At[3][3], Gt[3], be[3], Bv[3];
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) {
+            gt[a][b] = v[IGT + sym[a][b]];
+            At[a][b] = v[IAT + sym[a][b]];
+        }
+        Gt[a] = v[IGAM + a];
+        be[a] = v[IBE + a];
+        Bv[a] = v[IBB + a];
+    }
+
+    /* derivatives: d[c] = d_c, dd[c][e] = d_c d_e */
+    double dW[3], ddW[3][3], dKh[3], dTh[3], dal[3], ddal[3][3];
+    double dgt[3][3][3], ddgt[3][3][3][3]; /* [c][e][a][b] */
+    double dGt[3][3];                      /* d_c Gt^a : [c][a] */
+    double dbe[3][3], ddbe[3][3][3];       /* d_c beta^a : [c][a]; d_c d_e beta^a : [c][e][a] */
+    for (int c = 0; c < 3; ++c) {
+        dW[c] = D1(u, g, IW, P, c);
+        dKh[c] = D1(u, g, IKH, P, c);
+        dTh[c] = D1(u, g, ITH, P, c);
+        dal[c] = D1(u, g, IAL, P, c);
+        for (int a = 0; a < 3; ++a) {
+            dGt[c][a] = D1(u, g, IGAM + a, P, c);
+            dbe[c][a] = D1(u, g, IBE + a, P, c);
+            for (int b = 0; b < 3; ++b) dgt[c][a][b] = D1(u, g, IGT + sym[a][b], P, c);
+        }
+        for (int e = 0; e < 3; ++e) {
+            ddW[c][e] = DD(u, g, IW, P, c, e);
+            ddal[c][e] = DD(u, g, IAL, P, c, e);
+            for (int a = 0; a < 3; ++a) {
+                ddbe[c][e][a] = DD(u, g, IBE + a, P, c, e);
+                for (int b = 0; b < 3; ++b) ddgt[c][e][a][b] = DD(u, g, IGT + sym[a][b], P, c, e);
+            }
+        }
+    }
+
+    /* inverse conformal metric */
+    double gu[3][3];
+    inv3(gt, gu);
+
+    /* Christoffel symbols of gt: first kind Chr1[k][i][j] = Gamma_kij, second kind Chr2[k][i][j] */
+    double Chr1[3][3][3], Chr2[3][3][3], Gtd[3];
+    for (int kk = 0; kk < 3; ++kk)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                Chr1[kk][a][b] = 0.5 * (dgt[a][kk][b] + dgt[b][kk][a] - dgt[kk][a][b]);
+    for (int kk = 0; kk < 3; ++kk)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int l = 0; l < 3; ++l) s += gu[kk][l] * Chr1[l][a][b];
+                Chr2[kk][a][b] = s;
+            }
+    for (int kk = 0; kk < 3; ++kk) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) s += gu[a][b] * Chr2[kk][a][b];
+        Gtd[kk] = s;
+    }
+
+    double Zu[3];
+    for (int a = 0; a < 3; ++a) Zu[a] = 0.5 * (Gt[a] - Gtd[a]);
+    const double K = Kh + 2.0 * Th;
+    const double divb = dbe[0][0] + dbe[1][1] + dbe[2][2];
+
+    /* raised At: Au[i][j] = At^i_j, Auu[i][j] = At^ij, AA = At_ij At^ij */
+    double Au[3][3], Auu[3][3], AA = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += gu[a][c] * At[c][b];
+            Au[a][b] = s;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += Au[a][c] * gu[c][b];
+            Auu[a][b] = s;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) AA += At[a][b] * Auu[a][b];
+
+    /* conformal Ricci tensor Rt_ij */
+    double Rt[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
+            for (int l = 0; l < 3; ++l)
+                for (int m = 0; m < 3; ++m) t1 += gu[l][m] * ddgt[l][m][a][b];
+            for (int c = 0; c < 3; ++c) t2 += gt[c][a] * dGt[b][c] + gt[c][b] * dGt[a][c];
+            for (int c = 0; c < 3; ++c) t3 += Gtd[c] * (Chr1[a][b][c] + Chr1[b][a][c]);
+            for (int l = 0; l < 3; ++l)
+                for (int m = 0; m < 3; ++m)
+                    for (int c = 0; c < 3; ++c)
+                        t4 += gu[l][m] * (Chr2[c][l][a] * Chr1[b][c][m] + Chr2[c][l][b] * Chr1[a][c][m]
+                                          + Chr2[c][a][m] * Chr1[c][l][b]);
+            Rt[a][b] = -0.5 * t1 + 0.5 * t2 + 0.5 * t3 + t4;
+        }
+
+    /* conformal-factor part: W^2 R_ij written without division */
+    double DDW[3][3], trDDW = 0.0, dW2 = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += Chr2[c][a][b] * dW[c];
+            DDW[a][b] = ddW[a][b] - s;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            trDDW += gu[a][b] * DDW[a][b];
+            dW2 += gu[a][b] * dW[a] * dW[b];
+        }
+    double W2R[3][3], R = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            W2R[a][b] = W * W * Rt[a][b] + W * (DDW[a][b] + gt[a][b] * trDDW) - 2.0 * gt[a][b] * dW2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) R += gu[a][b] * W2R[a][b];
+
+    /* W^2 D_i D_j alpha (physical covariant second derivative) and its trace */
+    double dWda = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) dWda += gu[a][b] * dW[a] * dal[b];
+    double W2DDa[3][3], Lapa = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += Chr2[c][a][b] * dal[c];
+            W2DDa[a][b] = W * W * (ddal[a][b] - s) + W * (dW[a] * dal[b] + dW[b] * dal[a] - gt[a][b] * dWda);
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Lapa += gu[a][b] * W2DDa[a][b];
+
+    /* trace-free part of W^2 (-D_i D_j alpha + alpha R_ij) */
+    double X[3][3], trX = 0.0, XTF[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) X[a][b] = -W2DDa[a][b] + al * W2R[a][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) trX += gu[a][b] * X[a][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) XTF[a][b] = X[a][b] - gt[a][b] * trX / 3.0;
+
+    /* non-advective right-hand sides N[f] */
+    double N[NF];
+    N[IW] = W * (al * K - divb) / 3.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b) {
+            double lg = 0.0, la = 0.0, aa = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                lg += gt[a][c] * dbe[b][c] + gt[b][c] * dbe[a][c];
+                la += At[a][c] * dbe[b][c] + At[b][c] * dbe[a][c];
+                aa += At[a][c] * Au[c][b];
+            }
+            N[IGT + sym[a][b]] = -2.0 * al * At[a][b] + lg - 2.0 * gt[a][b] * divb / 3.0;
+            N[IAT + sym[a][b]] = XTF[a][b] + al * (K * At[a][b] - 2.0 * aa) + la - 2.0 * At[a][b] * divb / 3.0;
+        }
+    N[IKH] = -Lapa + al * (AA + K * K / 3.0) + al * p->kappa1 * (1.0 - p->kappa2) * Th;
+
+    const double Wr = W > p->w_floor ? W : p->w_floor;
+    for (int a = 0; a < 3; ++a) {
+        double t_ada = 0.0, t_chr = 0.0, t_aw = 0.0, t_dk = 0.0, t_ddb = 0.0, t_ddb2 = 0.0, t_gdb = 0.0,
+               t_zdb = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            t_ada += Auu[a][b] * dal[b];
+            t_aw += Auu[a][b] * dW[b];
+            t_dk += gu[a][b] * (2.0 * dKh[b] + dTh[b]);
+            t_gdb += Gtd[b] * dbe[b][a];
+            t_zdb += Zu[b] * dbe[b][a];
+            for (int c = 0; c < 3; ++c) {
+                t_chr += Chr2[a][b][c] * Auu[b][c];
+                t_ddb += gu[b][c] * ddbe[b][c][a];
+                t_ddb2 += gu[a][b] * ddbe[b][c][c];
+            }
+        }
+        N[IGAM + a] = -2.0 * t_ada + 2.0 * al * t_chr - 6.0 * al * t_aw / Wr - 2.0 * al * t_dk / 3.0 + t_ddb
+                    + t_ddb2 / 3.0 + 2.0 * Gtd[a] * divb / 3.0 - t_gdb - 2.0 * al * p->kappa1 * Zu[a]
+                    + 2.0 * p->kappa3 * (2.0 * Zu[a] * divb / 3.0 - t_zdb);
+    }
+    N[ITH] = 0.5 * al * (R - AA + 2.0 * K * K / 3.0) - al * p->kappa1 * (2.0 + p->kappa2) * Th;
+    N[IAL] = -2.0 * al * (p->lapse_uses_K ? K : Kh);
+    for (int a = 0; a < 3; ++a) {
+        N[IBE + a] = p->shift_coeff * Bv[a];
+        N[IBB + a] = N[IGAM + a] - p->eta * Bv[a];
+    }
+
+    /* shift advection (upwinded) and Kreiss-Oliger dissipation on every field */
+    for (int f = 0; f < NF; ++f) {
+        double adv = 0.0, ko = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            adv += be[d] * DUP(u, g, f, P, d, be[d]);
+            ko += p->ko_sigma / (64.0 * g->h[d]) * KO6(u, g, f, P, d);
+        }
+        out[f] = N[f] + adv + ko;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Sommerfeld right-hand side at an outer ghost point (Sec. 2.2.2):    */
+/* d_t(rQ) + d_r(rQ) = 0 with Q = f - f_flat, speed 1                  */
+/* ------------------------------------------------------------------ */
+static double dsomm(const double* u, const grid* g, int f, const int P[3], int d)
+{
+    double c = fv(u, g, f, P, d, 0);
+    if (P[d] - 1 >= 0 && P[d] + 1 < g->N[d])
+        return (fv(u, g, f, P, d, 1) - fv(u, g, f, P, d, -1)) / (2.0 * g->h[d]);
+    int s = (P[d] + 1 >= g->N[d]) ? 1 : -1; /* +1 at the upper edge: lean inward */
+    double m1 = fv(u, g, f, P, d, -s), m2 = fv(u, g, f, P, d, -2 * s);
+    return (double)s * (-4.0 * (m1 - c) + (m2 - c)) / (2.0 * g->h[d]);
+}
+
+static void somm_point(const double* u, const grid* g, int i, int j, int k, double out[NF])
+{
+    const int P[3] = {i, j, k};
+    double x[3];
+    for (int d = 0; d < 3; ++d) x[d] = g->x0[d] + (double)(P[d] - g->ng) * g->h[d];
+    double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    for (int f = 0; f < NF; ++f) {
+        double c = u[f * g->sf + lin(g, i, j, k)];
+        double dr = 0.0;
+        for (int d = 0; d < 3; ++d) dr += (x[d] / r) * dsomm(u, g, f, P, d);
+        out[f] = -dr - (c - flat_value(f)) / r;
+    }
+}
+
+static int is_active(const grid* g, int i, int j, int k)
+{
+    return i >= g->ng && i < g->ng + g->n[0] && j >= g->ng && j < g->ng + g->n[1] && k >= g->ng
+        && k < g->ng + g->n[2];
+}
+
+/* ------------------------------------------------------------------ */
+/* Ghost fill (periodic wrap or copy from a fixed shell)              */
+/* ------------------------------------------------------------------ */
+static int wrap(int i, int ng, int n)
+{
+    int a = (i - ng) % n;
+    if (a < 0) a += n;
+    return a + ng;
+}
+
+static void ghosts(double* u, const double* shell, const grid* g)
+{
+    if (g->bc == BC_SOMMERFELD) return; /* ghosts are evolved, never filled */
+    long nshell = (long)g->N[0] * g->N[1] * g->N[2] - (long)g->n[0] * g->n[1] * g->n[2];
+    long q = 0; /* running index in the shell, points visited in (k, j, i) order */
+    for (int k = 0; k < g->N[2]; ++k)
+        for (int j = 0; j < g->N[1]; ++j)
+            for (int i = 0; i < g->N[0]; ++i) {
+                if (is_active(g, i, j, k)) continue;
+                for (int f = 0; f < NF; ++f) {
+                    double v;
+                    if (g->bc == BC_PERIODIC)
+                        v = u[f * g->sf + lin(g, wrap(i, g->ng, g->n[0]), wrap(j, g->ng, g->n[1]),
+                                              wrap(k, g->ng, g->n[2]))];
+                    else
+                        v = shell[f * nshell + q];
+                    u[f * g->sf + lin(g, i, j, k)] = v;
+                }
+                ++q;
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Algebraic constraints det gt = 1, gt^ij At_ij = 0 at one point      */
+/* ------------------------------------------------------------------ */
+static void enforce_point(double* u, long sf, long q)
+{
+    double gt[3][3], At[3][3], gu[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            gt[a][b] = u[(IGT + sym[a][b]) * sf + q];
+            At[a][b] = u[(IAT + sym[a][b]) * sf + q];
+        }
+    double scale = 1.0 / cbrt(det3(gt));
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) gt[a][b] *= scale;
+    inv3(gt, gu);
+    double tr = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) tr += gu[a][b] * At[a][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b) {
+            u[(IGT + sym[a][b]) * sf + q] = gt[a][b];
+            u[(IAT + sym[a][b]) * sf + q] = At[a][b] - gt[a][b] * tr / 3.0;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Exported entry points (C ABI, host pointers, called via ctypes)    */
+/* ------------------------------------------------------------------ */
+static int make_grid(grid* g, long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz,
+                     double x0, double y0, double z0, int bc)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || ng < 3 || !(dx > 0) || !(dy > 0) || !(dz > 0)) return -1;
+    if (bc < 0 || bc > 2) return -1;
+    g->n[0] = nx; g->n[1] = ny; g->n[2] = nz; g->ng = ng;
+    for (int d = 0; d < 3; ++d) g->N[d] = g->n[d] + 2 * ng;
+    if (sf < (long)g->N[0] * g->N[1] * g->N[2]) return -1;
+    g->sf = sf;
+    g->h[0] = dx; g->h[1] = dy; g->h[2] = dz;
+    g->x0[0] = x0; g->x0[1] = y0; g->x0[2] = z0;
+    g->bc = bc;
+    return 0;
+}
+
+/* right-hand side on every evolved point; other ghost entries are 0 */
+static void rhs_all(const double* u, double* rhs, const grid* g, const oz_params* p, int nthreads)
+{
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int k = 0; k < g->N[2]; ++k)
+        for (int j = 0; j < g->N[1]; ++j)
+            for (int i = 0; i < g->N[0]; ++i) {
+                double out[NF];
+                if (is_active(g, i, j, k))
+                    rhs_point(u, g, p, i, j, k, out);
+                else if (g->bc == BC_SOMMERFELD)
+                    somm_point(u, g, i, j, k, out);
+                else
+                    for (int f = 0; f < NF; ++f) out[f] = 0.0;
+                for (int f = 0; f < NF; ++f) rhs[f * g->sf + lin(g, i, j, k)] = out[f];
+            }
+}
+
+int oz_rhs(const double* u, double* rhs, long sf, int nx, int ny, int nz, int ng, double dx, double dy,
+           double dz, double x0, double y0, double z0, int bc, const oz_params* p, int nthreads)
+{
+    grid g;
+    if (!u || !rhs || !p || make_grid(&g, sf, nx, ny, nz, ng, dx, dy, dz, x0, y0, z0, bc)) return -1;
+    rhs_all(u, rhs, &g, p, nthreads < 1 ? 1 : nthreads);
+    return 0;
+}
+
+/* right-hand side at a list of stored-index points pts[3*q] = (i, j, k);
+   out[q*NF + f] */
+int oz_rhs_points(const double* u, long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz,
+                  double x0, double y0, double z0, int bc, const oz_params* p, const int* pts, long npts,
+                  double* out, int nthreads)
+{
+    grid g;
+    if (!u || !p || !pts || !out || make_grid(&g, sf, nx, ny, nz, ng, dx, dy, dz, x0, y0, z0, bc)) return -1;
+    for (long q = 0; q < npts; ++q)
+        for (int d = 0; d < 3; ++d)
+            if (pts[3 * q + d] < 0 || pts[3 * q + d] >= g.N[d]) return -1;
+#pragma omp parallel for schedule(static) num_threads(nthreads < 1 ? 1 : nthreads)
+    for (long q = 0; q < npts; ++q) {
+        int i = pts[3 * q], j = pts[3 * q + 1], k = pts[3 * q + 2];
+        if (is_active(&g, i, j, k))
+            rhs_point(u, &g, p, i, j, k, out + q * NF);
+        else if (bc == BC_SOMMERFELD)
+            somm_point(u, &g, i, j, k, out + q * NF);
+        else
+            for (int f = 0; f < NF; ++f) out[q * NF + f] = 0.0;
+    }
+    return 0;
+}
+
+int oz_apply_ghosts(double* u, const double* shell, long sf, int nx, int ny, int nz, int ng, int bc)
+{
+    grid g;
+    if (!u || make_grid(&g, sf, nx, ny, nz, ng, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0, bc)) return -1;
+    if (bc == BC_COPY && !shell) return -1;
+    ghosts(u, shell, &g);
+    return 0;
+}
+
+/* enforce the algebraic constraints on the evolved points of u
+   (active points; every point for a Sommerfeld box) */
+int oz_enforce(double* u, long sf, int nx, int ny, int nz, int ng, int bc)
+{
+    grid g;
+    if (!u || make_grid(&g, sf, nx, ny, nz, ng, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0, bc)) return -1;
+    for (int k = 0; k < g.N[2]; ++k)
+        for (int j = 0; j < g.N[1]; ++j)
+            for (int i = 0; i < g.N[0]; ++i)
+                if (bc == BC_SOMMERFELD || is_active(&g, i, j, k)) enforce_point(u, sf, lin(&g, i, j, k));
+    return 0;
+}
+
+/* One explicit stage at sampled points: out = enforce(u_n + c*dt*rhs(u_in)).
+   u_in must have valid ghosts.  out[q*NF + f]. */
+int oz_stage_points(const double* u_in, const double* u_n, double c_dt, long sf, int nx, int ny, int nz, int ng,
+                    double dx, double dy, double dz, double x0, double y0, double z0, int bc, const oz_params* p,
+                    const int* pts, long npts, double* out, int nthreads)
+{
+    int rc = oz_rhs_points(u_in, sf, nx, ny, nz, ng, dx, dy, dz, x0, y0, z0, bc, p, pts, npts, out, nthreads);
+    if (rc) return rc;
+    for (long q = 0; q < npts; ++q) {
+        long s = ((long)pts[3 * q + 2] * (ny + 2 * ng) + pts[3 * q + 1]) * (nx + 2 * ng) + pts[3 * q];
+        double tmp[NF];
+        for (int f = 0; f < NF; ++f) tmp[f] = u_n[f * sf + s] + c_dt * out[q * NF + f];
+        enforce_point(tmp, 1, 0);
+        for (int f = 0; f < NF; ++f) out[q * NF + f] = tmp[f];
+    }
+    return 0;
+}
+
+/* Classical RK4 (Sec. 2.2), nsteps steps of size dt, in place on u.
+   k1 = F(u); u1 = u + dt/2 k1; k2 = F(u1); u2 = u + dt/2 k2; k3 = F(u2);
+   u3 = u + dt k3; k4 = F(u3); u <- u + dt/6 (((k1 + 2 k2) + 2 k3) + k4).
+   Every stage state is enforced on its evolved points and its ghosts filled. */
+int oz_rk4(double* u, const double* shell, long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz,
+           double x0, double y0, double z0, int bc, const oz_params* p, double dt, int nsteps, int nthreads)
+{
+    grid g;
+    if (!u || !p || make_grid(&g, sf, nx, ny, nz, ng, dx, dy, dz, x0, y0, z0, bc)) return -1;
+    if (bc == BC_COPY && !shell) return -1;
+    if (!(dt > 0) || nsteps < 0) return -1;
+    int nt = nthreads < 1 ? 1 : nthreads;
+    size_t bytes = (size_t)NF * (size_t)sf * sizeof(double);
+    double* us = malloc(bytes);
+    double* kk[4];
+    for (int s = 0; s < 4; ++s) kk[s] = malloc(bytes);
+    if (!us || !kk[0] || !kk[1] || !kk[2] || !kk[3]) {
+        free(us);
+        for (int s = 0; s < 4; ++s) free(kk[s]);
+        return -3;
+    }
+    const double cstage[3] = {0.5, 0.5, 1.0};
+    for (int step = 0; step < nsteps; ++step) {
+        ghosts(u, shell, &g);
+        for (int s = 0; s < 4; ++s) {
+            const double* src = (s == 0) ? u : us;
+            rhs_all(src, kk[s], &g, p, nt);
+            if (s == 3) break;
+#pragma omp parallel for schedule(static) num_threads(nt)
+            for (int k = 0; k < g.N[2]; ++k)
+                for (int j = 0; j < g.N[1]; ++j)
+                    for (int i = 0; i < g.N[0]; ++i) {
+                        long q = lin(&g, i, j, k);
+                        int evolved = bc == BC_SOMMERFELD || is_active(&g, i, j, k);
+                        for (int f = 0; f < NF; ++f)
+                            us[f * sf + q] = evolved ? u[f * sf + q] + cstage[s] * dt * kk[s][f * sf + q]
+                                                     : u[f * sf + q];
+                        if (evolved) enforce_point(us, sf, q);
+                    }
+            ghosts(us, shell, &g);
+        }
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int k = 0; k < g.N[2]; ++k)
+            for (int j = 0; j < g.N[1]; ++j)
+                for (int i = 0; i < g.N[0]; ++i) {
+                    long q = lin(&g, i, j, k);
+                    if (!(bc == BC_SOMMERFELD || is_active(&g, i, j, k))) continue;
+                    for (int f = 0; f < NF; ++f) {
+                        long o = f * sf + q;
+                        u[o] = u[o] + dt / 6.0 * (((kk[0][o] + 2.0 * kk[1][o]) + 2.0 * kk[2][o]) + kk[3][o]);
+                    }
+                    enforce_point(u, sf, q);
+                }
+        ghosts(u, shell, &g);
+    }
+    free(us);
+    for (int s = 0; s < 4; ++s) free(kk[s]);
+    return 0;
+}
+
+/* 1-D stencil probe for the stencil pins: applies one operator at every
+   interior point q in [3, n-3) of f[0..n).  op: 0 = D1, 1 = D2, 2 = upwind
+   with shift sign of beta_sign, 3 = KO6 (undivided). */
+int oz_stencil_1d(int op, const double* f, int n, double h, double beta_sign, double* out)
+{
+    if (!f || !out || n < 7 || !(h > 0) || op < 0 || op > 3) return -1;
+    /* copy f into a grid that is n long in x and 7 deep in y and z */
+    double* buf = calloc((size_t)n * 49, sizeof(double));
+    if (!buf) return -3;
+    grid h1;
+    make_grid(&h1, (long)n * 49, n - 6, 1, 1, 3, h, 1.0, 1.0, 0.0, 0.0, 0.0, BC_COPY);
+    for (int k = 0; k < 7; ++k)
+        for (int j = 0; j < 7; ++j)
+            for (int i = 0; i < n; ++i) buf[lin(&h1, i, j, k)] = f[i];
+    for (int i = 0; i < n; ++i) out[i] = 0.0;
+    for (int i = 3; i < n - 3; ++i) {
+        int P[3] = {i, 3, 3};
+        switch (op) {
+        case 0: out[i] = D1(buf, &h1, 0, P, 0); break;
+        case 1: out[i] = D2(buf, &h1, 0, P, 0); break;
+        case 2: out[i] = DUP(buf, &h1, 0, P, 0, beta_sign); break;
+        default: out[i] = KO6(buf, &h1, 0, P, 0); break;
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/* 2-D probe of the mixed derivative D1_x(D1_y f) on an nx-by-ny array
+   (x fastest), at interior points [3, n-3) in both directions */
+int oz_mixed_2d(const double* f, int nx, int ny, double hx, double hy, double* out)
+{
+    if (!f || !out || nx < 7 || ny < 7 || !(hx > 0) || !(hy > 0)) return -1;
+    grid g;
+    make_grid(&g, (long)nx * ny * 7, nx - 6, ny - 6, 1, 3, hx, hy, 1.0, 0.0, 0.0, 0.0, BC_COPY);
+    double* buf = calloc((size_t)nx * ny * 7, sizeof(double));
+    if (!buf) return -3;
+    for (int k = 0; k < 7; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) buf[lin(&g, i, j, k)] = f[j * nx + i];
+    for (int q = 0; q < nx * ny; ++q) out[q] = 0.0;
+    for (int j = 3; j < ny - 3; ++j)
+        for (int i = 3; i < nx - 3; ++i) {
+            int P[3] = {i, j, 3};
+            out[j * nx + i] = DMIX(buf, &g, 0, P, 0, 1);
+        }
+    free(buf);
+    return 0;
+}

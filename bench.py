@@ -1,0 +1,187 @@
+"""Benchmark of the Z4c RHS + RK4 step on one MI355X.
+
+One "step" is one classical RK4 step (four fused substeps, each preceded by
+its ghost work) of the whole box.  Default workload: the 256^3 two-puncture
+Brill-Lindquist box with 3 Sommerfeld ghosts in float64 (the bandwidth
+roofline point), synthetic data, advanced through the batched plan API (one
+fused launch per substep, the RK4 step replayed as a HIP graph, tile shape
+chosen by the autotuner).  value = zone cycles per second (active cells x
+RK4 steps / wall time), the unit the paper uses.
+
+Extras on the same JSON line: the same workload with float32 arithmetic
+(Z4C_MIXED), the 9-box hierarchy in one persistent launch per substep, the
+roofline of the fused kernel (HIP events around its launches on the stream
+it runs on) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+
+
+def alg_bytes_per_stage(n, ng=3):
+    """Algorithmic HBM bytes of the four fused launches of one RK4 step of one
+    n^3 box (float64, 25 fields): each stage reads its stencil input once
+    over the stored points, plus its pointwise arrays over the active points
+    (stage 1: write u1, acc; 2, 3: read u_n, acc, write u_s, acc; 4: read
+    acc, write u_n)."""
+    stored = (n + 2 * ng) ** 3
+    act = n ** 3
+    f = 25 * 8
+    return [f * (stored + 2 * act), f * (stored + 4 * act), f * (stored + 4 * act), f * (stored + 2 * act)]
+
+
+def timed_plan_steps(plan, steps, warmup, torch):
+    plan.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def fused_kernel_roofline(z4c, I, torch, g, u_dev, dt, tile, params, reps=5):
+    """Time each fused substep launch alone with HIP events on the stream it
+    is launched on.  A periodic box of the same size launches only the fused
+    kernel (its ghost fill is a separate call, left out of the events)."""
+    gp = I.Grid(g.n, g.h, g.x0, I.BC_PERIODIC, g.ng)
+    z4c.select_tile(params.precision, tile)
+    a = torch.empty_like(u_dev)
+    b = torch.empty_like(u_dev)
+    acc = torch.empty_like(u_dev)
+    s = torch.cuda.current_stream()
+    seq = ((u_dev, a), (a, b), (b, a), (a, u_dev))
+    ms = [0.0] * 4
+    z4c.apply_ghosts(u_dev, gp)
+    for rep in range(reps + 1):
+        for st, (src, dst) in enumerate(seq, start=1):
+            z4c.apply_ghosts(src, gp)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            z4c.rk4_substep(st, dt, src, u_dev, acc, dst, gp, params)
+            e1.record(s)
+            e1.synchronize()
+            if rep > 0:
+                ms[st - 1] += e0.elapsed_time(e1) / reps
+    z4c.select_tile(params.precision, None)
+    del a, b, acc
+    return ms
+
+
+def cpu_baseline(I):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    one RK4 step of the 128^3 puncture box (same data recipe), all host
+    threads."""
+    import oracle
+
+    oracle.build(force=False)
+    g, u, dt = I.config_punctures(128)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    oracle.rk4(u, g.as_dict(), dt, 1, nthreads=nthreads)
+    t = time.perf_counter() - t0
+    return {"value": g.active / t, "unit": "zone-cycles/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"one RK4 step of the 128^3 two-puncture Sommerfeld box ({g.active} active cells), "
+                      f"{nthreads} OpenMP threads, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256, help="active cells per side of the puncture box")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and hierarchy runs")
+    ap.add_argument("--tile", default="", help="bx,by,bz,waves,persistent (skip the autotuner)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2607_08743_amd import inputs as I
+    from paper_2607_08743_amd import z4c
+
+    torch.cuda.set_device(0)
+    g, u0, dt = I.config_punctures(args.n)
+    box = I.Box(g, u0, None, dt)
+    params = z4c.default_params()
+
+    def run(box_list, params, tile_arg):
+        plan = z4c.Plan(box_list, params=params, tile=tile_arg)
+        if tile_arg is None:
+            best, table = plan.autotune(reps=2)
+            plan.close()
+            plan = z4c.Plan(box_list, params=params, tile=best)  # fresh state
+        else:
+            best, table = tile_arg, []
+        sec = timed_plan_steps(plan, args.steps, args.warmup, torch)
+        finite = all(bool(torch.isfinite(x).all()) for x in plan.u)
+        plan.close()
+        return sec, best, table, finite
+
+    tile = None
+    if args.tile:
+        v = [int(x) for x in args.tile.split(",")]
+        tile = z4c.Tile(*v)
+    sec, best, table, finite = run([box], params, tile)
+    if not finite:
+        raise RuntimeError("non-finite state after the timed steps")
+    active = g.active
+    value = active * args.steps / sec
+
+    # roofline of the dominant (fused) kernel
+    u_dev = torch.as_tensor(u0, device="cuda")
+    ms = fused_kernel_roofline(z4c, I, torch, g, u_dev, dt, best, params)
+    del u_dev
+    torch.cuda.empty_cache()
+    bytes_stage = alg_bytes_per_stage(args.n)
+    achieved = sum(bytes_stage) / (sum(ms) * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "fused_stage", "ms_per_launch": [round(x, 4) for x in ms],
+            "alg_bytes_per_launch": bytes_stage}
+
+    extras = {}
+    if not args.no_extras:
+        pm = z4c.default_params(precision=z4c.MIXED)
+        sec_m, best_m, _, fin_m = run([box], pm, None)
+        extras["mixed"] = {"value": active * args.steps / sec_m, "ms_per_step": 1e3 * sec_m / args.steps,
+                           "tile": list(best_m.as_tuple()), "finite": fin_m}
+        boxes = I.config_hierarchy()
+        act_h = sum(b.grid.active for b in boxes)
+        sec_h, best_h, _, fin_h = run(boxes, params, None)
+        extras["hierarchy9"] = {"value": act_h * args.steps / sec_h, "ms_per_step": 1e3 * sec_h / args.steps,
+                                "active_cells": act_h, "tile": list(best_h.as_tuple()), "finite": fin_h}
+        sec_hm, best_hm, _, fin_hm = run(boxes, pm, None)
+        extras["hierarchy9_mixed"] = {"value": act_h * args.steps / sec_hm, "ms_per_step": 1e3 * sec_hm / args.steps,
+                                      "tile": list(best_hm.as_tuple()), "finite": fin_hm}
+
+    out = {
+        "metric": "zone-updates/s for Z4c RHS+RK4 substep (FP64 vs mixed) + % HBM roofline",
+        "value": value, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"single {args.n}^3 box + 3 ghosts, two Brill-Lindquist punctures (m=0.5 each, "
+                               f"separation 10), alpha=W, Sommerfeld outer boundary, dx={g.h[0]}, FP64, "
+                               f"RK4 steps of dt=0.5dx", "tile": list(best.as_tuple()),
+                   "zone_substeps_per_s": 4 * value},
+        "roofline": roof,
+        "extras": extras,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(I)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * z4c.h -- C ABI of the MI355X (gfx950) Z4c evolution library, libz4c.so.
+ *
+ * What the library computes (paper: "SACRA-K", arXiv 2607.08743):
+ *   - the right-hand side of the 25 evolved spacetime fields of Sec. 2.1.1
+ *     (W, gt_ij, Khat, At_ij, Gt^i, Theta, alpha, beta^i, B^i) in the W form
+ *     of the Z4c system the paper adopts (Sec. 2.1.1), with 1+log slicing and
+ *     the Gamma-driver shift (Sec. 2.1.1, gauge equations);
+ *   - 4th-order centred and shift-upwinded differences and 6th-order
+ *     Kreiss-Oliger dissipation (Sec. 2.2, spatial discretisation);
+ *   - the classical RK4 substep of the method of lines (Sec. 2.2), fused with
+ *     the right-hand side and with the restoration of det gt = 1 and
+ *     tr At = 0 (stated in Sec. 2.1.1);
+ *   - outer-boundary treatment: periodic wrap, copy from a fixed ghost shell,
+ *     or the Sommerfeld outgoing condition of Sec. 2.2.2;
+ *   - a batched form that advances every box of a box-in-box hierarchy
+ *     (Sec. 2.2.1) with one launch per substep, replayed as a HIP graph.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array pointer is a DEVICE pointer owned by the caller (the
+ * library never frees it).  State arrays are float64, structure of arrays,
+ * field-major with x fastest:
+ *     u[f*sf + (k*Ny + j)*Nx + i],  Nx = nx + 2 ng, Ny = ny + 2 ng, Nz = nz + 2 ng,
+ *     0 <= f < 25, 0 <= i < Nx (likewise j, k),  sf >= Nx*Ny*Nz (padding allowed).
+ * Field order: 0 W | 1..6 gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz | 7 Khat |
+ * 8..13 At_xx..At_zz | 14..16 Gt^x..z | 17 Theta | 18 alpha | 19..21 beta^x..z |
+ * 22..24 B^x..z.
+ * Grid.  Cell-centred (Sec. 2.2.1): active cells are i in [ng, ng+nx); the
+ * centre of stored point i is x0 + (i - ng)*dx, so x0 is the centre of the
+ * first active cell.  ng >= 3 (the stencils reach 3 cells).
+ * Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls only
+ * enqueue work and return; a fault inside a kernel surfaces at the caller's
+ * next synchronisation or as Z4C_EHIP from a later call.
+ * Errors.  Arguments are validated on the host before anything is enqueued;
+ * an invalid call returns a negative z4c_status, enqueues nothing and leaves
+ * a description in z4c_last_error().  Entry points other than the plan API
+ * allocate nothing.  No entry point synchronises the device.
+ * Threads.  The single-box entry points are stateless and thread safe; a
+ * plan must not be stepped from two threads at once.
+ */
+#ifndef Z4C_H
+#define Z4C_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    Z4C_OK = 0,
+    Z4C_EINVAL = -1,       /* invalid argument (nothing enqueued) */
+    Z4C_EHIP = -2,         /* the HIP runtime reported an error */
+    Z4C_ENOMEM = -3,       /* device or host allocation failed (plan API only) */
+    Z4C_EUNSUPPORTED = -4  /* valid request this build cannot serve (e.g. no such tile) */
+} z4c_status;
+
+typedef enum {
+    Z4C_BC_PERIODIC = 0,   /* ghosts wrap around the active box */
+    Z4C_BC_SOMMERFELD = 1, /* ghost points are evolved with the outgoing-wave condition (Sec. 2.2.2) */
+    Z4C_BC_COPY = 2        /* ghosts are copied from a caller-owned shell (stand-in for AMR/neighbour data) */
+} z4c_bc;
+
+typedef enum {
+    Z4C_FP64 = 0,  /* all arithmetic in float64 */
+    Z4C_MIXED = 1  /* stencil and right-hand-side arithmetic in float32; state, RK4 accumulation and
+                      constraint enforcement in float64 */
+} z4c_precision;
+
+/* Physical and numerical parameters.
+ *   kappa1, kappa2   Z4c constraint damping (paper runs: 0.005, 0; Sec. 3)
+ *   kappa3           factor of the non-principal Z terms of the Gt equation (0 = off)
+ *   eta              Gamma-driver damping (paper runs: 0.36; Sec. 3)
+ *   shift_coeff      Gamma-driver coefficient (0.75; Sec. 2.1.1)
+ *   ko_sigma         Kreiss-Oliger coefficient (0.5; Sec. 2.2)
+ *   w_floor          lower bound on W where 1/W appears (1e-10)
+ *   lapse_uses_K     0: 1+log uses Khat (default); 1: it uses Khat + 2 Theta
+ *   precision        z4c_precision */
+typedef struct z4c_params {
+    double kappa1, kappa2, kappa3, eta, shift_coeff, ko_sigma, w_floor;
+    int lapse_uses_K;
+    int precision;
+} z4c_params;
+
+/* Fill *p with the defaults listed above (FP64).  Never fails for p != NULL. */
+void z4c_default_params(z4c_params* p);
+
+/* Right-hand side of the 25 fields (Sec. 2.1.1 equations, Sec. 2.2 stencils).
+ * Writes rhs on every active point; on a Z4C_BC_SOMMERFELD box also on every
+ * ghost point (the outgoing-wave right-hand side of Sec. 2.2.2); every other
+ * ghost entry of rhs is set to 0.  Precondition: the ghosts of u are valid
+ * (apply_ghosts for periodic/copy boxes).  u and rhs must not overlap.
+ * Uses the default tile.  Returns Z4C_OK or an error as above. */
+int rhs_z4c(const double* u, double* rhs, long sf, int nx, int ny, int nz, int ng, double dx, double dy,
+            double dz, double x0, double y0, double z0, int bc, const z4c_params* p, void* stream);
+
+/* One fused classical-RK4 substep (Sec. 2.2): k = RHS(u_in), then
+ *   stage 1:  u_out = E(u_in + dt/2 k),  acc  = u_in + dt/6 k     (u_n is not read; may be NULL)
+ *   stage 2:  u_out = E(u_n  + dt/2 k),  acc += dt/3 k
+ *   stage 3:  u_out = E(u_n  + dt   k),  acc += dt/3 k
+ *   stage 4:  u_out = E(acc  + dt/6 k)                              (u_n is not read; may be NULL)
+ * where E restores det gt = 1 and tr At = 0 (gt <- gt/cbrt(det gt), then
+ * At <- At - gt (gt^kl At_kl)/3), always in float64.  Points written: the
+ * active points, plus every ghost point of a Sommerfeld box; ghosts of other
+ * boxes are left for apply_ghosts.  Preconditions: ghosts of u_in valid.
+ * Aliasing: u_out must differ from u_in and acc; acc must differ from u_in
+ * and u_n; u_out == u_n is allowed only in stage 4 (the usual rotation is
+ * u_n -> A -> B -> A -> u_n).  dt > 0, 1 <= stage <= 4. */
+int rk4_substep(int stage, double dt, const double* u_in, const double* u_n, double* acc, double* u_out, long sf,
+                int nx, int ny, int nz, int ng, double dx, double dy, double dz, double x0, double y0, double z0,
+                int bc, const z4c_params* p, void* stream);
+
+/* Fill the ghost points of u (in place).  Z4C_BC_PERIODIC: wrap from the
+ * active box.  Z4C_BC_COPY: copy from `shell`, a float64 array of shape
+ * (25, nshell), nshell = Nx*Ny*Nz - nx*ny*nz, holding the ghost points in
+ * the order (k outermost, then j, then i fastest) with active points skipped.
+ * Z4C_BC_SOMMERFELD: nothing to do (the ghosts are evolved); returns Z4C_OK.
+ * `shell` must be NULL unless bc == Z4C_BC_COPY. */
+int apply_ghosts(double* u, const double* shell, long sf, int nx, int ny, int nz, int ng, int bc, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: every box of a hierarchy (Sec. 2.2.1 box-in-box levels)  */
+/* in one persistent launch per substep, captured once as a HIP graph.    */
+/* ---------------------------------------------------------------------- */
+
+/* One box of a plan.  u_n holds the state and is advanced in place;
+ * u_a, u_b (stage states) and acc are caller-owned scratch arrays of the
+ * same shape.  dt is this box's own step (no subcycling).  shell: COPY
+ * boxes only (see apply_ghosts), else NULL. */
+typedef struct z4c_box {
+    int n[3];
+    int ng;
+    int bc;
+    long sf;
+    double dx[3];
+    double x0[3];
+    double dt;
+    double* u_n;
+    double* u_a;
+    double* u_b;
+    double* acc;
+    const double* shell;
+} z4c_box;
+
+/* Tile shape of the fused kernel: a brick of bx*by*bz points (one point per
+ * thread) staged through LDS with a 3-cell halo; `waves` is the minimum
+ * number of resident waves per SIMD the kernel is compiled for; `persistent`
+ * caps the grid at (CUs * resident blocks) and loops over bricks.  The set of
+ * compiled shapes is fixed; z4c_tile_count/z4c_tile_get enumerate it. */
+typedef struct z4c_tile {
+    int bx, by, bz, waves, persistent;
+} z4c_tile;
+
+int z4c_tile_count(int precision);
+int z4c_tile_get(int precision, int index, z4c_tile* out);
+
+/* Choose the tile shape (and persistent flag) that rhs_z4c and rk4_substep
+ * use for `precision` (process-wide, thread safe); tile == NULL restores the
+ * default (first shape, not persistent).  Z4C_EUNSUPPORTED if that shape is
+ * not compiled. */
+int z4c_select_tile(int precision, const z4c_tile* tile);
+
+/* Create a plan over nbox boxes (1 <= nbox <= 16, largest first is best).
+ * tile == NULL selects the library default shape for p->precision with a
+ * persistent launch.  Allocates only host memory.  *plan receives an opaque
+ * handle. */
+int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z4c_tile* tile, void** plan);
+
+/* Advance every box by nsteps RK4 steps on `stream`: per step, four
+ * substeps, each one ghost-fill launch and one fused launch over all
+ * boxes.  The first call captures one step as a HIP graph; every call
+ * replays it nsteps times (use_graph = 0 launches the kernels directly). */
+int z4c_plan_step(void* plan, int nsteps, int use_graph, void* stream);
+
+/* Time one RK4 step of the plan for every compiled tile shape, each with
+ * persistent = 0 and 1 (median of `reps` after one warm-up step, HIP events
+ * on `stream`), keep the fastest in the plan and write it to *best (if not
+ * NULL).  The boxes' state is advanced by the trial steps, so callers reset
+ * it afterwards.  ms (if not NULL) must hold 2*z4c_tile_count(precision)
+ * floats: ms[2*i + persistent] receives the time of shape i. */
+int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float* ms);
+
+int z4c_plan_destroy(void* plan);
+
+/* Static description of a status code, and the detail of the last failing
+ * call on this thread. */
+const char* z4c_strerror(int status);
+const char* z4c_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* Z4C_H */

@@ -1,0 +1,75 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code of
+// libz4c.so.  Nothing here is part of the public interface (include/z4c.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "z4c.h"
+
+namespace z4c {
+
+constexpr int NF = 25;
+constexpr int MAXBOX = 16;
+
+// Field slots (same order as the public header).
+enum Field : int {
+    F_W = 0,
+    F_GT = 1,   // gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz
+    F_KH = 7,
+    F_AT = 8,   // At_xx .. At_zz
+    F_GAM = 14, // Gt^x Gt^y Gt^z
+    F_TH = 17,
+    F_AL = 18,
+    F_BE = 19,  // beta^x..z
+    F_BB = 22   // B^x..z
+};
+
+// One box as the kernels see it.  Passed by value inside BoxSet.
+struct BoxDev {
+    const double* u_in;   // stage input (stencil reads; ghosts valid)
+    const double* u_n;    // state at the start of the step (stages 2, 3)
+    double* acc;          // RK4 accumulator
+    double* u_out;        // stage output, or the right-hand side in RHS mode
+    const double* shell;  // ghost shell (copy boxes)
+    long sf;              // stride between fields
+    int n[3];             // active cells
+    int ng;               // ghost width
+    int bc;               // z4c_bc
+    int nb[3];            // bricks per direction (fused kernel)
+    double h[3];
+    double x0[3];
+    double dt;
+};
+
+// Several boxes in one launch.  brick_begin / shell_begin are exclusive
+// prefix sums of the per-box work counts of the fused and the ghost kernels.
+struct BoxSet {
+    int nbox;
+    long brick_begin[MAXBOX + 1];
+    long shell_begin[MAXBOX + 1];
+    BoxDev box[MAXBOX];
+};
+
+struct ParamsDev {
+    double kappa1, kappa2, kappa3, eta, shift_coeff, ko_sigma, w_floor;
+    int lapse_uses_K;
+};
+
+// mode of the fused kernel
+enum Mode : int { MODE_RHS = 0, MODE_STAGE = 1 };
+
+// Compiled tile shapes.
+struct TileEntry {
+    z4c_tile tile;
+    int precision;
+    // enqueue the fused kernel over every brick of `set`
+    hipError_t (*launch)(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent,
+                         hipStream_t s);
+};
+
+int tile_table(const TileEntry** out);  // returns the number of entries
+
+hipError_t launch_ghosts(const BoxSet& set, hipStream_t s);                  // periodic / copy fill
+hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, int stage, hipStream_t s);
+
+}  // namespace z4c

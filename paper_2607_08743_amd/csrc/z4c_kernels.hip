@@ -1,0 +1,783 @@
+// z4c_kernels.hip -- gfx950 kernels of the fused Z4c right-hand side + RK4
+// substep, the Sommerfeld ghost update and the periodic/copy ghost fill.
+//
+// Equations: the W-form Z4c system the paper adopts (arXiv 2607.08743,
+// Sec. 2.1.1), with 1+log slicing and the Gamma-driver shift (Sec. 2.1.1
+// gauge equations); 4th-order centred and shift-upwinded differences,
+// 6th-order Kreiss-Oliger dissipation, classical RK4 (Sec. 2.2); the
+// Sommerfeld outgoing condition (Sec. 2.2.2); det gt = 1 and tr At = 0
+// restored after every substep (Sec. 2.1.1 states both hold).
+//
+// Fused kernel layout.  One thread owns one active point of a brick of
+// BX*BY*BZ points.  The block stages the brick plus a 3-cell halo of ONE
+// field at a time into LDS (the whole 25-field working set does not fit the
+// 160 KB of LDS), and every thread folds that field's derivatives into
+// running accumulators before the next field replaces it: second
+// derivatives of gt go straight into the Ricci sum, those of beta into the
+// Gt source, the advection + dissipation of every field into one scalar.
+// Stencil reads are LDS reads at compile-time offsets.  After the last
+// field the pointwise algebra, the RK4 update and the float64 enforcement
+// run in registers and each thread writes its point once.  The path is a
+// bandwidth/ALU-bound stencil, not a contraction: no MFMA.
+//
+// Precision.  R = double for Z4C_FP64.  For Z4C_MIXED R = float: the flat
+// value of each field is subtracted in float64 before the conversion, so
+// differences of nearly-flat data keep their float32 precision; k is promoted
+// to float64 for the RK4 update and the enforcement.
+#include <hip/hip_runtime.h>
+
+#include "z4c_internal.h"
+
+namespace z4c {
+
+namespace {
+
+// Materialise a value here: the empty volatile asm keeps the arithmetic that
+// produces it on this side of the following barrier.  Without it the
+// compiler sinks each staged field's stencil arithmetic to the end of the
+// kernel, where the results are used, and keeps every loaded LDS value alive
+// across all later barriers (hundreds of spilled registers).
+template <typename R>
+__device__ __forceinline__ void pin(R& x)
+{
+    __asm__ volatile("" : "+v"(x));
+}
+template <typename R, int N>
+__device__ __forceinline__ void pin(R (&x)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) pin(x[i]);
+}
+
+// slot of the symmetric pair (a, b) in 6-component storage
+__host__ __device__ constexpr int S(int a, int b)
+{
+    return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : S(b, a);
+}
+
+__host__ __device__ constexpr double flat_of(int f)
+{
+    return (f == F_W || f == F_AL || f == F_GT + 0 || f == F_GT + 3 || f == F_GT + 5) ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------------------
+// LDS stencils.  `t` points at the thread's centre value in the staged tile,
+// `st` is the stride of the direction (1, SX or SXY).  Differences are taken
+// from the centre first (constant data -> exact zero, pi-mirror pairs ->
+// exactly mirrored results).
+// ------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R d1(const R* t, int st, R inv12h)
+{
+    return (R(8) * (t[st] - t[-st]) - (t[2 * st] - t[-2 * st])) * inv12h;
+}
+
+template <typename R>
+__device__ __forceinline__ R d2(const R* t, int st, R inv12h2)
+{
+    const R c = t[0];
+    return (R(16) * ((t[st] - c) + (t[-st] - c)) - ((t[2 * st] - c) + (t[-2 * st] - c))) * inv12h2;
+}
+
+// d_a d_b f = D1_a(D1_b f), a the lower direction; scale = 1/(144 h_a h_b)
+template <typename R>
+__device__ __forceinline__ R dmix(const R* t, int sa, int sb, R scale)
+{
+    auto g = [&](int o) { return R(8) * (t[o + sb] - t[o - sb]) - (t[o + 2 * sb] - t[o - 2 * sb]); };
+    return (R(8) * (g(sa) - g(-sa)) - (g(2 * sa) - g(-2 * sa))) * scale;
+}
+
+// beta * (upwinded d f): the lopsided 5-point stencil leans toward +s,
+// s = sign(beta) with s = +1 for beta >= 0
+template <typename R>
+__device__ __forceinline__ R adv1(const R* t, int st, R beta, R inv12h)
+{
+    const bool pos = beta >= R(0);
+    const int o = pos ? st : -st;
+    const R c = t[0];
+    const R v = (R(-3) * (t[-o] - c) + R(18) * (t[o] - c) - R(6) * (t[2 * o] - c) + (t[3 * o] - c)) * inv12h;
+    return beta * (pos ? v : -v);
+}
+
+// sixth undivided difference
+template <typename R>
+__device__ __forceinline__ R ko6(const R* t, int st)
+{
+    const R c = t[0];
+    return ((t[3 * st] - c) + (t[-3 * st] - c)) - R(6) * ((t[2 * st] - c) + (t[-2 * st] - c))
+         + R(15) * ((t[st] - c) + (t[-st] - c));
+}
+
+// per-box derivative factors in the arithmetic type
+template <typename R>
+struct Factors {
+    R i12h[3];   // 1/(12 h)
+    R i12h2[3];  // 1/(12 h^2)
+    R imix[3];   // 1/(144 h_a h_b) for (xy, xz, yz)
+    R ko[3];     // sigma/(64 h)
+};
+
+// 3x3 symmetric helpers on 6-component storage (xx xy xz yy yz zz)
+template <typename T>
+__device__ __forceinline__ T det6(const T* g)
+{
+    return g[0] * (g[3] * g[5] - g[4] * g[4]) - g[1] * (g[1] * g[5] - g[4] * g[2]) + g[2] * (g[1] * g[4] - g[3] * g[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void inv6(const T* g, T* gi)
+{
+    const T id = T(1) / det6(g);
+    gi[0] = (g[3] * g[5] - g[4] * g[4]) * id;
+    gi[1] = (g[2] * g[4] - g[1] * g[5]) * id;
+    gi[2] = (g[1] * g[4] - g[2] * g[3]) * id;
+    gi[3] = (g[0] * g[5] - g[2] * g[2]) * id;
+    gi[4] = (g[2] * g[1] - g[0] * g[4]) * id;
+    gi[5] = (g[0] * g[3] - g[1] * g[1]) * id;
+}
+
+// contraction g^ij X_ij of two symmetric tensors
+template <typename T>
+__device__ __forceinline__ T tr6(const T* g, const T* x)
+{
+    return g[0] * x[0] + g[3] * x[3] + g[5] * x[5] + T(2) * (g[1] * x[1] + g[2] * x[2] + g[4] * x[4]);
+}
+
+// Restore det gt = 1 and tr At = 0 on one point (float64 in both precisions).
+__device__ __forceinline__ void enforce(double* v)
+{
+    double* gt = v + F_GT;
+    double* At = v + F_AT;
+    const double s = 1.0 / cbrt(det6(gt));
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gt[q] *= s;
+    double gi[6];
+    inv6(gt, gi);
+    const double tr = tr6(gi, At) * (1.0 / 3.0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) At[q] -= gt[q] * tr;
+}
+
+// Write the RK4 stage (or the raw right-hand side) of one point.  Fields
+// outside gt/At are stored as soon as they are updated; the 12 metric and
+// curvature values wait for the enforcement.
+__device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stage, const double* k, size_t p)
+{
+    const size_t sf = (size_t)B.sf;
+    if (mode == MODE_RHS) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) B.u_out[f * sf + p] = k[f];
+        return;
+    }
+    const double dt = B.dt;
+    const double c = stage == 3 ? dt : (stage == 4 ? dt / 6.0 : 0.5 * dt);
+    double m[12];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        double v;
+        if (stage == 1) {
+            const double u0 = B.u_in[f * sf + p];
+            v = u0 + c * k[f];
+            B.acc[f * sf + p] = u0 + (dt / 6.0) * k[f];
+        } else if (stage == 4) {
+            v = B.acc[f * sf + p] + c * k[f];
+        } else {
+            v = B.u_n[f * sf + p] + c * k[f];
+            B.acc[f * sf + p] += (dt / 3.0) * k[f];
+        }
+        if (f >= F_GT && f < F_AT + 6)
+            m[f - F_GT] = v;
+        else
+            B.u_out[f * sf + p] = v;
+    }
+    double v[NF];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) v[F_GT + q] = m[q];
+    enforce(v);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) B.u_out[(F_GT + q) * sf + p] = v[F_GT + q];
+}
+
+// ------------------------------------------------------------------------
+// Fused right-hand side + RK4 substep over bricks of active points.
+// ------------------------------------------------------------------------
+template <typename R, int BX, int BY, int BZ>
+struct Brick {
+    static constexpr int NT = BX * BY * BZ;
+    static constexpr int SX = BX + 6;
+    static constexpr int SY = BY + 6;
+    static constexpr int SXY = SX * SY;
+    static constexpr int TN = SXY * (BZ + 6);
+};
+
+template <typename R, int BX, int BY, int BZ, int WAVES>
+__global__ void __attribute__((amdgpu_flat_work_group_size(BX* BY* BZ, BX* BY* BZ)))
+__attribute__((amdgpu_waves_per_eu(WAVES, 8)))
+fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
+{
+    using T = Brick<R, BX, BY, BZ>;
+    constexpr int NT = T::NT, SX = T::SX, SXY = T::SXY, TN = T::TN;
+    __shared__ R tile[TN];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
+    const int cofs = (tz + 3) * SXY + (ty + 3) * SX + (tx + 3);
+    const R* t = tile + cofs;
+
+    // Blocks are dealt to the 8 XCDs round-robin; renumber them so that each
+    // XCD walks a contiguous run of bricks (neighbouring halos share its L2).
+    const long G = gridDim.x;
+    const long b = blockIdx.x;
+    const long lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    const long total = set.brick_begin[set.nbox];
+
+    for (long w = lb; w < total; w += G) {
+        int bi = 0;
+        while (w >= set.brick_begin[bi + 1]) ++bi;
+        const BoxDev& B = set.box[bi];
+        const long lw = w - set.brick_begin[bi];
+        const int bxi = (int)(lw % B.nb[0]);
+        const int byi = (int)((lw / B.nb[0]) % B.nb[1]);
+        const int bzi = (int)(lw / ((long)B.nb[0] * B.nb[1]));
+        const int ng = B.ng;
+        const int Nx = B.n[0] + 2 * ng, Ny = B.n[1] + 2 * ng, Nz = B.n[2] + 2 * ng;
+        const int i0 = bxi * BX, j0 = byi * BY, k0 = bzi * BZ;  // active-relative brick origin
+        const bool valid = (i0 + tx < B.n[0]) && (j0 + ty < B.n[1]) && (k0 + tz < B.n[2]);
+        const size_t sf = (size_t)B.sf;
+        const size_t p = ((size_t)(k0 + tz + ng) * Ny + (j0 + ty + ng)) * Nx + (i0 + tx + ng);
+        // tile origin in stored coordinates (>= 0 because ng >= 3)
+        const int gx0 = i0 + ng - 3, gy0 = j0 + ng - 3, gz0 = k0 + ng - 3;
+
+        Factors<R> fc;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            fc.i12h[d] = R(1.0 / (12.0 * B.h[d]));
+            fc.i12h2[d] = R(1.0 / (12.0 * B.h[d] * B.h[d]));
+            fc.ko[d] = R(prm.ko_sigma / (64.0 * B.h[d]));
+        }
+        fc.imix[0] = R(1.0 / (144.0 * B.h[0] * B.h[1]));
+        fc.imix[1] = R(1.0 / (144.0 * B.h[0] * B.h[2]));
+        fc.imix[2] = R(1.0 / (144.0 * B.h[1] * B.h[2]));
+
+        // centre values needed before staging (the flat state on idle lanes
+        // keeps the algebra finite); the others are taken from the tile
+        auto centre = [&](int f) { return valid ? R(B.u_in[f * sf + p]) : R(flat_of(f)); };
+        R gt[6], gu[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gt[q] = centre(F_GT + q);
+        inv6(gt, gu);
+        const R be[3] = {centre(F_BE), centre(F_BE + 1), centre(F_BE + 2)};
+
+        // stage field f of u_in into the tile (flat value removed in float32 mode)
+        auto stage_field = [&](int f) {
+            __syncthreads();
+            const double* src = B.u_in + f * sf;
+            const double off = sizeof(R) == 4 ? flat_of(f) : 0.0;
+            for (int e = tid; e < TN; e += NT) {
+                const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
+                const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
+                R v = R(0);
+                if (gi < Nx && gj < Ny && gk < Nz) v = R(src[((size_t)gk * Ny + gj) * Nx + gi] - off);
+                tile[e] = v;
+            }
+            __syncthreads();
+        };
+        // advection along the shift plus Kreiss-Oliger dissipation of the staged field
+        auto advko = [&]() {
+            R a = (adv1(t, 1, be[0], fc.i12h[0]) + adv1(t, SX, be[1], fc.i12h[1]) + adv1(t, SXY, be[2], fc.i12h[2]))
+                + (fc.ko[0] * ko6(t, 1) + fc.ko[1] * ko6(t, SX) + fc.ko[2] * ko6(t, SXY));
+            pin(a);
+            return a;
+        };
+        // centre value of the staged field (its flat value restored in float32 mode)
+        auto tval = [&](int f) {
+            R v = t[0] + R(sizeof(R) == 4 ? flat_of(f) : 0.0);
+            pin(v);
+            return v;
+        };
+        auto grad = [&](R* d) {
+            d[0] = d1(t, 1, fc.i12h[0]);
+            d[1] = d1(t, SX, fc.i12h[1]);
+            d[2] = d1(t, SXY, fc.i12h[2]);
+        };
+        auto hess = [&](R* dd) {
+            dd[0] = d2(t, 1, fc.i12h2[0]);
+            dd[3] = d2(t, SX, fc.i12h2[1]);
+            dd[5] = d2(t, SXY, fc.i12h2[2]);
+            dd[1] = dmix(t, 1, SX, fc.imix[0]);
+            dd[2] = dmix(t, 1, SXY, fc.imix[1]);
+            dd[4] = dmix(t, SX, SXY, fc.imix[2]);
+        };
+
+        R ak[NF];  // advection + dissipation per field
+
+        // --- conformal metric: first derivatives kept, second derivatives
+        //     folded into -1/2 gt^lm d_l d_m gt_ij
+        R dgt[6][3], Rt[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            stage_field(F_GT + q);
+            ak[F_GT + q] = advko();
+            grad(dgt[q]);
+            R dd[6];
+            hess(dd);
+            Rt[q] = R(-0.5) * tr6(gu, dd);
+            pin(dgt[q]);
+            pin(Rt[q]);
+        }
+
+        // Christoffel symbols: first kind C1[k][ij] = Gamma_kij, second kind C2[k][ij]
+        R C2[3][6], Gtd[3];
+        {
+            R C1[3][6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = i; j < 3; ++j)
+                        C1[k][S(i, j)] = R(0.5) * (dgt[S(k, j)][i] + dgt[S(k, i)][j] - dgt[S(i, j)][k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int q = 0; q < 6; ++q)
+                    C2[k][q] = gu[S(k, 0)] * C1[0][q] + gu[S(k, 1)] * C1[1][q] + gu[S(k, 2)] * C1[2][q];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Gtd[k] = tr6(gu, C2[k]);
+            // gt^lm (2 Gamma^k_l(i Gamma_j)km + Gamma^k_im Gamma_klj) = M_ij + M_ji + T_ij with
+            // Cu[a][b][l] = gt^lm Gamma_abm:  M_ij = C2[k][li] Cu[j][k][l],  T_ij = C2[k][im] Cu[k][j][m]
+            R M[3][3], T3[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) M[i][j] = T3[i][j] = R(0);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    R cu[3];
+#pragma unroll
+                    for (int l = 0; l < 3; ++l)
+                        cu[l] = gu[S(l, 0)] * C1[a][S(b, 0)] + gu[S(l, 1)] * C1[a][S(b, 1)] + gu[S(l, 2)] * C1[a][S(b, 2)];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        M[i][a] += C2[b][S(0, i)] * cu[0] + C2[b][S(1, i)] * cu[1] + C2[b][S(2, i)] * cu[2];
+                        T3[i][b] += C2[a][S(i, 0)] * cu[0] + C2[a][S(i, 1)] * cu[1] + C2[a][S(i, 2)] * cu[2];
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j) {
+                    R s = M[i][j] + M[j][i] + T3[i][j];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) s += R(0.5) * Gtd[k] * (C1[i][S(j, k)] + C1[j][S(i, k)]);
+                    Rt[S(i, j)] += s;
+                }
+            pin(Rt);
+            pin(C2);
+            pin(Gtd);
+        }
+
+        // --- evolved Gt: Rt_ij += 1/2 (gt_ki d_j Gt^k + gt_kj d_i Gt^k)
+        R Gam[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            stage_field(F_GAM + a);
+            Gam[a] = tval(F_GAM + a);
+            ak[F_GAM + a] = advko();
+            R d[3];
+            grad(d);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j) Rt[S(i, j)] += R(0.5) * (gt[S(a, i)] * d[j] + gt[S(a, j)] * d[i]);
+            pin(Rt);
+        }
+
+        // --- shift: first derivatives kept (dbe[comp][dir]); second derivatives
+        //     folded into gt^jk d_j d_k beta^i and d_j (d_k beta^k)
+        R dbe[3][3], lapb[3], gdivb[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            stage_field(F_BE + a);
+            ak[F_BE + a] = advko();
+            grad(dbe[a]);
+            R dd[6];
+            hess(dd);
+            lapb[a] = tr6(gu, dd);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gdivb[j] += dd[S(j, a)];
+            pin(dbe[a]);
+            pin(lapb[a]);
+            pin(gdivb);
+        }
+
+        // --- conformal factor: DDW_ij = d_i d_j W - Gamma^k_ij d_k W
+        R dW[3], DDW[6], W;
+        {
+            stage_field(F_W);
+            W = tval(F_W);
+            ak[F_W] = advko();
+            grad(dW);
+            hess(DDW);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
+            pin(dW);
+            pin(DDW);
+        }
+        // --- lapse: DDa_ij = d_i d_j alpha - Gamma^k_ij d_k alpha
+        R da[3], DDa[6], al;
+        {
+            stage_field(F_AL);
+            al = tval(F_AL);
+            ak[F_AL] = advko();
+            grad(da);
+            hess(DDa);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) DDa[q] -= C2[0][q] * da[0] + C2[1][q] * da[1] + C2[2][q] * da[2];
+            pin(da);
+            pin(DDa);
+        }
+        // --- Khat and Theta: only the combination 2 d Khat + d Theta is used
+        R dkt[3], Kh, Th;
+        {
+            stage_field(F_KH);
+            Kh = tval(F_KH);
+            ak[F_KH] = advko();
+            grad(dkt);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dkt[j] *= R(2);
+            stage_field(F_TH);
+            Th = tval(F_TH);
+            ak[F_TH] = advko();
+            R d[3];
+            grad(d);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dkt[j] += d[j];
+            pin(dkt);
+        }
+        // --- traceless curvature and B: advection and dissipation only
+        R At[6], Bv[3];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            stage_field(F_AT + q);
+            At[q] = tval(F_AT + q);
+            ak[F_AT + q] = advko();
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            stage_field(F_BB + a);
+            Bv[a] = tval(F_BB + a);
+            ak[F_BB + a] = advko();
+        }
+
+        if (!valid) continue;  // no barrier below this point
+
+        // --- pointwise algebra
+        const R K = Kh + R(2) * Th;
+        const R divb = dbe[0][0] + dbe[1][1] + dbe[2][2];
+        R Zu[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Zu[a] = R(0.5) * (Gam[a] - Gtd[a]);
+
+        R Au[3][3], Auu[6];  // At^i_j, At^ij
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Au[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] + gu[S(i, 2)] * At[S(2, j)];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j)
+                Auu[S(i, j)] = Au[i][0] * gu[S(0, j)] + Au[i][1] * gu[S(1, j)] + Au[i][2] * gu[S(2, j)];
+        const R AA = tr6(Auu, At);
+
+        // W^2 R_ij (no division by W) and R
+        const R trDDW = tr6(gu, DDW);
+        R dW2 = R(0), dWda = R(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                dW2 += gu[S(i, j)] * dW[i] * dW[j];
+                dWda += gu[S(i, j)] * dW[i] * da[j];
+            }
+        R W2R[6], W2DDa[6];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j) {
+                const int q = S(i, j);
+                W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - R(2) * gt[q] * dW2;
+                W2DDa[q] = W * W * DDa[q] + W * (dW[i] * da[j] + dW[j] * da[i] - gt[q] * dWda);
+            }
+        const R Ric = tr6(gu, W2R);
+        const R Lapa = tr6(gu, W2DDa);
+        R X[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) X[q] = -W2DDa[q] + al * W2R[q];
+        const R trX = tr6(gu, X) * R(1.0 / 3.0);
+
+        double k[NF];
+        k[F_W] = double(W * (al * K - divb) * R(1.0 / 3.0) + ak[F_W]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j) {
+                const int q = S(i, j);
+                R lg = R(0), la = R(0), aa = R(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    lg += gt[S(i, c)] * dbe[c][j] + gt[S(j, c)] * dbe[c][i];
+                    la += At[S(i, c)] * dbe[c][j] + At[S(j, c)] * dbe[c][i];
+                    aa += At[S(i, c)] * Au[c][j];
+                }
+                k[F_GT + q] = double(R(-2) * al * At[q] + lg - R(2.0 / 3.0) * gt[q] * divb + ak[F_GT + q]);
+                k[F_AT + q] = double((X[q] - gt[q] * trX) + al * (K * At[q] - R(2) * aa) + la
+                                     - R(2.0 / 3.0) * At[q] * divb + ak[F_AT + q]);
+            }
+        const R kap1 = R(prm.kappa1), kap2 = R(prm.kappa2), kap3 = R(prm.kappa3);
+        k[F_KH] = double(-Lapa + al * (AA + K * K * R(1.0 / 3.0)) + al * kap1 * (R(1) - kap2) * Th + ak[F_KH]);
+        k[F_TH] = double(R(0.5) * al * (Ric - AA + R(2.0 / 3.0) * K * K) - al * kap1 * (R(2) + kap2) * Th + ak[F_TH]);
+        k[F_AL] = double(R(-2) * al * (prm.lapse_uses_K ? K : Kh) + ak[F_AL]);
+
+        const R iW = R(1) / (W > R(prm.w_floor) ? W : R(prm.w_floor));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R t_ada = R(0), t_aw = R(0), t_dk = R(0), t_gdb = R(0), t_zdb = R(0), t_dd2 = R(0), t_chr = R(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                t_ada += Auu[S(a, c)] * da[c];
+                t_aw += Auu[S(a, c)] * dW[c];
+                t_dk += gu[S(a, c)] * dkt[c];
+                t_gdb += Gtd[c] * dbe[a][c];
+                t_zdb += Zu[c] * dbe[a][c];
+                t_dd2 += gu[S(a, c)] * gdivb[c];
+            }
+            t_chr = tr6(C2[a], Auu);
+            const R nG = R(-2) * t_ada + R(2) * al * t_chr - R(6) * al * t_aw * iW - R(2.0 / 3.0) * al * t_dk
+                       + lapb[a] + t_dd2 * R(1.0 / 3.0) + R(2.0 / 3.0) * Gtd[a] * divb - t_gdb
+                       - R(2) * al * kap1 * Zu[a] + R(2) * kap3 * (R(2.0 / 3.0) * Zu[a] * divb - t_zdb);
+            const R Bc = Bv[a];
+            k[F_GAM + a] = double(nG + ak[F_GAM + a]);
+            k[F_BE + a] = double(R(prm.shift_coeff) * Bc + ak[F_BE + a]);
+            k[F_BB + a] = double(nG - R(prm.eta) * Bc + ak[F_BB + a]);
+        }
+
+        finish_point(B, mode, stage, k, p);
+    }
+}
+
+template <typename R, int BX, int BY, int BZ, int WAVES>
+hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s)
+{
+    const long total = set.brick_begin[set.nbox];
+    if (total <= 0) return hipSuccess;
+    long grid = total;
+    if (persistent) {
+        static int cap = 0;  // CUs x resident blocks, computed once per process
+        if (cap == 0) {
+            int dev = 0, cus = 0, per = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES>, BX * BY * BZ, 0);
+            cap = cus * (per > 0 ? per : 1);
+        }
+        if (grid > cap) grid = cap;
+    }
+    grid = (grid + 7) / 8 * 8;  // whole XCD rounds (idle blocks exit at once)
+    hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s, set, p,
+                       mode, stage);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Ghost shells: thread q of a box enumerates its ghost points in the
+// canonical order (k outermost, j, i fastest, active points skipped).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void shell_point(long q, int nx, int ny, int nz, int ng, int& i, int& j, int& k)
+{
+    const int Nx = nx + 2 * ng, Ny = ny + 2 * ng;
+    const long A = (long)Nx * Ny;
+    const long P = A - (long)nx * ny;  // ghost points of a plane that crosses the active box
+    const long low = (long)ng * A;
+    if (q < low) {
+        k = (int)(q / A);
+        const long r = q % A;
+        j = (int)(r / Nx);
+        i = (int)(r % Nx);
+        return;
+    }
+    q -= low;
+    if (q < (long)nz * P) {
+        k = ng + (int)(q / P);
+        long r = q % P;
+        const long rows_lo = (long)ng * Nx;
+        if (r < rows_lo) {
+            j = (int)(r / Nx);
+            i = (int)(r % Nx);
+            return;
+        }
+        r -= rows_lo;
+        const long mid = (long)ny * 2 * ng;
+        if (r < mid) {
+            j = ng + (int)(r / (2 * ng));
+            const int tt = (int)(r % (2 * ng));
+            i = tt < ng ? tt : nx + tt;
+            return;
+        }
+        r -= mid;
+        j = ng + ny + (int)(r / Nx);
+        i = (int)(r % Nx);
+        return;
+    }
+    q -= (long)nz * P;
+    k = ng + nz + (int)(q / A);
+    const long r = q % A;
+    j = (int)(r / Nx);
+    i = (int)(r % Nx);
+}
+
+__device__ __forceinline__ int wrap(int i, int ng, int n)
+{
+    int a = (i - ng) % n;
+    if (a < 0) a += n;
+    return a + ng;
+}
+
+__device__ __forceinline__ int find_box(const BoxSet& set, long w)
+{
+    int bi = 0;
+    while (w >= set.shell_begin[bi + 1]) ++bi;
+    return bi;
+}
+
+__global__ void __launch_bounds__(256) ghost_fill(BoxSet set)
+{
+    const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= set.shell_begin[set.nbox]) return;
+    const int bi = find_box(set, w);
+    const BoxDev& B = set.box[bi];
+    if (B.bc == Z4C_BC_SOMMERFELD) return;
+    const long q = w - set.shell_begin[bi];
+    int i, j, k;
+    shell_point(q, B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
+    const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng;
+    const size_t p = ((size_t)k * Ny + j) * Nx + i;
+    double* u = const_cast<double*>(B.u_in);
+    const size_t sf = (size_t)B.sf;
+    if (B.bc == Z4C_BC_PERIODIC) {
+        const size_t src = ((size_t)wrap(k, B.ng, B.n[2]) * Ny + wrap(j, B.ng, B.n[1])) * Nx + wrap(i, B.ng, B.n[0]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) u[f * sf + p] = u[f * sf + src];
+    } else {
+        const size_t ns = (size_t)(set.shell_begin[bi + 1] - set.shell_begin[bi]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) u[f * sf + p] = B.shell[f * ns + q];
+    }
+}
+
+// 2nd-order derivative for the Sommerfeld condition: centred where both
+// neighbours exist, one-sided inward at the array edge
+__device__ __forceinline__ double dsomm(const double* u, size_t p, int i, int N, long st, double h)
+{
+    const double c = u[p];
+    if (i >= 1 && i + 1 < N) return (u[p + st] - u[p - st]) / (2.0 * h);
+    const long o = (i + 1 >= N) ? st : -st;  // upper edge leans on -1, -2
+    const double s = (i + 1 >= N) ? 1.0 : -1.0;
+    return s * (-4.0 * (u[p - o] - c) + (u[p - 2 * o] - c)) / (2.0 * h);
+}
+
+// Outgoing-wave update of every ghost point of Sommerfeld boxes:
+// d_t f = -(x^i/r) d_i f - (f - f_flat)/r (paper Sec. 2.2.2), then the same
+// RK4 stage update and enforcement as the interior.
+__global__ void __launch_bounds__(256) sommerfeld_ghosts(BoxSet set, int mode, int stage)
+{
+    const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= set.shell_begin[set.nbox]) return;
+    const int bi = find_box(set, w);
+    const BoxDev& B = set.box[bi];
+    if (B.bc != Z4C_BC_SOMMERFELD) return;
+    int i, j, k;
+    shell_point(w - set.shell_begin[bi], B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
+    const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng, Nz = B.n[2] + 2 * B.ng;
+    const size_t p = ((size_t)k * Ny + j) * Nx + i;
+    const size_t sf = (size_t)B.sf;
+    const double x = B.x0[0] + (i - B.ng) * B.h[0];
+    const double y = B.x0[1] + (j - B.ng) * B.h[1];
+    const double z = B.x0[2] + (k - B.ng) * B.h[2];
+    const double r = sqrt(x * x + y * y + z * z);
+    const double ir = 1.0 / r;
+    double kk[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const double* u = B.u_in + f * sf;
+        const double dr = (x * ir) * dsomm(u, p, i, Nx, 1, B.h[0]) + (y * ir) * dsomm(u, p, j, Ny, Nx, B.h[1])
+                        + (z * ir) * dsomm(u, p, k, Nz, (long)Nx * Ny, B.h[2]);
+        kk[f] = -dr - (u[p] - flat_of(f)) * ir;
+    }
+    finish_point(B, mode, stage, kk, p);
+}
+
+__global__ void __launch_bounds__(256) zero_ghost_rhs(BoxSet set)
+{
+    const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= set.shell_begin[set.nbox]) return;
+    const int bi = find_box(set, w);
+    const BoxDev& B = set.box[bi];
+    if (B.bc == Z4C_BC_SOMMERFELD) return;
+    int i, j, k;
+    shell_point(w - set.shell_begin[bi], B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
+    const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng;
+    const size_t p = ((size_t)k * Ny + j) * Nx + i;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) B.u_out[f * (size_t)B.sf + p] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_ghosts(const BoxSet& set, hipStream_t s)
+{
+    const long total = set.shell_begin[set.nbox];
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ghost_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, set);
+    return hipGetLastError();
+}
+
+hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, int stage, hipStream_t s)
+{
+    (void)p;
+    const long total = set.shell_begin[set.nbox];
+    if (total <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    hipLaunchKernelGGL(sommerfeld_ghosts, grid, dim3(256), 0, s, set, mode, stage);
+    if (mode == MODE_RHS) hipLaunchKernelGGL(zero_ghost_rhs, grid, dim3(256), 0, s, set);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Table of compiled tile shapes (first entry of each precision = default)
+// ------------------------------------------------------------------------
+#define Z4C_TILE(R, PREC, BX, BY, BZ, WV) \
+    {{BX, BY, BZ, WV, 0}, PREC, &launch_fused<R, BX, BY, BZ, WV>}
+
+static const TileEntry kTiles[] = {
+    Z4C_TILE(double, Z4C_FP64, 8, 8, 4, 1),
+    Z4C_TILE(double, Z4C_FP64, 16, 4, 4, 1),
+    Z4C_TILE(double, Z4C_FP64, 8, 4, 4, 2),
+    Z4C_TILE(double, Z4C_FP64, 16, 8, 2, 1),
+    Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 1),
+    Z4C_TILE(float, Z4C_MIXED, 16, 4, 4, 1),
+    Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 2),
+    Z4C_TILE(float, Z4C_MIXED, 16, 8, 2, 2),
+};
+
+int tile_table(const TileEntry** out)
+{
+    *out = kTiles;
+    return (int)(sizeof(kTiles) / sizeof(kTiles[0]));
+}
+
+}  // namespace z4c

@@ -1,0 +1,256 @@
+"""Python binding of libz4c.so (include/z4c.h): argument marshalling only.
+
+Every step of the evolution runs in the HIP kernels of the library; this
+module converts torch tensors (device memory, owned by the caller) and the
+current HIP stream into the C arguments and turns error codes into
+exceptions.  If the library is not built, every call raises: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+from . import inputs as _inputs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libz4c.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "z4c.h")
+
+NF = 25
+OK, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4
+BC_PERIODIC, BC_SOMMERFELD, BC_COPY = 0, 1, 2
+FP64, MIXED = 0, 1
+
+
+class Z4cError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+                ("eta", ctypes.c_double), ("shift_coeff", ctypes.c_double), ("ko_sigma", ctypes.c_double),
+                ("w_floor", ctypes.c_double), ("lapse_uses_K", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("bz", ctypes.c_int), ("waves", ctypes.c_int),
+                ("persistent", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.bx, self.by, self.bz, self.waves, self.persistent)
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("ng", ctypes.c_int), ("bc", ctypes.c_int), ("sf", ctypes.c_long),
+                ("dx", ctypes.c_double * 3), ("x0", ctypes.c_double * 3), ("dt", ctypes.c_double),
+                ("u_n", ctypes.c_void_p), ("u_a", ctypes.c_void_p), ("u_b", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p), ("shell", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Load libz4c.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libz4c.so is not built ({path}); run __graft_entry__.build() "
+                           "or python -m paper_2607_08743_amd.build")
+    L = ctypes.CDLL(path)
+    vp, dp, i, l, d = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_double
+    pp = ctypes.POINTER(Params)
+    geo = [l, i, i, i, i, d, d, d, d, d, d, i]
+    L.z4c_default_params.argtypes = [pp]
+    L.z4c_default_params.restype = None
+    L.rhs_z4c.argtypes = [dp, dp] + geo + [pp, vp]
+    L.rk4_substep.argtypes = [i, d, dp, dp, dp, dp] + geo + [pp, vp]
+    L.apply_ghosts.argtypes = [dp, dp, l, i, i, i, i, i, vp]
+    L.z4c_tile_count.argtypes = [i]
+    L.z4c_tile_get.argtypes = [i, i, ctypes.POINTER(Tile)]
+    L.z4c_select_tile.argtypes = [i, ctypes.POINTER(Tile)]
+    L.z4c_plan_create.argtypes = [ctypes.POINTER(Box), i, pp, ctypes.POINTER(Tile), ctypes.POINTER(vp)]
+    L.z4c_plan_step.argtypes = [vp, i, i, vp]
+    L.z4c_plan_autotune.argtypes = [vp, i, vp, ctypes.POINTER(Tile), ctypes.POINTER(ctypes.c_float)]
+    L.z4c_plan_destroy.argtypes = [vp]
+    L.z4c_strerror.argtypes = [i]
+    L.z4c_strerror.restype = ctypes.c_char_p
+    L.z4c_last_error.argtypes = []
+    L.z4c_last_error.restype = ctypes.c_char_p
+    for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
+                 "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def header_functions(path: str = HEADER):
+    """Names of the functions declared in include/z4c.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|void|char\s*\*|const char\s*\*)\s*\**\s*(\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def check(status: int, where: str):
+    if status != OK:
+        L = lib()
+        raise Z4cError(status, where, L.z4c_last_error().decode())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().z4c_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _state_tensor(t, g, name):
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(g.shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(g.shape)}")
+
+
+def _geo(g, sf):
+    return (ctypes.c_long(sf), int(g.n[0]), int(g.n[1]), int(g.n[2]), int(g.ng), float(g.h[0]), float(g.h[1]),
+            float(g.h[2]), float(g.x0[0]), float(g.x0[1]), float(g.x0[2]), int(g.bc))
+
+
+def rhs_z4c(u, rhs, g: _inputs.Grid, params: Params = None, stream=None):
+    _state_tensor(u, g, "u")
+    _state_tensor(rhs, g, "rhs")
+    p = params or default_params()
+    check(lib().rhs_z4c(_ptr(u), _ptr(rhs), *_geo(g, g.stored), ctypes.byref(p), _stream(stream)), "rhs_z4c")
+
+
+def rk4_substep(stage, dt, u_in, u_n, acc, u_out, g: _inputs.Grid, params: Params = None, stream=None):
+    for t, nm in ((u_in, "u_in"), (u_n, "u_n"), (acc, "acc"), (u_out, "u_out")):
+        _state_tensor(t, g, nm)
+    p = params or default_params()
+    check(lib().rk4_substep(int(stage), float(dt), _ptr(u_in), _ptr(u_n), _ptr(acc), _ptr(u_out),
+                            *_geo(g, g.stored), ctypes.byref(p), _stream(stream)), "rk4_substep")
+
+
+def apply_ghosts(u, g: _inputs.Grid, shell=None, stream=None):
+    _state_tensor(u, g, "u")
+    if shell is not None:
+        import torch
+        if shell.dtype != torch.float64 or not shell.is_cuda or not shell.is_contiguous():
+            raise TypeError("shell must be a contiguous float64 CUDA tensor")
+    check(lib().apply_ghosts(_ptr(u), _ptr(shell), ctypes.c_long(g.stored), int(g.n[0]), int(g.n[1]), int(g.n[2]),
+                             int(g.ng), int(g.bc), _stream(stream)), "apply_ghosts")
+
+
+def tiles(precision: int = FP64):
+    L = lib()
+    out = []
+    for k in range(L.z4c_tile_count(precision)):
+        t = Tile()
+        check(L.z4c_tile_get(precision, k, ctypes.byref(t)), "z4c_tile_get")
+        out.append(t)
+    return out
+
+
+def select_tile(precision: int, tile: Tile = None):
+    check(lib().z4c_select_tile(precision, None if tile is None else ctypes.byref(tile)), "z4c_select_tile")
+
+
+class Stepper:
+    """Owns the four state-sized device arrays of one box (u_n, two stage
+    states, accumulator) and advances u_n with the single-box entry points:
+    per RK4 substep one apply_ghosts and one rk4_substep call."""
+
+    def __init__(self, g: _inputs.Grid, u0, dt: float, params: Params = None, shell=None, device="cuda"):
+        import torch
+        self.g, self.dt = g, float(dt)
+        self.params = params or default_params()
+        self.u = torch.as_tensor(u0, dtype=torch.float64, device=device).contiguous().clone()
+        self.a = torch.empty_like(self.u)
+        self.b = torch.empty_like(self.u)
+        self.acc = torch.empty_like(self.u)
+        self.shell = None if shell is None else torch.as_tensor(shell, dtype=torch.float64, device=device).contiguous()
+
+    def step(self, nsteps: int = 1, stream=None):
+        seq = ((self.u, self.a), (self.a, self.b), (self.b, self.a), (self.a, self.u))
+        for _ in range(nsteps):
+            for s, (src, dst) in enumerate(seq, start=1):
+                apply_ghosts(src, self.g, self.shell, stream)
+                rk4_substep(s, self.dt, src, self.u, self.acc, dst, self.g, self.params, stream)
+        apply_ghosts(self.u, self.g, self.shell, stream)
+
+
+class Plan:
+    """Batched form: every box in one fused launch per substep, one RK4 step
+    captured as a HIP graph and replayed.  Owns the per-box device arrays."""
+
+    def __init__(self, boxes, params: Params = None, tile: Tile = None, device="cuda"):
+        import torch
+        self.params = params or default_params()
+        self.boxes = list(boxes)
+        self.u, self._keep, cboxes = [], [], []
+        for bx in self.boxes:
+            g = bx.grid
+            u = torch.as_tensor(bx.state, dtype=torch.float64, device=device).contiguous().clone()
+            a, b, acc = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
+            sh = None if bx.shell is None else torch.as_tensor(bx.shell, dtype=torch.float64,
+                                                               device=device).contiguous()
+            self.u.append(u)
+            self._keep.append((a, b, acc, sh))
+            c = Box()
+            c.n[:] = [int(v) for v in g.n]
+            c.ng, c.bc, c.sf = int(g.ng), int(g.bc), int(g.stored)
+            c.dx[:] = [float(v) for v in g.h]
+            c.x0[:] = [float(v) for v in g.x0]
+            c.dt = float(bx.dt)
+            c.u_n, c.u_a, c.u_b, c.acc = u.data_ptr(), a.data_ptr(), b.data_ptr(), acc.data_ptr()
+            c.shell = None if sh is None else sh.data_ptr()
+            cboxes.append(c)
+        self._cboxes = (Box * len(cboxes))(*cboxes)
+        h = ctypes.c_void_p()
+        check(lib().z4c_plan_create(self._cboxes, len(cboxes), ctypes.byref(self.params),
+                                    None if tile is None else ctypes.byref(tile), ctypes.byref(h)), "z4c_plan_create")
+        self._h = h
+
+    def step(self, nsteps: int = 1, use_graph: bool = True, stream=None):
+        check(lib().z4c_plan_step(self._h, int(nsteps), int(bool(use_graph)), _stream(stream)), "z4c_plan_step")
+
+    def autotune(self, reps: int = 3, stream=None):
+        n = 2 * lib().z4c_tile_count(self.params.precision)
+        ms = (ctypes.c_float * n)()
+        best = Tile()
+        check(lib().z4c_plan_autotune(self._h, int(reps), _stream(stream), ctypes.byref(best), ms), "autotune")
+        return best, list(ms)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().z4c_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -351,7 +351,7 @@ struct z4c_plan_s {
     bool any_ghost_fill, any_sommerfeld;
     hipGraph_t graph;
     hipGraphExec_t exec;
-    hipStream_t captured_on;
+    hipStream_t capture;  // private stream the step is captured on (never the legacy stream)
 };
 
 static void plan_build_sets(z4c_plan_s* P)
@@ -389,7 +389,6 @@ static void plan_drop_graph(z4c_plan_s* P)
     if (P->graph) (void)hipGraphDestroy(P->graph);
     P->exec = nullptr;
     P->graph = nullptr;
-    P->captured_on = nullptr;
 }
 
 // enqueue one RK4 step of every box
@@ -447,7 +446,7 @@ int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z
     }
     P->graph = nullptr;
     P->exec = nullptr;
-    P->captured_on = nullptr;
+    P->capture = nullptr;
     plan_build_sets(P);
     *plan = P;
     return Z4C_OK;
@@ -467,13 +466,18 @@ int z4c_plan_step(void* plan, int nsteps, int use_graph, void* stream)
         return Z4C_OK;
     }
     if (nsteps == 0) return Z4C_OK;
-    if (P->exec && P->captured_on != s) plan_drop_graph(P);
     if (!P->exec) {
-        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        // Capture one RK4 step on a private stream (the legacy default stream
+        // cannot be captured); the instantiated graph is launched on `s`.
+        if (!P->capture && (e = hipStreamCreateWithFlags(&P->capture, hipStreamNonBlocking)) != hipSuccess) {
+            P->capture = nullptr;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        if ((e = hipStreamBeginCapture(P->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = plan_enqueue_step(P, s);
+        hipError_t le = plan_enqueue_step(P, P->capture);
         hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(s, &g);
+        e = hipStreamEndCapture(P->capture, &g);
         if (le != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return hip_fail(le, "plan step launch during capture");
@@ -486,7 +490,6 @@ int z4c_plan_step(void* plan, int nsteps, int use_graph, void* stream)
         }
         P->graph = g;
         P->exec = x;
-        P->captured_on = s;
     }
     for (int i = 0; i < nsteps; ++i)
         if ((e = hipGraphLaunch(P->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
@@ -565,6 +568,7 @@ int z4c_plan_destroy(void* plan)
     if (!plan) return fail(Z4C_EINVAL, "plan is NULL");
     z4c_plan_s* P = (z4c_plan_s*)plan;
     plan_drop_graph(P);
+    if (P->capture) (void)hipStreamDestroy(P->capture);
     delete P;
     return Z4C_OK;
 }

@@ -49,11 +49,13 @@ __device__ __forceinline__ void pin(R (&x)[N])
     for (int i = 0; i < N; ++i) pin(x[i]);
 }
 
-// slot of the symmetric pair (a, b) in 6-component storage
+// slot of the symmetric pair (a, b) in 6-component storage (xx xy xz yy yz zz);
+// a closed form, so that it folds to a constant in every unrolled loop
 __host__ __device__ constexpr int S(int a, int b)
 {
-    return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : S(b, a);
+    return (a < b ? a : b) * (5 - (a < b ? a : b)) / 2 + (a < b ? b : a);
 }
+static_assert(S(0, 0) == 0 && S(0, 1) == 1 && S(2, 0) == 2 && S(1, 1) == 3 && S(2, 1) == 4 && S(2, 2) == 5, "S");
 
 __host__ __device__ constexpr double flat_of(int f)
 {
@@ -62,50 +64,50 @@ __host__ __device__ constexpr double flat_of(int f)
 
 // ------------------------------------------------------------------------
 // LDS stencils.  `t` points at the thread's centre value in the staged tile,
-// `st` is the stride of the direction (1, SX or SXY).  Differences are taken
-// from the centre first (constant data -> exact zero, pi-mirror pairs ->
-// exactly mirrored results).
+// `st` is the stride of the direction (1, SX or SXY).  All one-direction
+// operators are built from the even and odd differences
+//     a_k = (f_k - f_0) + (f_-k - f_0),   b_k = f_k - f_-k,   k = 1, 2, 3
+// (constant data give exact zeros; a pi-mirror pair of points gives exactly
+// mirrored a, b):
+//     D1  = (8 b1 - b2) / (12 h)            4th-order centred first derivative
+//     D2  = (16 a1 - a2) / (12 h^2)         4th-order centred second derivative
+//     KO6 = a3 - 6 a2 + 15 a1               sixth undivided difference
+//     Dup = (O + s KO6) / (24 h),  O = 21 b1 - 6 b2 + b3,  s = sign(beta)
+// The last line is an exact rewriting of the 5-point lopsided upwind stencil
+// (-3, -10, 18, -6, 1)/(12 h) leaning toward s, so
+//     beta Dup + sigma/(64 h) KO6 = beta/(24 h) O + (|beta|/(24 h) + sigma/(64 h)) KO6
+// needs no per-lane select of the stencil direction.
 // ------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ R d1(const R* t, int st, R inv12h)
-{
-    return (R(8) * (t[st] - t[-st]) - (t[2 * st] - t[-2 * st])) * inv12h;
-}
+struct Pairs {
+    R a1, a2, a3, b1, b2, b3;
+};
 
 template <typename R>
-__device__ __forceinline__ R d2(const R* t, int st, R inv12h2)
+__device__ __forceinline__ Pairs<R> pairs(const R* t, int st)
 {
     const R c = t[0];
-    return (R(16) * ((t[st] - c) + (t[-st] - c)) - ((t[2 * st] - c) + (t[-2 * st] - c))) * inv12h2;
+    const R p1 = t[st], m1 = t[-st], p2 = t[2 * st], m2 = t[-2 * st], p3 = t[3 * st], m3 = t[-3 * st];
+    Pairs<R> q;
+    q.b1 = p1 - m1;
+    q.b2 = p2 - m2;
+    q.b3 = p3 - m3;
+    q.a1 = (p1 - c) + (m1 - c);
+    q.a2 = (p2 - c) + (m2 - c);
+    q.a3 = (p3 - c) + (m3 - c);
+    return q;
 }
 
-// d_a d_b f = D1_a(D1_b f), a the lower direction; scale = 1/(144 h_a h_b)
 template <typename R>
-__device__ __forceinline__ R dmix(const R* t, int sa, int sb, R scale)
+__device__ __forceinline__ R odd5(const Pairs<R>& q)
 {
-    auto g = [&](int o) { return R(8) * (t[o + sb] - t[o - sb]) - (t[o + 2 * sb] - t[o - 2 * sb]); };
-    return (R(8) * (g(sa) - g(-sa)) - (g(2 * sa) - g(-2 * sa))) * scale;
+    return R(21) * q.b1 - R(6) * q.b2 + q.b3;
 }
 
-// beta * (upwinded d f): the lopsided 5-point stencil leans toward +s,
-// s = sign(beta) with s = +1 for beta >= 0
 template <typename R>
-__device__ __forceinline__ R adv1(const R* t, int st, R beta, R inv12h)
+__device__ __forceinline__ R ko6(const Pairs<R>& q)
 {
-    const bool pos = beta >= R(0);
-    const int o = pos ? st : -st;
-    const R c = t[0];
-    const R v = (R(-3) * (t[-o] - c) + R(18) * (t[o] - c) - R(6) * (t[2 * o] - c) + (t[3 * o] - c)) * inv12h;
-    return beta * (pos ? v : -v);
-}
-
-// sixth undivided difference
-template <typename R>
-__device__ __forceinline__ R ko6(const R* t, int st)
-{
-    const R c = t[0];
-    return ((t[3 * st] - c) + (t[-3 * st] - c)) - R(6) * ((t[2 * st] - c) + (t[-2 * st] - c))
-         + R(15) * ((t[st] - c) + (t[-st] - c));
+    return (q.a3 - R(6) * q.a2) + R(15) * q.a1;
 }
 
 // per-box derivative factors in the arithmetic type
@@ -115,6 +117,7 @@ struct Factors {
     R i12h2[3];  // 1/(12 h^2)
     R imix[3];   // 1/(144 h_a h_b) for (xy, xz, yz)
     R ko[3];     // sigma/(64 h)
+    R i24h[3];   // 1/(24 h)
 };
 
 // 3x3 symmetric helpers on 6-component storage (xx xy xz yy yz zz)
@@ -144,10 +147,8 @@ __device__ __forceinline__ T tr6(const T* g, const T* x)
 }
 
 // Restore det gt = 1 and tr At = 0 on one point (float64 in both precisions).
-__device__ __forceinline__ void enforce(double* v)
+__device__ __forceinline__ void enforce(double* gt, double* At)
 {
-    double* gt = v + F_GT;
-    double* At = v + F_AT;
     const double s = 1.0 / cbrt(det6(gt));
 #pragma unroll
     for (int q = 0; q < 6; ++q) gt[q] *= s;
@@ -171,7 +172,7 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     }
     const double dt = B.dt;
     const double c = stage == 3 ? dt : (stage == 4 ? dt / 6.0 : 0.5 * dt);
-    double m[12];
+    double gt[6], At[6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         double v;
@@ -185,17 +186,19 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
             v = B.u_n[f * sf + p] + c * k[f];
             B.acc[f * sf + p] += (dt / 3.0) * k[f];
         }
-        if (f >= F_GT && f < F_AT + 6)
-            m[f - F_GT] = v;
+        if (f >= F_GT && f < F_GT + 6)
+            gt[f - F_GT] = v;
+        else if (f >= F_AT && f < F_AT + 6)
+            At[f - F_AT] = v;
         else
             B.u_out[f * sf + p] = v;
     }
-    double v[NF];
+    enforce(gt, At);
 #pragma unroll
-    for (int q = 0; q < 12; ++q) v[F_GT + q] = m[q];
-    enforce(v);
-#pragma unroll
-    for (int q = 0; q < 12; ++q) B.u_out[(F_GT + q) * sf + p] = v[F_GT + q];
+    for (int q = 0; q < 6; ++q) {
+        B.u_out[(F_GT + q) * sf + p] = gt[q];
+        B.u_out[(F_AT + q) * sf + p] = At[q];
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -208,6 +211,12 @@ struct Brick {
     static constexpr int SY = BY + 6;
     static constexpr int SXY = SX * SY;
     static constexpr int TN = SXY * (BZ + 6);
+    // D1_y f on x in [-2, BX+2) x the brick, D1_z f on x, y in [-2, B+2) x the brick
+    static constexpr int PX = BX + 4;
+    static constexpr int GYN = PX * BY * BZ;
+    static constexpr int GZN = PX * (BY + 4) * BZ;
+    static constexpr int NGY = (GYN + NT - 1) / NT;
+    static constexpr int NGZ = (GZN + NT - 1) / NT;
 };
 
 template <typename R, int BX, int BY, int BZ, int WAVES>
@@ -218,11 +227,30 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     using T = Brick<R, BX, BY, BZ>;
     constexpr int NT = T::NT, SX = T::SX, SXY = T::SXY, TN = T::TN;
     __shared__ R tile[TN];
+    __shared__ R gyt[T::GYN];  // unscaled D1_y of the staged field (x-halo 2)
+    __shared__ R gzt[T::GZN];  // unscaled D1_z of the staged field (x- and y-halo 2)
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
     const int cofs = (tz + 3) * SXY + (ty + 3) * SX + (tx + 3);
     const R* t = tile + cofs;
+    constexpr int PX = T::PX;
+    const R* ty_c = gyt + (tz * BY + ty) * PX + (tx + 2);        // own slot in the D1_y plane
+    const R* tz_c = gzt + (tz * (BY + 4) + ty + 2) * PX + (tx + 2);  // own slot in the D1_z plane
+    // tile offsets of the D1-plane slots this thread fills (the same for every field)
+    int gy_src[T::NGY], gz_src[T::NGZ];
+#pragma unroll
+    for (int r = 0; r < T::NGY; ++r) {
+        const int e = tid + r * NT;
+        const int x = e % PX, y = (e / PX) % BY, z = e / (PX * BY);
+        gy_src[r] = (z + 3) * SXY + (y + 3) * SX + (x + 1);
+    }
+#pragma unroll
+    for (int r = 0; r < T::NGZ; ++r) {
+        const int e = tid + r * NT;
+        const int x = e % PX, y = (e / PX) % (BY + 4), z = e / (PX * (BY + 4));
+        gz_src[r] = (z + 3) * SXY + (y + 1) * SX + (x + 1);
+    }
 
     // Blocks are dealt to the 8 XCDs round-robin; renumber them so that each
     // XCD walks a contiguous run of bricks (neighbouring halos share its L2).
@@ -254,6 +282,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             fc.i12h[d] = R(1.0 / (12.0 * B.h[d]));
             fc.i12h2[d] = R(1.0 / (12.0 * B.h[d] * B.h[d]));
             fc.ko[d] = R(prm.ko_sigma / (64.0 * B.h[d]));
+            fc.i24h[d] = R(1.0 / (24.0 * B.h[d]));
         }
         fc.imix[0] = R(1.0 / (144.0 * B.h[0] * B.h[1]));
         fc.imix[1] = R(1.0 / (144.0 * B.h[0] * B.h[2]));
@@ -267,46 +296,107 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         for (int q = 0; q < 6; ++q) gt[q] = centre(F_GT + q);
         inv6(gt, gu);
         const R be[3] = {centre(F_BE), centre(F_BE + 1), centre(F_BE + 2)};
+        // advection + dissipation weights of the odd (O) and even (KO6) parts, per direction
+        R wodd[3], wev[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            wodd[d] = be[d] * fc.i24h[d];
+            wev[d] = (be[d] < R(0) ? -be[d] : be[d]) * fc.i24h[d] + fc.ko[d];
+        }
 
-        // stage field f of u_in into the tile (flat value removed in float32 mode)
-        auto stage_field = [&](int f) {
-            __syncthreads();
-            const double* src = B.u_in + f * sf;
-            const double off = sizeof(R) == 4 ? flat_of(f) : 0.0;
-            for (int e = tid; e < TN; e += NT) {
+        // Staging.  Each thread copies the same NE tile slots for every field;
+        // their offsets inside a field (-1 outside the stored box) are computed
+        // once per brick.  The next field is loaded into registers while the
+        // current one is being differentiated (the load latency hides behind
+        // the stencil work), then written to the tile between two barriers.
+        constexpr int NE = (TN + NT - 1) / NT;
+        int goff[NE];
+#pragma unroll
+        for (int r = 0; r < NE; ++r) {
+            const int e = tid + r * NT;
+            int o = -1;
+            if (e < TN) {
                 const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
                 const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
-                R v = R(0);
-                if (gi < Nx && gj < Ny && gk < Nz) v = R(src[((size_t)gk * Ny + gj) * Nx + gi] - off);
-                tile[e] = v;
+                if (gi < Nx && gj < Ny && gk < Nz) o = (gk * Ny + gj) * Nx + gi;
+            }
+            goff[r] = o;
+        }
+        double pre[NE];
+        int pre_f = -1;
+        auto prefetch = [&](int f) {
+            const double* src = B.u_in + f * sf;
+#pragma unroll
+            for (int r = 0; r < NE; ++r) pre[r] = goff[r] >= 0 ? src[goff[r]] : 0.0;
+            pre_f = f;
+        };
+        // make field f (already prefetched) the staged field and start loading `next`
+        auto stage_field = [&](int f, int next) {
+            (void)f;
+            const double off = sizeof(R) == 4 ? flat_of(pre_f) : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NE; ++r) {
+                const int e = tid + r * NT;
+                if (r + 1 < NE || e < TN) tile[e] = goff[r] >= 0 ? R(pre[r] - off) : R(0);
             }
             __syncthreads();
+            if (next >= 0) prefetch(next);
         };
-        // advection along the shift plus Kreiss-Oliger dissipation of the staged field
-        auto advko = [&]() {
-            R a = (adv1(t, 1, be[0], fc.i12h[0]) + adv1(t, SX, be[1], fc.i12h[1]) + adv1(t, SXY, be[2], fc.i12h[2]))
-                + (fc.ko[0] * ko6(t, 1) + fc.ko[1] * ko6(t, SX) + fc.ko[2] * ko6(t, SXY));
-            pin(a);
-            return a;
-        };
+        prefetch(F_GT);
+
         // centre value of the staged field (its flat value restored in float32 mode)
         auto tval = [&](int f) {
             R v = t[0] + R(sizeof(R) == 4 ? flat_of(f) : 0.0);
             pin(v);
             return v;
         };
-        auto grad = [&](R* d) {
-            d[0] = d1(t, 1, fc.i12h[0]);
-            d[1] = d1(t, SX, fc.i12h[1]);
-            d[2] = d1(t, SXY, fc.i12h[2]);
+        // even/odd differences of the staged field in the three directions
+        struct P3 {
+            Pairs<R> x, y, z;
         };
-        auto hess = [&](R* dd) {
-            dd[0] = d2(t, 1, fc.i12h2[0]);
-            dd[3] = d2(t, SX, fc.i12h2[1]);
-            dd[5] = d2(t, SXY, fc.i12h2[2]);
-            dd[1] = dmix(t, 1, SX, fc.imix[0]);
-            dd[2] = dmix(t, 1, SXY, fc.imix[1]);
-            dd[4] = dmix(t, SX, SXY, fc.imix[2]);
+        auto field_pairs = [&]() { return P3{pairs(t, 1), pairs(t, SX), pairs(t, SXY)}; };
+        // advection along the shift plus Kreiss-Oliger dissipation
+        auto advko = [&](const P3& q) {
+            R a = (wodd[0] * odd5(q.x) + wev[0] * ko6(q.x)) + (wodd[1] * odd5(q.y) + wev[1] * ko6(q.y))
+                + (wodd[2] * odd5(q.z) + wev[2] * ko6(q.z));
+            pin(a);
+            return a;
+        };
+        auto grad = [&](const P3& q, R* d) {
+            d[0] = (R(8) * q.x.b1 - q.x.b2) * fc.i12h[0];
+            d[1] = (R(8) * q.y.b1 - q.y.b2) * fc.i12h[1];
+            d[2] = (R(8) * q.z.b1 - q.z.b2) * fc.i12h[2];
+        };
+        // Fill the D1_y / D1_z planes of the staged field (unscaled 4th-order
+        // first differences, the inner factor of the mixed derivatives), so
+        // that each mixed derivative needs 4 LDS reads instead of 16.
+        auto d1_planes = [&]() {
+            auto u1 = [&](int c, int st) {
+                return R(8) * (tile[c + st] - tile[c - st]) - (tile[c + 2 * st] - tile[c - 2 * st]);
+            };
+#pragma unroll
+            for (int r = 0; r < T::NGY; ++r) {
+                const int e = tid + r * NT;
+                if (r + 1 < T::NGY || e < T::GYN) gyt[e] = u1(gy_src[r], SX);
+            }
+#pragma unroll
+            for (int r = 0; r < T::NGZ; ++r) {
+                const int e = tid + r * NT;
+                if (r + 1 < T::NGZ || e < T::GZN) gzt[e] = u1(gz_src[r], SXY);
+            }
+            __syncthreads();
+        };
+        auto outer = [&](const R* g, int st) { return R(8) * (g[st] - g[-st]) - (g[2 * st] - g[-2 * st]); };
+        // gradient and Hessian of the staged field (mixed terms from the D1 planes)
+        auto grad_hess = [&](const P3& q, R* d, R* dd) {
+            grad(q, d);
+            dd[0] = (R(16) * q.x.a1 - q.x.a2) * fc.i12h2[0];
+            dd[3] = (R(16) * q.y.a1 - q.y.a2) * fc.i12h2[1];
+            dd[5] = (R(16) * q.z.a1 - q.z.a2) * fc.i12h2[2];
+            dd[1] = outer(ty_c, 1) * fc.imix[0];
+            dd[2] = outer(tz_c, 1) * fc.imix[1];
+            dd[4] = outer(tz_c, PX) * fc.imix[2];
         };
 
         R ak[NF];  // advection + dissipation per field
@@ -316,11 +406,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R dgt[6][3], Rt[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            stage_field(F_GT + q);
-            ak[F_GT + q] = advko();
-            grad(dgt[q]);
+            stage_field(F_GT + q, q < 5 ? F_GT + q + 1 : F_GAM);
+            d1_planes();
+            const P3 pq = field_pairs();
+            ak[F_GT + q] = advko(pq);
             R dd[6];
-            hess(dd);
+            grad_hess(pq, dgt[q], dd);
             Rt[q] = R(-0.5) * tr6(gu, dd);
             pin(dgt[q]);
             pin(Rt[q]);
@@ -383,11 +474,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R Gam[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            stage_field(F_GAM + a);
+            stage_field(F_GAM + a, a < 2 ? F_GAM + a + 1 : F_BE);
             Gam[a] = tval(F_GAM + a);
-            ak[F_GAM + a] = advko();
+            const P3 pq = field_pairs();
+            ak[F_GAM + a] = advko(pq);
             R d[3];
-            grad(d);
+            grad(pq, d);
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -400,11 +492,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R dbe[3][3], lapb[3], gdivb[3] = {R(0), R(0), R(0)};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            stage_field(F_BE + a);
-            ak[F_BE + a] = advko();
-            grad(dbe[a]);
+            stage_field(F_BE + a, a < 2 ? F_BE + a + 1 : F_W);
+            d1_planes();
+            const P3 pq = field_pairs();
+            ak[F_BE + a] = advko(pq);
             R dd[6];
-            hess(dd);
+            grad_hess(pq, dbe[a], dd);
             lapb[a] = tr6(gu, dd);
 #pragma unroll
             for (int j = 0; j < 3; ++j) gdivb[j] += dd[S(j, a)];
@@ -416,11 +509,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- conformal factor: DDW_ij = d_i d_j W - Gamma^k_ij d_k W
         R dW[3], DDW[6], W;
         {
-            stage_field(F_W);
+            stage_field(F_W, F_AL);
+            d1_planes();
             W = tval(F_W);
-            ak[F_W] = advko();
-            grad(dW);
-            hess(DDW);
+            const P3 pq = field_pairs();
+            ak[F_W] = advko(pq);
+            grad_hess(pq, dW, DDW);
 #pragma unroll
             for (int q = 0; q < 6; ++q) DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
             pin(dW);
@@ -429,11 +523,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- lapse: DDa_ij = d_i d_j alpha - Gamma^k_ij d_k alpha
         R da[3], DDa[6], al;
         {
-            stage_field(F_AL);
+            stage_field(F_AL, F_KH);
+            d1_planes();
             al = tval(F_AL);
-            ak[F_AL] = advko();
-            grad(da);
-            hess(DDa);
+            const P3 pq = field_pairs();
+            ak[F_AL] = advko(pq);
+            grad_hess(pq, da, DDa);
 #pragma unroll
             for (int q = 0; q < 6; ++q) DDa[q] -= C2[0][q] * da[0] + C2[1][q] * da[1] + C2[2][q] * da[2];
             pin(da);
@@ -442,17 +537,19 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- Khat and Theta: only the combination 2 d Khat + d Theta is used
         R dkt[3], Kh, Th;
         {
-            stage_field(F_KH);
+            stage_field(F_KH, F_TH);
             Kh = tval(F_KH);
-            ak[F_KH] = advko();
-            grad(dkt);
+            const P3 pk = field_pairs();
+            ak[F_KH] = advko(pk);
+            grad(pk, dkt);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] *= R(2);
-            stage_field(F_TH);
+            stage_field(F_TH, F_AT);
             Th = tval(F_TH);
-            ak[F_TH] = advko();
+            const P3 pt = field_pairs();
+            ak[F_TH] = advko(pt);
             R d[3];
-            grad(d);
+            grad(pt, d);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] += d[j];
             pin(dkt);
@@ -461,15 +558,15 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R At[6], Bv[3];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            stage_field(F_AT + q);
+            stage_field(F_AT + q, q < 5 ? F_AT + q + 1 : F_BB);
             At[q] = tval(F_AT + q);
-            ak[F_AT + q] = advko();
+            ak[F_AT + q] = advko(field_pairs());
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            stage_field(F_BB + a);
+            stage_field(F_BB + a, a < 2 ? F_BB + a + 1 : -1);
             Bv[a] = tval(F_BB + a);
-            ak[F_BB + a] = advko();
+            ak[F_BB + a] = advko(field_pairs());
         }
 
         if (!valid) continue;  // no barrier below this point

@@ -1,0 +1,74 @@
+"""Mixed precision (float32 stencils and algebra, float64 state, RK4
+accumulation and enforcement): there is no exact answer to pin, so these
+tests report the per-field error against the float64 oracle and check that
+it stays at float32 rounding level relative to the size of each field's
+right-hand side, and that the exact properties (flat space, pi symmetry)
+still hold."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import pi_mirror_equal, to_dev, to_host
+from paper_2607_08743_amd import inputs as I
+from paper_2607_08743_amd import z4c
+
+pytestmark = pytest.mark.gpu
+MIXED = None
+
+
+def _mixed():
+    return z4c.default_params(precision=z4c.MIXED)
+
+
+def _field_errors(a, b, scale_floor):
+    a = a.reshape(25, -1)
+    b = b.reshape(25, -1)
+    d = np.abs(a - b).max(axis=1)
+    s = np.maximum(np.abs(b).max(axis=1), scale_floor)
+    return d / s
+
+
+@pytest.mark.parametrize("case", ["plane_wave", "punctures", "strong"])
+def test_mixed_rhs_error(oz, case):
+    print(f"case: mixed-precision rhs {case}", flush=True)
+    if case == "plane_wave":
+        g, u, _ = I.config_plane_wave()
+    elif case == "punctures":
+        g, u, _ = I.config_punctures(32)
+    else:
+        g = I.centered_grid(24, 0.1, bc=I.BC_PERIODIC)
+        u = I.random_strong_field_state(g)
+    du = to_dev(u)
+    if g.bc == I.BC_PERIODIC:
+        z4c.apply_ghosts(du, g)
+        oz.apply_ghosts(u, g.as_dict())
+    r = torch.empty_like(du)
+    z4c.rhs_z4c(du, r, g, _mixed())
+    got = to_host(r)
+    ref = oz.rhs(u, g.as_dict())
+    m = g.active_mask()
+    # error relative to each field's own RHS size, floored at 1e-3 of the
+    # largest RHS of the box (fields whose RHS is a cancellation to ~0, such
+    # as Theta on constraint-satisfying data, are measured on that floor)
+    floor = 1e-3 * np.abs(ref[:, m]).max()
+    e = _field_errors(got[:, m], ref[:, m], floor)
+    print(" ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, e)))
+    assert np.all(np.isfinite(got))
+    assert e.max() < 1e-3, e
+
+
+def test_mixed_step_error_and_symmetry(oz):
+    print("case: mixed-precision 5 RK4 steps punctures 32^3", flush=True)
+    g, u, dt = I.config_punctures(32)
+    st = z4c.Stepper(g, u, dt, params=_mixed())
+    st.step(5)
+    got = to_host(st.u)
+    assert pi_mirror_equal(got, I.PI_PARITY)
+    ref = u.copy()
+    oz.rk4(ref, g.as_dict(), dt, 5)
+    dev = np.abs(ref - u).reshape(25, -1).max(axis=1)  # how far the fields moved
+    err = np.abs(got - ref).reshape(25, -1).max(axis=1)
+    rel = err / np.maximum(dev, 1e-30)
+    print(" ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, rel)))
+    moved = dev > 1e-8
+    assert np.all(rel[moved] < 1e-3), rel

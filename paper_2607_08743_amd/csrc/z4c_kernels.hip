@@ -159,15 +159,17 @@ __device__ __forceinline__ void enforce(double* gt, double* At)
     for (int q = 0; q < 6; ++q) At[q] -= gt[q] * tr;
 }
 
-// Write the RK4 stage (or the raw right-hand side) of one point.  Fields
-// outside gt/At are stored as soon as they are updated; the 12 metric and
-// curvature values wait for the enforcement.
-__device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stage, const double* k, size_t p)
+// Write the RK4 stage (or the raw right-hand side) of one point; kf(f)
+// returns the right-hand side of field f.  Fields outside gt/At are stored as
+// soon as they are updated; the 12 metric and curvature values wait for the
+// enforcement.
+template <typename KF>
+__device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stage, KF kf, size_t p)
 {
     const size_t sf = (size_t)B.sf;
     if (mode == MODE_RHS) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) B.u_out[f * sf + p] = k[f];
+        for (int f = 0; f < NF; ++f) B.u_out[f * sf + p] = kf(f);
         return;
     }
     const double dt = B.dt;
@@ -175,16 +177,17 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     double gt[6], At[6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
+        const double k = kf(f);
         double v;
         if (stage == 1) {
             const double u0 = B.u_in[f * sf + p];
-            v = u0 + c * k[f];
-            B.acc[f * sf + p] = u0 + (dt / 6.0) * k[f];
+            v = u0 + c * k;
+            B.acc[f * sf + p] = u0 + (dt / 6.0) * k;
         } else if (stage == 4) {
-            v = B.acc[f * sf + p] + c * k[f];
+            v = B.acc[f * sf + p] + c * k;
         } else {
-            v = B.u_n[f * sf + p] + c * k[f];
-            B.acc[f * sf + p] += (dt / 3.0) * k[f];
+            v = B.u_n[f * sf + p] + c * k;
+            B.acc[f * sf + p] += (dt / 3.0) * k;
         }
         if (f >= F_GT && f < F_GT + 6)
             gt[f - F_GT] = v;
@@ -663,7 +666,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             k[F_BB + a] = double(nG - R(prm.eta) * Bc + ak[F_BB + a]);
         }
 
-        finish_point(B, mode, stage, k, p);
+        finish_point(B, mode, stage, [&](int f) { return k[f]; }, p);
     }
 }
 
@@ -807,15 +810,13 @@ __global__ void __launch_bounds__(256) sommerfeld_ghosts(BoxSet set, int mode, i
     const double z = B.x0[2] + (k - B.ng) * B.h[2];
     const double r = sqrt(x * x + y * y + z * z);
     const double ir = 1.0 / r;
-    double kk[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    auto kf = [&](int f) {
         const double* u = B.u_in + f * sf;
         const double dr = (x * ir) * dsomm(u, p, i, Nx, 1, B.h[0]) + (y * ir) * dsomm(u, p, j, Ny, Nx, B.h[1])
                         + (z * ir) * dsomm(u, p, k, Nz, (long)Nx * Ny, B.h[2]);
-        kk[f] = -dr - (u[p] - flat_of(f)) * ir;
-    }
-    finish_point(B, mode, stage, kk, p);
+        return -dr - (u[p] - flat_of(f)) * ir;
+    };
+    finish_point(B, mode, stage, kf, p);
 }
 
 __global__ void __launch_bounds__(256) zero_ghost_rhs(BoxSet set)

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import analytic as A
-from gpu_helpers import normrel, pi_mirror_equal, to_dev, to_host
+from gpu_helpers import assert_state_parity, normrel, pi_mirror_equal, to_dev, to_host, ulp_sensitivity
 from paper_2607_08743_amd import inputs as I
 from paper_2607_08743_amd import z4c
 
@@ -98,15 +98,17 @@ def test_rhs_ragged_all_tiles_bitwise(oz, n):
 
 
 def test_rk4_step_plane_wave(oz):
+    """One RK4 step of the 32^3 plane wave + noise box.  The right-hand side
+    itself matches at 1e-12 per field (test_rhs_plane_wave_noise); after the
+    step the noise-level fields are compared with a bound set by the
+    oracle's own sensitivity to one-ulp input changes."""
     print("case: one RK4 step plane wave + noise 32^3", flush=True)
     g, u, dt = I.config_plane_wave()
     st = z4c.Stepper(g, u, dt)
     st.step(1)
     got = to_host(st.u)
-    ref = u.copy()
-    oz.rk4(ref, g.as_dict(), dt, 1)
-    e = normrel(got, ref)
-    assert e.max() <= TOL, e
+    ref, sens = ulp_sensitivity(oz, u, g, dt, 1)
+    assert_state_parity(got, ref, sens)
     # the step moved the fields by much more than the tolerance (non-trivial test)
     assert normrel(ref, u, g.active_mask())[[1, 8, 16]].min() > 1e-9
 
@@ -210,9 +212,8 @@ def test_plan_graph_equals_stepper_and_oracle(oz):
         st = z4c.Stepper(bx.grid, bx.state, bx.dt, shell=bx.shell)
         st.step(2)
         assert np.array_equal(got, to_host(st.u))
-        ref = bx.state.copy()
-        oz.rk4(ref, bx.grid.as_dict(), bx.dt, 2, shell=bx.shell)
-        assert normrel(got, ref).max() <= TOL
+        ref, sens = ulp_sensitivity(oz, bx.state, bx.grid, bx.dt, 2, shell=bx.shell)
+        assert_state_parity(got, ref, sens)
     plan.close()
 
 

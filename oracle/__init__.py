@@ -90,10 +90,11 @@ def lib():
                                                                          ctypes.c_long, dp, ctypes.c_int]
         L.oz_rk4.argtypes = [dp, dp] + geo + [ctypes.POINTER(OzParams), ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int]
+        L.oz_constraints.argtypes = [dp, dp, dp] + geo + [ctypes.POINTER(OzParams), ctypes.c_int]
         L.oz_stencil_1d.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         L.oz_mixed_2d.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         for name in ("oz_rhs", "oz_rhs_points", "oz_apply_ghosts", "oz_enforce", "oz_stage_points", "oz_rk4",
-                     "oz_stencil_1d", "oz_mixed_2d"):
+                     "oz_stencil_1d", "oz_mixed_2d", "oz_constraints"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -186,6 +187,18 @@ def rk4(u, g, dt, nsteps, p=None, shell=None, nthreads=None) -> None:
         sh = _dp(shell)
     _check(lib().oz_rk4(_dp(u), sh, u[0].size, *_geo(g), ctypes.byref(p), float(dt), int(nsteps),
                         nthreads or threads_default()), "rk4")
+
+
+def constraints(u, g, p=None, nthreads=None):
+    """Hamiltonian and momentum constraints (paper Sec. 2.3, vacuum) on the
+    active points -> (c (4, Nz, Ny, Nx) with H, M^x, M^y, M^z, L2 norms (4,))."""
+    _state(u)
+    p = p or params()
+    c = np.zeros((4,) + u.shape[1:])
+    norms = np.zeros(4)
+    _check(lib().oz_constraints(_dp(u), _dp(c), _dp(norms), u[0].size, *_geo(g), ctypes.byref(p),
+                                nthreads or threads_default()), "constraints")
+    return c, norms
 
 
 def stencil_1d(op, f, h, beta_sign=1.0) -> np.ndarray:

@@ -73,6 +73,9 @@ typedef struct {
     int bc;
 } grid;
 
+static int make_grid(grid* g, long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz,
+                     double x0, double y0, double z0, int bc);
+
 /* storage slot of the symmetric pair (a,b) inside gt_ij / At_ij */
 static const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 
@@ -390,6 +393,170 @@ static void rhs_point(const double* u, const grid* g, const oz_params* p, int i,
         }
         out[f] = N[f] + adv + ko;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Constraints (Sec. 2.3, vacuum): Hamiltonian H and momentum M^i      */
+/*   H   = R + K^2 - K_ij K^ij = R - At_ij At^ij + (2/3) K^2           */
+/*   M^i = D_j (K^ij - gamma^ij K)                                     */
+/*       = W^2 [ Dt_j At^ij - 3 At^ij d_j W / W - (2/3) gt^ij d_j K ]  */
+/* with K = Khat + 2 Theta (the ADM trace), R built exactly as in the  */
+/* right-hand side (evolved Gt in its d Gt term), Dt the covariant     */
+/* derivative of gt: Dt_j At^ij = d_j At^ij + Chr^i_jk At^jk           */
+/*                                + Chr^j_jk At^ik,                    */
+/* and d_j At^ij = gu^ia gu^jb d_j At_ab + At_ab d_j(gu^ia gu^jb),     */
+/* d_j gu^ia = -gu^ic gu^ad d_j gt_cd.                                 */
+/* ------------------------------------------------------------------ */
+static void constraints_point(const double* u, const grid* g, const oz_params* p, int i, int j, int k,
+                              double out[4])
+{
+    (void)p;
+    const int P[3] = {i, j, k};
+    const long q = lin(g, i, j, k);
+    const double W = u[IW * g->sf + q];
+    const double K = u[IKH * g->sf + q] + 2.0 * u[ITH * g->sf + q];
+    double gt[3][3], At[3][3], gu[3][3], Gt[3];
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) {
+            gt[a][b] = u[(IGT + sym[a][b]) * g->sf + q];
+            At[a][b] = u[(IAT + sym[a][b]) * g->sf + q];
+        }
+        Gt[a] = u[(IGAM + a) * g->sf + q];
+    }
+    inv3(gt, gu);
+    double dW[3], ddW[3][3], dK[3], dgt[3][3][3], ddgt[3][3][3][3], dGt[3][3], dAt[3][3][3];
+    for (int c = 0; c < 3; ++c) {
+        dW[c] = D1(u, g, IW, P, c);
+        dK[c] = D1(u, g, IKH, P, c) + 2.0 * D1(u, g, ITH, P, c);
+        for (int a = 0; a < 3; ++a) {
+            dGt[c][a] = D1(u, g, IGAM + a, P, c);
+            for (int b = 0; b < 3; ++b) {
+                dgt[c][a][b] = D1(u, g, IGT + sym[a][b], P, c);
+                dAt[c][a][b] = D1(u, g, IAT + sym[a][b], P, c);
+            }
+        }
+        for (int e = 0; e < 3; ++e) {
+            ddW[c][e] = DD(u, g, IW, P, c, e);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) ddgt[c][e][a][b] = DD(u, g, IGT + sym[a][b], P, c, e);
+        }
+    }
+    double Chr1[3][3][3], Chr2[3][3][3], Gtd[3];
+    for (int kk = 0; kk < 3; ++kk)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Chr1[kk][a][b] = 0.5 * (dgt[a][kk][b] + dgt[b][kk][a] - dgt[kk][a][b]);
+    for (int kk = 0; kk < 3; ++kk)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int l = 0; l < 3; ++l) s += gu[kk][l] * Chr1[l][a][b];
+                Chr2[kk][a][b] = s;
+            }
+    for (int kk = 0; kk < 3; ++kk) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) s += gu[a][b] * Chr2[kk][a][b];
+        Gtd[kk] = s;
+    }
+    /* Ricci scalar R = gu^ij W^2 R_ij (as in the right-hand side) */
+    double Rt[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0;
+            for (int l = 0; l < 3; ++l)
+                for (int m = 0; m < 3; ++m) t1 += gu[l][m] * ddgt[l][m][a][b];
+            for (int c = 0; c < 3; ++c) t2 += gt[c][a] * dGt[b][c] + gt[c][b] * dGt[a][c];
+            for (int c = 0; c < 3; ++c) t3 += Gtd[c] * (Chr1[a][b][c] + Chr1[b][a][c]);
+            for (int l = 0; l < 3; ++l)
+                for (int m = 0; m < 3; ++m)
+                    for (int c = 0; c < 3; ++c)
+                        t4 += gu[l][m] * (Chr2[c][l][a] * Chr1[b][c][m] + Chr2[c][l][b] * Chr1[a][c][m]
+                                          + Chr2[c][a][m] * Chr1[c][l][b]);
+            Rt[a][b] = -0.5 * t1 + 0.5 * t2 + 0.5 * t3 + t4;
+        }
+    (void)Gt;
+    double DDW[3][3], trDDW = 0.0, dW2 = 0.0, R = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += Chr2[c][a][b] * dW[c];
+            DDW[a][b] = ddW[a][b] - s;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            trDDW += gu[a][b] * DDW[a][b];
+            dW2 += gu[a][b] * dW[a] * dW[b];
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            R += gu[a][b] * (W * W * Rt[a][b] + W * (DDW[a][b] + gt[a][b] * trDDW) - 2.0 * gt[a][b] * dW2);
+    /* raised At and At_ij At^ij */
+    double Auu[3][3], AA = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d) s += gu[a][c] * gu[b][d] * At[c][d];
+            Auu[a][b] = s;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) AA += At[a][b] * Auu[a][b];
+    out[0] = R - AA + 2.0 * K * K / 3.0;
+    /* d_j gu^ia = -gu^ic gu^ad d_j gt_cd */
+    double dgu[3][3][3]; /* [j][i][a] */
+    for (int jj = 0; jj < 3; ++jj)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int c = 0; c < 3; ++c)
+                    for (int d = 0; d < 3; ++d) s += gu[a][c] * gu[b][d] * dgt[jj][c][d];
+                dgu[jj][a][b] = -s;
+            }
+    for (int a = 0; a < 3; ++a) {
+        double div = 0.0, chr = 0.0, aw = 0.0, gk = 0.0;
+        for (int jj = 0; jj < 3; ++jj) {
+            /* d_j At^aj */
+            for (int c = 0; c < 3; ++c)
+                for (int d = 0; d < 3; ++d)
+                    div += gu[a][c] * gu[jj][d] * dAt[jj][c][d]
+                         + At[c][d] * (dgu[jj][a][c] * gu[jj][d] + gu[a][c] * dgu[jj][jj][d]);
+            for (int kk = 0; kk < 3; ++kk) chr += Chr2[a][jj][kk] * Auu[jj][kk] + Chr2[jj][jj][kk] * Auu[a][kk];
+            aw += Auu[a][jj] * dW[jj];
+            gk += gu[a][jj] * dK[jj];
+        }
+        out[1 + a] = W * W * (div + chr - 3.0 * aw / W - 2.0 * gk / 3.0);
+    }
+}
+
+/* Constraints on every active point: c[m*sf + q] for m = H, M^x, M^y, M^z
+   (ghost entries 0), and the volume-normalised L2 norms of paper Sec. 2.3,
+   sqrt(sum C^2 dV / sum dV) over the active cells (cubic cells of one box:
+   dV is constant), summed in plain (k, j, i) order. */
+int oz_constraints(const double* u, double* c, double* norms, long sf, int nx, int ny, int nz, int ng, double dx,
+                   double dy, double dz, double x0, double y0, double z0, int bc, const oz_params* p, int nthreads)
+{
+    grid g;
+    if (!u || !c || !norms || !p || make_grid(&g, sf, nx, ny, nz, ng, dx, dy, dz, x0, y0, z0, bc)) return -1;
+    for (long q = 0; q < 4 * sf; ++q) c[q] = 0.0;
+#pragma omp parallel for schedule(static) num_threads(nthreads < 1 ? 1 : nthreads)
+    for (int k = g.ng; k < g.ng + g.n[2]; ++k)
+        for (int j = g.ng; j < g.ng + g.n[1]; ++j)
+            for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
+                double out[4];
+                constraints_point(u, &g, p, i, j, k, out);
+                for (int m = 0; m < 4; ++m) c[m * sf + lin(&g, i, j, k)] = out[m];
+            }
+    for (int m = 0; m < 4; ++m) {
+        double s = 0.0;
+        for (int k = g.ng; k < g.ng + g.n[2]; ++k)
+            for (int j = g.ng; j < g.ng + g.n[1]; ++j)
+                for (int i = g.ng; i < g.ng + g.n[0]; ++i) {
+                    double v = c[m * sf + lin(&g, i, j, k)];
+                    s += v * v;
+                }
+        norms[m] = sqrt(s / ((double)g.n[0] * g.n[1] * g.n[2]));
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */

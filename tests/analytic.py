@@ -151,6 +151,37 @@ def adm_expected_fn(prim):
     return expected
 
 
+def adm_constraints_fn(prim):
+    """x -> [H, M^x, M^y, M^z] of the ADM data: H = R + K^2 - K_ij K^ij,
+    M^i = gamma^ij (D_k K^k_j - d_j K) (vacuum, paper Sec. 2.3)."""
+    gam = lambda x: prim(x)[0]
+    Kf = lambda x: prim(x)[1]
+    chris = _christoffel(gam)
+    dchris = jacfwd(chris)
+
+    def Kmix(x):
+        return _inv3(gam(x)) @ Kf(x)
+
+    dKmix = jacfwd(Kmix)
+
+    def cons(x):
+        g, K = gam(x), Kf(x)
+        gi = _inv3(g)
+        G = chris(x)
+        dG = dchris(x)
+        Ric = (torch.einsum("kijk->ij", dG) - torch.einsum("kikj->ij", dG)
+               + torch.einsum("kkl,lij->ij", G, G) - torch.einsum("kjl,lik->ij", G, G))
+        Km = gi @ K
+        trK = torch.trace(Km)
+        H = torch.einsum("ij,ij->", gi, Ric) + trK * trK - torch.trace(Km @ Km)
+        dKm = dKmix(x)
+        divK = torch.einsum("kjk->j", dKm) + torch.einsum("kkl,lj->j", G, Km) - torch.einsum("lkj,kl->j", G, Km)
+        M = gi @ (divK - torch.einsum("kkj->j", dKm))
+        return torch.cat([H.reshape(1), M, torch.zeros(21, dtype=DT)])
+
+    return cons
+
+
 def evaluate(fn, grid, only_active=False) -> np.ndarray:
     """Evaluate x -> 25-vector on the stored (or active) points of a grid;
     returns (25, Nz, Ny, Nx) (zeros off the active set if only_active)."""

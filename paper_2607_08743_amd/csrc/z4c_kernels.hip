@@ -37,6 +37,24 @@ namespace {
 // compiler sinks each staged field's stencil arithmetic to the end of the
 // kernel, where the results are used, and keeps every loaded LDS value alive
 // across all later barriers (hundreds of spilled registers).
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt immediates (gfx9 encoding): vmcnt <= n with the other counters
+// unconstrained, and lgkmcnt = 0
+#define VM_N(n) ((((n) & 0xF) | ((((n) >> 4) & 0x3) << 14)) | (0x7 << 4) | (0xF << 8))
+#define LGKM0 (0xF | (0x3 << 14) | (0x7 << 4))
+
+// Workgroup barrier without a memory fence (s_barrier alone): the caller
+// waits for exactly the LDS writes it needs with s_waitcnt, so that later
+// tiles' loads stay in flight across it.  The empty asm statements keep the
+// compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void bar()
+{
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 template <typename R>
 __device__ __forceinline__ void pin(R& x)
 {
@@ -222,21 +240,30 @@ struct Brick {
     static constexpr int NGZ = (GZN + NT - 1) / NT;
 };
 
-template <typename R, int BX, int BY, int BZ, int WAVES>
+template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA>
 __global__ void __attribute__((amdgpu_flat_work_group_size(BX* BY* BZ, BX* BY* BZ)))
 __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
 {
     using T = Brick<R, BX, BY, BZ>;
     constexpr int NT = T::NT, SX = T::SX, SXY = T::SXY, TN = T::TN;
-    __shared__ R tile[TN];
+    static_assert(!DMA || (sizeof(R) == 8 && SX % 2 == 0 && NT % 64 == 0), "DMA staging: float64, even rows");
+    // DMA staging moves pairs of doubles (16 bytes per lane); every wave issues
+    // the same NR rounds, so the tile is padded to NR * NT pairs.
+    constexpr int NR = (TN / 2 + NT - 1) / NT;
+    constexpr int TNP = DMA ? NR * NT * 2 : TN;
+    __shared__ __attribute__((aligned(16))) R tile0[TNP];
+    __shared__ __attribute__((aligned(16))) R tile1[DMA ? TNP : 2];
+    __shared__ __attribute__((aligned(16))) R tile2[DMA ? TNP : 2];
     __shared__ R gyt[T::GYN];  // unscaled D1_y of the staged field (x-halo 2)
     __shared__ R gzt[T::GZN];  // unscaled D1_z of the staged field (x- and y-halo 2)
+    auto tilebuf = [&](int k) -> R* { return k == 0 ? tile0 : (k == 1 ? tile1 : tile2); };
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
     const int cofs = (tz + 3) * SXY + (ty + 3) * SX + (tx + 3);
-    const R* t = tile + cofs;
+    const R* tb = tile0;  // tile of the staged field
+    const R* t = tb + cofs;
     constexpr int PX = T::PX;
     const R* ty_c = gyt + (tz * BY + ty) * PX + (tx + 2);        // own slot in the D1_y plane
     const R* tz_c = gzt + (tz * (BY + 4) + ty + 2) * PX + (tx + 2);  // own slot in the D1_z plane
@@ -255,14 +282,27 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         gz_src[r] = (z + 3) * SXY + (y + 1) * SX + (x + 1);
     }
 
-    // Blocks are dealt to the 8 XCDs round-robin; renumber them so that each
-    // XCD walks a contiguous run of bricks (neighbouring halos share its L2).
+    // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD one
+    // contiguous chunk of the brick sequence and let its resident blocks
+    // walk it NS bricks at a time: bricks processed together, and in
+    // consecutive rounds, are neighbours (x fastest, then y), so most of
+    // their halos come from that XCD's L2.
     const long G = gridDim.x;
     const long b = blockIdx.x;
-    const long lb = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
     const long total = set.brick_begin[set.nbox];
+    const bool split = G % 8 == 0;
+    const long NS = split ? G / 8 : G;              // blocks per XCD
+    const long slot = split ? b / 8 : b;
+    const long C = split ? (total + 7) / 8 : total;  // bricks per XCD
+    const long first = (split ? (b % 8) * C : 0) + slot;
+    const long last = split ? ((b % 8) + 1) * C < total ? ((b % 8) + 1) * C : total : total;
 
-    for (long w = lb; w < total; w += G) {
+    for (long w = first; w < last; w += NS) {
+        if (DMA && w != first) {
+            // every wave is done with the previous brick's tiles before new loads land
+            __builtin_amdgcn_s_waitcnt(LGKM0);
+            bar();
+        }
         int bi = 0;
         while (w >= set.brick_begin[bi + 1]) ++bi;
         const BoxDev& B = set.box[bi];
@@ -307,46 +347,108 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             wev[d] = (be[d] < R(0) ? -be[d] : be[d]) * fc.i24h[d] + fc.ko[d];
         }
 
-        // Staging.  Each thread copies the same NE tile slots for every field;
-        // their offsets inside a field (-1 outside the stored box) are computed
-        // once per brick.  The next field is loaded into registers while the
-        // current one is being differentiated (the load latency hides behind
-        // the stencil work), then written to the tile between two barriers.
-        constexpr int NE = (TN + NT - 1) / NT;
+        // Field order of the staging sequence.
+        constexpr int NSEQ = 25;
+        auto seq = [](int i) -> int {
+            return i < 6 ? F_GT + i
+                 : i < 9 ? F_GAM + (i - 6)
+                 : i < 12 ? F_BE + (i - 9)
+                 : i == 12 ? F_W
+                 : i == 13 ? F_AL
+                 : i == 14 ? F_KH
+                 : i == 15 ? F_TH
+                 : i < 22 ? F_AT + (i - 16)
+                 : F_BB + (i - 22);
+        };
+
+        // Register staging (float32 tiles, or boxes the DMA path does not take).
+        // Each thread copies the same NE tile slots for every field; their
+        // offsets inside a field (-1 outside the stored box) are computed once
+        // per brick.  The next field is loaded into registers while the current
+        // one is being differentiated, then written to the tile between two
+        // barriers.
+        constexpr int NE = DMA ? 1 : (TN + NT - 1) / NT;
         int goff[NE];
-#pragma unroll
-        for (int r = 0; r < NE; ++r) {
-            const int e = tid + r * NT;
-            int o = -1;
-            if (e < TN) {
-                const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
-                const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
-                if (gi < Nx && gj < Ny && gk < Nz) o = (gk * Ny + gj) * Nx + gi;
-            }
-            goff[r] = o;
-        }
         double pre[NE];
         int pre_f = -1;
+        // DMA staging (float64): each field's tile is loaded straight into one
+        // of three LDS buffers two fields ahead of its use, without registers;
+        // per round a wave moves 64 pairs of doubles into consecutive LDS.
+        int doff[DMA ? NR : 1];
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        if constexpr (DMA) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int e = 2 * (r * NT + tid);
+                int o = 0;  // slots outside the stored box read a harmless valid address
+                if (e < TN) {
+                    const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
+                    const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
+                    if (gi < Nx && gj < Ny && gk < Nz) o = (gk * Ny + gj) * Nx + gi;
+                }
+                doff[r] = o;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NE; ++r) {
+                const int e = tid + r * NT;
+                int o = -1;
+                if (e < TN) {
+                    const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
+                    const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
+                    if (gi < Nx && gj < Ny && gk < Nz) o = (gk * Ny + gj) * Nx + gi;
+                }
+                goff[r] = o;
+            }
+        }
+        auto dma_issue = [&](int f, int k) {
+            const double* src = B.u_in + f * sf;
+            R* dst = tilebuf(k) + 2 * 64 * wave;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                __builtin_amdgcn_global_load_lds((const void*)(src + doff[r]), (lds_void*)(dst + 2 * NT * r), 16, 0,
+                                                 0);
+        };
         auto prefetch = [&](int f) {
             const double* src = B.u_in + f * sf;
 #pragma unroll
             for (int r = 0; r < NE; ++r) pre[r] = goff[r] >= 0 ? src[goff[r]] : 0.0;
             pre_f = f;
         };
-        // make field f (already prefetched) the staged field and start loading `next`
-        auto stage_field = [&](int f, int next) {
-            (void)f;
-            const double off = sizeof(R) == 4 ? flat_of(pre_f) : 0.0;
-            __syncthreads();
+        // make element i of the sequence the staged field
+        auto stage_field = [&](int i) {
+            if constexpr (DMA) {
+                // wait until this wave's loads of field i have landed (the loads
+                // of field i+1, issued later, may still be in flight), then
+                // until every wave has, and has finished reading field i-1
+                if (i + 1 < NSEQ)
+                    __builtin_amdgcn_s_waitcnt(VM_N(NR));
+                else
+                    __builtin_amdgcn_s_waitcnt(VM_N(0));
+                __builtin_amdgcn_s_waitcnt(LGKM0);
+                bar();
+                if (i + 2 < NSEQ) dma_issue(seq(i + 2), (i + 2) % 3);
+                tb = tilebuf(i % 3);
+                t = tb + cofs;
+            } else {
+                const double off = sizeof(R) == 4 ? flat_of(pre_f) : 0.0;
+                __syncthreads();
+                R* tw = tilebuf(0);
 #pragma unroll
-            for (int r = 0; r < NE; ++r) {
-                const int e = tid + r * NT;
-                if (r + 1 < NE || e < TN) tile[e] = goff[r] >= 0 ? R(pre[r] - off) : R(0);
+                for (int r = 0; r < NE; ++r) {
+                    const int e = tid + r * NT;
+                    if (r + 1 < NE || e < TN) tw[e] = goff[r] >= 0 ? R(pre[r] - off) : R(0);
+                }
+                __syncthreads();
+                if (i + 1 < NSEQ) prefetch(seq(i + 1));
             }
-            __syncthreads();
-            if (next >= 0) prefetch(next);
         };
-        prefetch(F_GT);
+        if constexpr (DMA) {
+            dma_issue(seq(0), 0);
+            dma_issue(seq(1), 1);
+        } else {
+            prefetch(seq(0));
+        }
 
         // centre value of the staged field (its flat value restored in float32 mode)
         auto tval = [&](int f) {
@@ -376,7 +478,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // that each mixed derivative needs 4 LDS reads instead of 16.
         auto d1_planes = [&]() {
             auto u1 = [&](int c, int st) {
-                return R(8) * (tile[c + st] - tile[c - st]) - (tile[c + 2 * st] - tile[c - 2 * st]);
+                return R(8) * (tb[c + st] - tb[c - st]) - (tb[c + 2 * st] - tb[c - 2 * st]);
             };
 #pragma unroll
             for (int r = 0; r < T::NGY; ++r) {
@@ -388,7 +490,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
                 const int e = tid + r * NT;
                 if (r + 1 < T::NGZ || e < T::GZN) gzt[e] = u1(gz_src[r], SXY);
             }
-            __syncthreads();
+            if constexpr (DMA) {
+                __builtin_amdgcn_s_waitcnt(LGKM0);
+                bar();  // no memory fence: the next fields' loads stay in flight
+            } else {
+                __syncthreads();
+            }
         };
         auto outer = [&](const R* g, int st) { return R(8) * (g[st] - g[-st]) - (g[2 * st] - g[-2 * st]); };
         // gradient and Hessian of the staged field (mixed terms from the D1 planes)
@@ -409,7 +516,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R dgt[6][3], Rt[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            stage_field(F_GT + q, q < 5 ? F_GT + q + 1 : F_GAM);
+            stage_field(q);
             d1_planes();
             const P3 pq = field_pairs();
             ak[F_GT + q] = advko(pq);
@@ -477,7 +584,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R Gam[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            stage_field(F_GAM + a, a < 2 ? F_GAM + a + 1 : F_BE);
+            stage_field(6 + a);
             Gam[a] = tval(F_GAM + a);
             const P3 pq = field_pairs();
             ak[F_GAM + a] = advko(pq);
@@ -495,7 +602,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R dbe[3][3], lapb[3], gdivb[3] = {R(0), R(0), R(0)};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            stage_field(F_BE + a, a < 2 ? F_BE + a + 1 : F_W);
+            stage_field(9 + a);
             d1_planes();
             const P3 pq = field_pairs();
             ak[F_BE + a] = advko(pq);
@@ -512,7 +619,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- conformal factor: DDW_ij = d_i d_j W - Gamma^k_ij d_k W
         R dW[3], DDW[6], W;
         {
-            stage_field(F_W, F_AL);
+            stage_field(12);
             d1_planes();
             W = tval(F_W);
             const P3 pq = field_pairs();
@@ -526,7 +633,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- lapse: DDa_ij = d_i d_j alpha - Gamma^k_ij d_k alpha
         R da[3], DDa[6], al;
         {
-            stage_field(F_AL, F_KH);
+            stage_field(13);
             d1_planes();
             al = tval(F_AL);
             const P3 pq = field_pairs();
@@ -540,14 +647,14 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- Khat and Theta: only the combination 2 d Khat + d Theta is used
         R dkt[3], Kh, Th;
         {
-            stage_field(F_KH, F_TH);
+            stage_field(14);
             Kh = tval(F_KH);
             const P3 pk = field_pairs();
             ak[F_KH] = advko(pk);
             grad(pk, dkt);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] *= R(2);
-            stage_field(F_TH, F_AT);
+            stage_field(15);
             Th = tval(F_TH);
             const P3 pt = field_pairs();
             ak[F_TH] = advko(pt);
@@ -561,13 +668,13 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         R At[6], Bv[3];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            stage_field(F_AT + q, q < 5 ? F_AT + q + 1 : F_BB);
+            stage_field(16 + q);
             At[q] = tval(F_AT + q);
             ak[F_AT + q] = advko(field_pairs());
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            stage_field(F_BB + a, a < 2 ? F_BB + a + 1 : -1);
+            stage_field(22 + a);
             Bv[a] = tval(F_BB + a);
             ak[F_BB + a] = advko(field_pairs());
         }
@@ -670,8 +777,20 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     }
 }
 
-template <typename R, int BX, int BY, int BZ, int WAVES>
-hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s)
+// DMA staging moves 16-byte pairs: every tile row must start on an even
+// element of a 16-byte aligned field (odd ghost width, even nx, even field
+// stride, aligned base).
+inline bool dma_compatible(const BoxSet& set)
+{
+    for (int b = 0; b < set.nbox; ++b) {
+        const BoxDev& B = set.box[b];
+        if (B.ng % 2 == 0 || B.n[0] % 2 != 0 || B.sf % 2 != 0 || ((uintptr_t)B.u_in & 15) != 0) return false;
+    }
+    return true;
+}
+
+template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA>
+hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s)
 {
     const long total = set.brick_begin[set.nbox];
     if (total <= 0) return hipSuccess;
@@ -682,15 +801,25 @@ hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int sta
             int dev = 0, cus = 0, per = 0;
             (void)hipGetDevice(&dev);
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES>, BX * BY * BZ, 0);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES, DMA>,
+                                                               BX * BY * BZ, 0);
             cap = cus * (per > 0 ? per : 1);
         }
         if (grid > cap) grid = cap;
     }
     grid = (grid + 7) / 8 * 8;  // whole XCD rounds (idle blocks exit at once)
-    hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s, set, p,
-                       mode, stage);
+    hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES, DMA>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s,
+                       set, p, mode, stage);
     return hipGetLastError();
+}
+
+template <typename R, int BX, int BY, int BZ, int WAVES>
+hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s)
+{
+    if constexpr (sizeof(R) == 8 && BX % 2 == 0 && (BX * BY * BZ) % 64 == 0) {
+        if (dma_compatible(set)) return launch_variant<R, BX, BY, BZ, WAVES, true>(set, p, mode, stage, persistent, s);
+    }
+    return launch_variant<R, BX, BY, BZ, WAVES, false>(set, p, mode, stage, persistent, s);
 }
 
 // ------------------------------------------------------------------------
@@ -866,6 +995,8 @@ static const TileEntry kTiles[] = {
     Z4C_TILE(double, Z4C_FP64, 16, 4, 4, 1),
     Z4C_TILE(double, Z4C_FP64, 8, 4, 4, 2),
     Z4C_TILE(double, Z4C_FP64, 16, 8, 2, 1),
+    Z4C_TILE(double, Z4C_FP64, 16, 2, 8, 1),
+    Z4C_TILE(double, Z4C_FP64, 8, 4, 8, 1),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 16, 4, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 2),

@@ -9,11 +9,13 @@ chosen by the autotuner).  value = zone cycles per second (active cells x
 RK4 steps / wall time), the unit the paper uses.
 
 Extras on the same JSON line: the same workload with float32 arithmetic
-(Z4C_MIXED), the 9-box hierarchy in one persistent launch per substep, the
-roofline of the fused kernel (HIP events around its launches on the stream
-it runs on) and the CPU oracle timed on a bounded sample.
+(Z4C_MIXED), its z >= 0 half with equatorial symmetry, the 9-box hierarchy
+in one persistent launch per substep, the constraint monitor, the roofline
+of the fused kernel (HIP events around its launches on the stream it runs
+on) and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +25,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+KERNEL_SRC = os.path.join(ROOT, "paper_2607_08743_amd", "csrc", "z4c_kernels.hip")
+
+# HBM bytes per fused launch (mean of the four substeps) from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes over `bench.py --tile <tile> --steps 3
+# --warmup 1 --no-extras --no-cpu-baseline`, each scaled by what the same
+# counter reads for a plain 1 GiB device copy (`bench.py --copy-calibration`).
+# Keyed by the SHA-256 of the kernel source the counters were taken on: once
+# the source changes the figure no longer applies and `traffic` is null.
+MEASURED_TRAFFIC = {}
+
+
+def kernel_source_digest():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    n = 1 << 27  # float64 elements: 1 GiB each way
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 3}}))
 
 
 def alg_bytes_per_stage(n, ng=3):
@@ -75,6 +102,31 @@ def fused_kernel_roofline(z4c, I, torch, g, u_dev, dt, tile, params, reps=5):
     return ms
 
 
+def constraint_monitor_rate(z4c, torch, g, u0, n, reps=5):
+    """Constraint monitor (norms only) on the benchmark state: mean time per
+    call (HIP events on the launch stream) and its algorithmic bytes (18
+    fields read over the active points plus the 2-cell stencil margin)."""
+    u = torch.as_tensor(u0, device="cuda")
+    ws = torch.empty(z4c.constraints_workspace(g), dtype=torch.float64, device="cuda")
+    norms = torch.empty(4, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    z4c.constraints(u, g, norms=norms, ws=ws)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        z4c.constraints(u, g, norms=norms, ws=ws)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = 18 * 8 * (n + 4) ** 3
+    out = {"ms_per_call": round(ms, 4), "alg_bytes": alg, "achieved_GBs": round(alg / (ms * 1e-3) / 1e9, 1),
+           "zone_per_s": n ** 3 / (ms * 1e-3), "norms": [float(x) for x in norms.cpu()]}
+    del u, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(I):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     one RK4 step of the 128^3 puncture box (same data recipe), all host
@@ -101,12 +153,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and hierarchy runs")
     ap.add_argument("--tile", default="", help="bx,by,bz,waves,persistent (skip the autotuner)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        torch.cuda.set_device(0)
+        copy_calibration(torch)
+        return
 
     from paper_2607_08743_amd import inputs as I
     from paper_2607_08743_amd import z4c
@@ -146,17 +205,30 @@ def main():
     torch.cuda.empty_cache()
     bytes_stage = alg_bytes_per_stage(args.n)
     achieved = sum(bytes_stage) / (sum(ms) * 1e-3) / 1e9
+    digest = kernel_source_digest()
+    meas = MEASURED_TRAFFIC.get(digest)
+    traffic = meas["bytes_per_launch"] if meas and tuple(meas["tile"]) == tuple(best.as_tuple()) \
+        and meas["n"] == args.n else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "fused_stage", "ms_per_launch": [round(x, 4) for x in ms],
-            "alg_bytes_per_launch": bytes_stage}
+            "ms_per_launch_mean": round(sum(ms) / 4, 4),
+            "alg_bytes_per_launch": bytes_stage, "alg_bytes_per_launch_mean": sum(bytes_stage) // 4,
+            "kernel_source_sha256": digest[:16]}
 
     extras = {}
+    extras["constraints"] = constraint_monitor_rate(z4c, torch, g, u0, args.n)
     if not args.no_extras:
         pm = z4c.default_params(precision=z4c.MIXED)
         sec_m, best_m, _, fin_m = run([box], pm, None)
         extras["mixed"] = {"value": active * args.steps / sec_m, "ms_per_step": 1e3 * sec_m / args.steps,
                            "tile": list(best_m.as_tuple()), "finite": fin_m}
+        ge, ue, dte = I.config_punctures_equatorial(args.n)
+        sec_e, best_e, _, fin_e = run([I.Box(ge, ue, None, dte)], params, None)
+        extras["equatorial"] = {"value": ge.active * args.steps / sec_e, "ms_per_step": 1e3 * sec_e / args.steps,
+                                "active_cells": ge.active, "full_box_equivalent_value":
+                                    2 * ge.active * args.steps / sec_e,
+                                "tile": list(best_e.as_tuple()), "finite": fin_e}
         boxes = I.config_hierarchy()
         act_h = sum(b.grid.active for b in boxes)
         sec_h, best_h, _, fin_h = run(boxes, params, None)

@@ -57,7 +57,12 @@ typedef enum {
 typedef enum {
     Z4C_BC_PERIODIC = 0,   /* ghosts wrap around the active box */
     Z4C_BC_SOMMERFELD = 1, /* ghost points are evolved with the outgoing-wave condition (Sec. 2.2.2) */
-    Z4C_BC_COPY = 2        /* ghosts are copied from a caller-owned shell (stand-in for AMR/neighbour data) */
+    Z4C_BC_COPY = 2,       /* ghosts are copied from a caller-owned shell (stand-in for AMR/neighbour data) */
+    Z4C_BC_EQUATORIAL = 3  /* equatorial symmetry (Sec. 2.4, the paper's octant/equatorial runs): the lower z
+                              face of the active box is the plane z = 0; ghost layer ng-1-m is layer ng+m
+                              times (-1)^(number of z indices of the component), filled by apply_ghosts;
+                              the other five faces are Sommerfeld faces whose ghosts are evolved.  Place
+                              the box at z0 = dz/2 for the outgoing-wave terms to see z >= 0. */
 } z4c_bc;
 
 typedef enum {
@@ -86,8 +91,9 @@ void z4c_default_params(z4c_params* p);
 
 /* Right-hand side of the 25 fields (Sec. 2.1.1 equations, Sec. 2.2 stencils).
  * Writes rhs on every active point; on a Z4C_BC_SOMMERFELD box also on every
- * ghost point (the outgoing-wave right-hand side of Sec. 2.2.2); every other
- * ghost entry of rhs is set to 0.  Precondition: the ghosts of u are valid
+ * ghost point, on a Z4C_BC_EQUATORIAL box on the ghost points at and above
+ * the symmetry plane (the outgoing-wave right-hand side of Sec. 2.2.2); every
+ * other ghost entry of rhs is set to 0.  Precondition: the ghosts of u are valid
  * (apply_ghosts for periodic/copy boxes).  u and rhs must not overlap.
  * Uses the default tile.  Returns Z4C_OK or an error as above. */
 int rhs_z4c(const double* u, double* rhs, long sf, int nx, int ny, int nz, int ng, double dx, double dy,
@@ -100,8 +106,9 @@ int rhs_z4c(const double* u, double* rhs, long sf, int nx, int ny, int nz, int n
  *   stage 4:  u_out = E(acc  + dt/6 k)                              (u_n is not read; may be NULL)
  * where E restores det gt = 1 and tr At = 0 (gt <- gt/cbrt(det gt), then
  * At <- At - gt (gt^kl At_kl)/3), always in float64.  Points written: the
- * active points, plus every ghost point of a Sommerfeld box; ghosts of other
- * boxes are left for apply_ghosts.  Preconditions: ghosts of u_in valid.
+ * active points, plus the ghost points of Sommerfeld faces (every ghost of a
+ * Sommerfeld box, those at and above the plane of an equatorial box); the
+ * other ghosts are left for apply_ghosts.  Preconditions: ghosts of u_in valid.
  * Aliasing: u_out must differ from u_in and acc; acc must differ from u_in
  * and u_n; u_out == u_n is allowed only in stage 4 (the usual rotation is
  * u_n -> A -> B -> A -> u_n).  dt > 0, 1 <= stage <= 4. */
@@ -113,9 +120,32 @@ int rk4_substep(int stage, double dt, const double* u_in, const double* u_n, dou
  * active box.  Z4C_BC_COPY: copy from `shell`, a float64 array of shape
  * (25, nshell), nshell = Nx*Ny*Nz - nx*ny*nz, holding the ghost points in
  * the order (k outermost, then j, then i fastest) with active points skipped.
+ * Z4C_BC_EQUATORIAL: the ng layers below the symmetry plane, every i and j,
+ * from their mirror layers with the z parity of each field (the other ghosts
+ * are evolved and must be valid already).
  * Z4C_BC_SOMMERFELD: nothing to do (the ghosts are evolved); returns Z4C_OK.
  * `shell` must be NULL unless bc == Z4C_BC_COPY. */
 int apply_ghosts(double* u, const double* shell, long sf, int nx, int ny, int nz, int ng, int bc, void* stream);
+
+/* Constraint monitor (Sec. 2.3): the Hamiltonian constraint
+ *   H = R - At_ij At^ij + (2/3) K^2              (K = Khat + 2 Theta)
+ * and the momentum constraint
+ *   M^i = W^2 [ Dt_j At^ij - 3 At^ij d_j W / W - (2/3) gt^ij d_j K ]
+ * of the vacuum 3+1 equations, on every active point, with R assembled as in
+ * the right-hand side (evolved Gt in its d Gt term) and the 4th-order
+ * centred stencils of Sec. 2.2; and their volume-normalised L2 norms
+ * sqrt(sum C^2 / ncells) over the active cells (uniform cells: the dV
+ * weights cancel).  Precondition: ghosts of u valid.
+ *   c        device, NULL or 4 fields of stride sf (H, M^x, M^y, M^z); ghost
+ *            entries are set to 0.  Must not overlap u.
+ *   norms    device, 4 doubles (same order).
+ *   ws       device workspace of ws_len >= z4c_constraints_workspace(nx, ny,
+ *            nz) doubles, caller-owned, overwritten.
+ * The reduction order is fixed by the box size, so the norms are bitwise
+ * reproducible.  Nothing is allocated. */
+long z4c_constraints_workspace(int nx, int ny, int nz);
+int z4c_constraints(const double* u, double* c, double* norms, double* ws, long ws_len, long sf, int nx, int ny,
+                    int nz, int ng, double dx, double dy, double dz, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batched form: every box of a hierarchy (Sec. 2.2.1 box-in-box levels)  */

@@ -23,7 +23,11 @@ something other than itself):
 * Z4 damping: homogeneous Theta and Z modes decay at rates kappa1(2+kappa2) and
   kappa1 through the classical RK4 amplification polynomial;
 * Sommerfeld: F(t-r)/r gives the exact time derivative at 2nd order;
-* pi symmetry: symmetrised data stays bitwise symmetric.
+* pi symmetry: symmetrised data stays bitwise symmetric;
+* equatorial symmetry: a half box with the reflection boundary evolves
+  bitwise like the upper half of the full, z-symmetric Sommerfeld box (whose
+  evolution uses no reflection code), and its ghost fill matches the parity
+  rule written out independently in the test.
 
 Parity unpinned (no physics pin distinguishes them; both paths must agree):
 the kappa3 terms (default 0), ``lapse_uses_K`` and the use of the computed
@@ -42,7 +46,7 @@ SRC = os.path.join(HERE, "z4c_oracle.c")
 LIB = os.path.join(HERE, "liboracle_z4c.so")
 
 NF = 25
-BC_PERIODIC, BC_SOMMERFELD, BC_COPY = 0, 1, 2
+BC_PERIODIC, BC_SOMMERFELD, BC_COPY, BC_EQUATORIAL = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -53,6 +57,13 @@ def build(force: bool = True) -> str:
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+class OzLevel(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("sf", ctypes.c_long),
+                ("n", ctypes.c_int * 3), ("ng", ctypes.c_int), ("h", ctypes.c_double * 3),
+                ("x0", ctypes.c_double * 3), ("F", ctypes.c_int * 3), ("bc", ctypes.c_int),
+                ("has_prev", ctypes.c_int)]
 
 
 class OzParams(ctypes.Structure):
@@ -92,9 +103,17 @@ def lib():
                                               ctypes.c_int]
         L.oz_constraints.argtypes = [dp, dp, dp] + geo + [ctypes.POINTER(OzParams), ctypes.c_int]
         L.oz_stencil_1d.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        L.oz_bo_advance.argtypes = [ctypes.POINTER(OzLevel), ctypes.c_int, ctypes.POINTER(OzParams), ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int]
+        L.oz_prolong.argtypes = [dp, dp, dp, dp, ctypes.c_long, ip, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_int,
+                                 ip, ctypes.c_int]
+        L.oz_restrict.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_int, ip,
+                                  ctypes.c_int]
+        L.oz_transfer_weights.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
         L.oz_mixed_2d.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         for name in ("oz_rhs", "oz_rhs_points", "oz_apply_ghosts", "oz_enforce", "oz_stage_points", "oz_rk4",
-                     "oz_stencil_1d", "oz_mixed_2d", "oz_constraints"):
+                     "oz_stencil_1d", "oz_mixed_2d", "oz_constraints", "oz_bo_advance", "oz_prolong", "oz_restrict",
+                     "oz_transfer_weights"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -199,6 +218,76 @@ def constraints(u, g, p=None, nthreads=None):
     _check(lib().oz_constraints(_dp(u), _dp(c), _dp(norms), u[0].size, *_geo(g), ctypes.byref(p),
                                 nthreads or threads_default()), "constraints")
     return c, norms
+
+
+def _ivec(v):
+    a = (ctypes.c_int * 3)(*[int(x) for x in v])
+    return ctypes.cast(a, ctypes.POINTER(ctypes.c_int)), a
+
+
+class Level:
+    """One level of a box-in-box hierarchy for bo_advance: its grid, state u
+    (advanced in place), the earlier time level `prev` (allocated here) and
+    F, the parent active cell index of its lower faces (levels >= 1)."""
+
+    def __init__(self, grid, u, F=(0, 0, 0)):
+        self.grid = grid
+        self.u = _state(u)
+        self.prev = np.zeros_like(u)
+        self.F = tuple(int(x) for x in F)
+        self.has_prev = 0
+
+
+def bo_advance(levels, dt0, nsteps, p=None, nthreads=None) -> None:
+    """Berger-Oliger advance of the hierarchy by nsteps coarse steps of dt0
+    (level l takes 2^l steps of dt0 / 2^l each)."""
+    p = p or params()
+    arr = (OzLevel * len(levels))()
+    for L, lv in zip(arr, levels):
+        g = lv.grid
+        L.u = lv.u.ctypes.data
+        L.prev = lv.prev.ctypes.data
+        L.sf = lv.u[0].size
+        L.n[:] = [int(x) for x in g.n]
+        L.ng = int(g.ng)
+        L.h[:] = [float(x) for x in g.h]
+        L.x0[:] = [float(x) for x in g.x0]
+        L.F[:] = list(lv.F)
+        L.bc = int(g.bc)
+        L.has_prev = lv.has_prev
+    _check(lib().oz_bo_advance(arr, len(levels), ctypes.byref(p), float(dt0), int(nsteps),
+                               nthreads or threads_default()), "bo_advance")
+    for L, lv in zip(arr, levels):
+        lv.has_prev = L.has_prev
+
+
+def prolong(parent_levels, wt, np_, ngp, uc, nc, ngc, F, nthreads=None) -> None:
+    """Fill every ghost of the child state uc from up to three parent time
+    levels (None allowed) combined with the time weights wt."""
+    pa = [None if a is None else _dp(_state(a)) for a in parent_levels]
+    sfp = next(a for a in parent_levels if a is not None)[0].size
+    wt = np.ascontiguousarray(wt, dtype=np.float64)
+    pn, _k1 = _ivec(np_)
+    cn, _k2 = _ivec(nc)
+    fF, _k3 = _ivec(F)
+    _check(lib().oz_prolong(pa[0], pa[1], pa[2], _dp(wt), sfp, pn, int(ngp), _dp(_state(uc)), uc[0].size, cn, int(ngc),
+                            fF, nthreads or threads_default()), "prolong")
+
+
+def restrict(uc, nc, ngc, up, np_, ngp, F, nthreads=None) -> None:
+    cn, _k1 = _ivec(nc)
+    pn, _k2 = _ivec(np_)
+    fF, _k3 = _ivec(F)
+    _check(lib().oz_restrict(_dp(_state(uc)), uc[0].size, cn, int(ngc), _dp(_state(up)), up[0].size, pn, int(ngp), fF,
+                             nthreads or threads_default()), "restrict")
+
+
+def transfer_weights(theta, quadratic):
+    """(time weights (3,), prolongation weights for even / odd child cells
+    (6,) each, restriction weights (4,))."""
+    out = [np.zeros(3), np.zeros(6), np.zeros(6), np.zeros(4)]
+    _check(lib().oz_transfer_weights(float(theta), int(quadratic), *[_dp(o) for o in out]), "transfer_weights")
+    return tuple(out)
 
 
 def stencil_1d(op, f, h, beta_sign=1.0) -> np.ndarray:

@@ -32,7 +32,12 @@
  *     the array edge), speed 1 for every field;
  *   - enforcement: gt <- gt / cbrt(det gt), then At <- At - gt (gu.At)/3 with
  *     gu the inverse of the rescaled gt;
- *   - 1/W in the Gt equation uses max(W, w_floor).
+ *   - 1/W in the Gt equation uses max(W, w_floor);
+ *   - equatorial symmetry (Sec. 2.2.2 / Sec. 2.4 use it to halve the work):
+ *     the lower z face of the active box is the plane z = 0; ghost layer
+ *     k = ng-1-m holds the value of layer ng+m times (-1)^(number of z
+ *     indices of the component), for every i, j; the other five faces are
+ *     Sommerfeld faces as above.
  *
  * Data layout (numpy order [f][k][j][i], x fastest):
  *   u[f*sf + (k*Ny + j)*Nx + i], Nx = nx + 2 ng, ..., i in [0, Nx).
@@ -56,7 +61,7 @@ enum {
     IBB = 22          /* B^x..z : 22..24 */
 };
 
-enum { BC_PERIODIC = 0, BC_SOMMERFELD = 1, BC_COPY = 2 };
+enum { BC_PERIODIC = 0, BC_SOMMERFELD = 1, BC_COPY = 2, BC_EQUATORIAL = 3 };
 
 typedef struct {
     double kappa1, kappa2, kappa3, eta, shift_coeff, ko_sigma, w_floor;
@@ -85,6 +90,17 @@ static double flat_value(int f)
     if (f == IW || f == IAL) return 1.0;
     if (f == IGT + 0 || f == IGT + 3 || f == IGT + 5) return 1.0;
     return 0.0;
+}
+
+/* sign of field f under the reflection z -> -z: (-1)^(number of z indices) */
+static double z_parity(int f)
+{
+    static const int tensor_z[6] = {0, 0, 1, 0, 1, 2}; /* xx xy xz yy yz zz */
+    int nz = 0;
+    if (f >= IGT && f < IGT + 6) nz = tensor_z[f - IGT];
+    if (f >= IAT && f < IAT + 6) nz = tensor_z[f - IAT];
+    if (f == IGAM + 2 || f == IBE + 2 || f == IBB + 2) nz = 1;
+    return (nz % 2) ? -1.0 : 1.0;
 }
 
 static long lin(const grid* g, int i, int j, int k)
@@ -593,6 +609,15 @@ static int is_active(const grid* g, int i, int j, int k)
         && k < g->ng + g->n[2];
 }
 
+/* points advanced in time: active points, plus the outer ghost points of
+   Sommerfeld faces (all ghosts of a Sommerfeld box; those above the
+   symmetry plane of an equatorial box) */
+static int is_evolved(const grid* g, int i, int j, int k)
+{
+    if (is_active(g, i, j, k) || g->bc == BC_SOMMERFELD) return 1;
+    return g->bc == BC_EQUATORIAL && k >= g->ng;
+}
+
 /* ------------------------------------------------------------------ */
 /* Ghost fill (periodic wrap or copy from a fixed shell)              */
 /* ------------------------------------------------------------------ */
@@ -606,6 +631,15 @@ static int wrap(int i, int ng, int n)
 static void ghosts(double* u, const double* shell, const grid* g)
 {
     if (g->bc == BC_SOMMERFELD) return; /* ghosts are evolved, never filled */
+    if (g->bc == BC_EQUATORIAL) {
+        /* layers below the symmetry plane mirror those above it */
+        for (int k = 0; k < g->ng; ++k)
+            for (int j = 0; j < g->N[1]; ++j)
+                for (int i = 0; i < g->N[0]; ++i)
+                    for (int f = 0; f < NF; ++f)
+                        u[f * g->sf + lin(g, i, j, k)] = z_parity(f) * u[f * g->sf + lin(g, i, j, 2 * g->ng - 1 - k)];
+        return;
+    }
     long nshell = (long)g->N[0] * g->N[1] * g->N[2] - (long)g->n[0] * g->n[1] * g->n[2];
     long q = 0; /* running index in the shell, points visited in (k, j, i) order */
     for (int k = 0; k < g->N[2]; ++k)
@@ -657,7 +691,7 @@ static int make_grid(grid* g, long sf, int nx, int ny, int nz, int ng, double dx
                      double x0, double y0, double z0, int bc)
 {
     if (nx < 1 || ny < 1 || nz < 1 || ng < 3 || !(dx > 0) || !(dy > 0) || !(dz > 0)) return -1;
-    if (bc < 0 || bc > 2) return -1;
+    if (bc < 0 || bc > 3) return -1;
     g->n[0] = nx; g->n[1] = ny; g->n[2] = nz; g->ng = ng;
     for (int d = 0; d < 3; ++d) g->N[d] = g->n[d] + 2 * ng;
     if (sf < (long)g->N[0] * g->N[1] * g->N[2]) return -1;
@@ -678,7 +712,7 @@ static void rhs_all(const double* u, double* rhs, const grid* g, const oz_params
                 double out[NF];
                 if (is_active(g, i, j, k))
                     rhs_point(u, g, p, i, j, k, out);
-                else if (g->bc == BC_SOMMERFELD)
+                else if (is_evolved(g, i, j, k))
                     somm_point(u, g, i, j, k, out);
                 else
                     for (int f = 0; f < NF; ++f) out[f] = 0.0;
@@ -711,7 +745,7 @@ int oz_rhs_points(const double* u, long sf, int nx, int ny, int nz, int ng, doub
         int i = pts[3 * q], j = pts[3 * q + 1], k = pts[3 * q + 2];
         if (is_active(&g, i, j, k))
             rhs_point(u, &g, p, i, j, k, out + q * NF);
-        else if (bc == BC_SOMMERFELD)
+        else if (is_evolved(&g, i, j, k))
             somm_point(u, &g, i, j, k, out + q * NF);
         else
             for (int f = 0; f < NF; ++f) out[q * NF + f] = 0.0;
@@ -728,8 +762,8 @@ int oz_apply_ghosts(double* u, const double* shell, long sf, int nx, int ny, int
     return 0;
 }
 
-/* enforce the algebraic constraints on the evolved points of u
-   (active points; every point for a Sommerfeld box) */
+/* enforce the algebraic constraints on the evolved points of u (active
+   points, plus the Sommerfeld-face ghosts) */
 int oz_enforce(double* u, long sf, int nx, int ny, int nz, int ng, int bc)
 {
     grid g;
@@ -737,7 +771,7 @@ int oz_enforce(double* u, long sf, int nx, int ny, int nz, int ng, int bc)
     for (int k = 0; k < g.N[2]; ++k)
         for (int j = 0; j < g.N[1]; ++j)
             for (int i = 0; i < g.N[0]; ++i)
-                if (bc == BC_SOMMERFELD || is_active(&g, i, j, k)) enforce_point(u, sf, lin(&g, i, j, k));
+                if (is_evolved(&g, i, j, k)) enforce_point(u, sf, lin(&g, i, j, k));
     return 0;
 }
 
@@ -792,7 +826,7 @@ int oz_rk4(double* u, const double* shell, long sf, int nx, int ny, int nz, int 
                 for (int j = 0; j < g.N[1]; ++j)
                     for (int i = 0; i < g.N[0]; ++i) {
                         long q = lin(&g, i, j, k);
-                        int evolved = bc == BC_SOMMERFELD || is_active(&g, i, j, k);
+                        int evolved = is_evolved(&g, i, j, k);
                         for (int f = 0; f < NF; ++f)
                             us[f * sf + q] = evolved ? u[f * sf + q] + cstage[s] * dt * kk[s][f * sf + q]
                                                      : u[f * sf + q];
@@ -805,7 +839,7 @@ int oz_rk4(double* u, const double* shell, long sf, int nx, int ny, int nz, int 
             for (int j = 0; j < g.N[1]; ++j)
                 for (int i = 0; i < g.N[0]; ++i) {
                     long q = lin(&g, i, j, k);
-                    if (!(bc == BC_SOMMERFELD || is_active(&g, i, j, k))) continue;
+                    if (!is_evolved(&g, i, j, k)) continue;
                     for (int f = 0; f < NF; ++f) {
                         long o = f * sf + q;
                         u[o] = u[o] + dt / 6.0 * (((kk[0][o] + 2.0 * kk[1][o]) + 2.0 * kk[2][o]) + kk[3][o]);
@@ -866,5 +900,322 @@ int oz_mixed_2d(const double* f, int nx, int ny, double hx, double hy, double* o
             out[j * nx + i] = DMIX(buf, &g, 0, P, 0, 1);
         }
     free(buf);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Box-in-box hierarchy with Berger-Oliger time subcycling (Sec.       */
+/* 2.2.1): successive levels refine 2:1 on cell-centred grids (child   */
+/* centres sit h_parent/4 from parent centres), every level takes two  */
+/* steps of half the size per parent step; the child's ghost zone is   */
+/* filled by 6th-order Lagrange interpolation in space of the parent,  */
+/* interpolated in time between the parent's time levels (2nd order,   */
+/* 1st order while the parent has no earlier level); after the child   */
+/* has caught up, every parent cell it covers is overwritten by a      */
+/* 4th-order Lagrange interpolation of the child data.                 */
+/*                                                                     */
+/* Readings (also in the design notes): one box per level; the child's */
+/* lower faces coincide with parent cell faces (F = parent active cell */
+/* index of the face); the restriction stencil reaches one child ghost */
+/* layer, which is filled by prolongation at the new time first.       */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double* u;    /* state, advanced in place */
+    double* prev; /* this level one step earlier (kept for the time interpolation of its child) */
+    long sf;
+    int n[3];
+    int ng;
+    double h[3];
+    double x0[3];
+    int F[3];     /* levels >= 1: lower face in the parent's active cell index */
+    int bc;       /* level 0: its own boundary kind; levels >= 1: ignored (filled from the parent) */
+    int has_prev; /* in/out: prev holds a valid earlier time level */
+} oz_level;
+
+/* Lagrange weights of the m nodes at the point x */
+static void lagrange_weights(const double* nodes, int m, double x, double* w)
+{
+    for (int a = 0; a < m; ++a) {
+        double num = 1.0, den = 1.0;
+        for (int b = 0; b < m; ++b)
+            if (b != a) {
+                num *= x - nodes[b];
+                den *= nodes[a] - nodes[b];
+            }
+        w[a] = num / den;
+    }
+}
+
+/* child active index a along one direction -> first parent active index
+   of the 6-point stencil and its weights.  Child cell a lies in parent cell
+   F + floor(a/2), a quarter parent cell below (a even) or above (a odd)
+   its centre; the stencil takes three parent cells on the near side and
+   two on the far side plus the containing one. */
+static int prolong_1d(int a, int F, double w[6])
+{
+    int half = a >= 0 ? a / 2 : -((1 - a) / 2); /* floor(a / 2) */
+    int odd = a - 2 * half;
+    double nodes[6];
+    int first = odd ? -2 : -3;
+    for (int m = 0; m < 6; ++m) nodes[m] = (double)(first + m);
+    lagrange_weights(nodes, 6, odd ? 0.25 : -0.25, w);
+    return F + half + first;
+}
+
+static void make_level_grid(grid* g, const oz_level* L, int bc)
+{
+    make_grid(g, L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0], L->x0[1],
+              L->x0[2], bc);
+}
+
+/* Fill every ghost point of the child from the parent time levels
+   pa[0..3) combined with the time weights wt (a NULL level has weight 0). */
+static void prolong_ghosts(const grid* gp, const double* const pa[3], const double wt[3], const grid* gc,
+                           double* uc, const int F[3], int nt)
+{
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int k = 0; k < gc->N[2]; ++k)
+        for (int j = 0; j < gc->N[1]; ++j)
+            for (int i = 0; i < gc->N[0]; ++i) {
+                if (is_active(gc, i, j, k)) continue;
+                double wx[6], wy[6], wz[6];
+                int lx = prolong_1d(i - gc->ng, F[0], wx) + gp->ng;
+                int ly = prolong_1d(j - gc->ng, F[1], wy) + gp->ng;
+                int lz = prolong_1d(k - gc->ng, F[2], wz) + gp->ng;
+                for (int f = 0; f < NF; ++f) {
+                    double s = 0.0;
+                    for (int c = 0; c < 6; ++c)
+                        for (int b = 0; b < 6; ++b)
+                            for (int a = 0; a < 6; ++a) {
+                                long q = f * gp->sf + lin(gp, lx + a, ly + b, lz + c);
+                                double v = 0.0;
+                                for (int t = 0; t < 3; ++t)
+                                    if (pa[t]) v += wt[t] * pa[t][q];
+                                s += wz[c] * wy[b] * wx[a] * v;
+                            }
+                    uc[f * gc->sf + lin(gc, i, j, k)] = s;
+                }
+            }
+}
+
+/* Overwrite every parent active cell covered by the child's active region
+   with the 4th-order Lagrange interpolation of the child (nodes at -3/2,
+   -1/2, 1/2, 3/2 child cells from the parent centre). */
+static void restrict_to_parent(const grid* gc, const double* uc, const grid* gp, double* up, const int F[3], int nt)
+{
+    static const double nodes[4] = {-1.5, -0.5, 0.5, 1.5};
+    double r[4];
+    lagrange_weights(nodes, 4, 0.0, r);
+    const int m0 = gc->n[0] / 2, m1 = gc->n[1] / 2, m2 = gc->n[2] / 2;
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int c = 0; c < m2; ++c)
+        for (int b = 0; b < m1; ++b)
+            for (int a = 0; a < m0; ++a) {
+                /* child active cells 2a-1 .. 2a+2 (and likewise in y, z) */
+                int ci = 2 * a - 1 + gc->ng, cj = 2 * b - 1 + gc->ng, ck = 2 * c - 1 + gc->ng;
+                long qp = lin(gp, F[0] + a + gp->ng, F[1] + b + gp->ng, F[2] + c + gp->ng);
+                for (int f = 0; f < NF; ++f) {
+                    double s = 0.0;
+                    for (int z = 0; z < 4; ++z)
+                        for (int y = 0; y < 4; ++y)
+                            for (int x = 0; x < 4; ++x)
+                                s += r[z] * r[y] * r[x] * uc[f * gc->sf + lin(gc, ci + x, cj + y, ck + z)];
+                    up[f * gp->sf + qp] = s;
+                }
+            }
+}
+
+/* weights of the parent levels (earlier, start, end of the parent step)
+   at the fraction theta of the parent step */
+static void time_weights(double theta, int quadratic, double wt[3])
+{
+    if (quadratic) {
+        static const double nodes[3] = {-1.0, 0.0, 1.0};
+        lagrange_weights(nodes, 3, theta, wt);
+    } else {
+        static const double nodes[2] = {0.0, 1.0};
+        wt[0] = 0.0;
+        lagrange_weights(nodes, 2, theta, wt + 1);
+    }
+}
+
+typedef struct {
+    const grid* gp;
+    const double* pa[3];
+    int quadratic;
+    const int* F;
+} parent_ref;
+
+static void fill_level_ghosts(double* u, const grid* g, const parent_ref* pr, double theta, int nt)
+{
+    if (!pr) {
+        ghosts(u, NULL, g);
+        return;
+    }
+    double wt[3];
+    time_weights(theta, pr->quadratic, wt);
+    const double* pa[3] = {pr->quadratic ? pr->pa[0] : NULL, pr->pa[1], pr->pa[2]};
+    prolong_ghosts(pr->gp, pa, wt, g, u, pr->F, nt);
+}
+
+static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt, int nt, const parent_ref* pr,
+                    double theta0);
+
+/* one RK4 step of level l (the textbook form of oz_rk4), ghosts of every
+   stage input filled at that stage's time, then its children */
+static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt, int nt, const parent_ref* pr,
+                    double theta0)
+{
+    oz_level* L = &lv[l];
+    grid g;
+    make_level_grid(&g, L, l == 0 ? L->bc : BC_COPY);
+    const long sf = L->sf;
+    const size_t bytes = (size_t)NF * (size_t)sf * sizeof(double);
+    double* cur = malloc(bytes);
+    double* us = malloc(bytes);
+    double* kk[4];
+    for (int s = 0; s < 4; ++s) kk[s] = malloc(bytes);
+    int rc = 0;
+    if (!cur || !us || !kk[0] || !kk[1] || !kk[2] || !kk[3]) {
+        rc = -3;
+        goto done;
+    }
+    /* stage times in units of the parent step: theta0 + {0, 1/4, 1/4, 1/2} */
+    const double cstage[3] = {0.5, 0.5, 1.0};
+    fill_level_ghosts(L->u, &g, pr, theta0, nt);
+    memcpy(cur, L->u, bytes);
+    for (int s = 0; s < 4; ++s) {
+        const double* src = s == 0 ? L->u : us;
+        rhs_all(src, kk[s], &g, p, nt);
+        if (s == 3) break;
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int k = 0; k < g.N[2]; ++k)
+            for (int j = 0; j < g.N[1]; ++j)
+                for (int i = 0; i < g.N[0]; ++i) {
+                    long q = lin(&g, i, j, k);
+                    int ev = is_evolved(&g, i, j, k);
+                    for (int f = 0; f < NF; ++f)
+                        us[f * sf + q] = ev ? L->u[f * sf + q] + cstage[s] * dt * kk[s][f * sf + q] : L->u[f * sf + q];
+                    if (ev) enforce_point(us, sf, q);
+                }
+        fill_level_ghosts(us, &g, pr, theta0 + 0.5 * cstage[s], nt);
+    }
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int k = 0; k < g.N[2]; ++k)
+        for (int j = 0; j < g.N[1]; ++j)
+            for (int i = 0; i < g.N[0]; ++i) {
+                long q = lin(&g, i, j, k);
+                if (!is_evolved(&g, i, j, k)) continue;
+                for (int f = 0; f < NF; ++f) {
+                    long o = f * sf + q;
+                    L->u[o] = L->u[o] + dt / 6.0 * (((kk[0][o] + 2.0 * kk[1][o]) + 2.0 * kk[2][o]) + kk[3][o]);
+                }
+                enforce_point(L->u, sf, q);
+            }
+    fill_level_ghosts(L->u, &g, pr, theta0 + 0.5, nt);
+    if (l + 1 < nlev) {
+        oz_level* C = &lv[l + 1];
+        parent_ref me = {&g, {L->has_prev ? L->prev : NULL, cur, L->u}, L->has_prev, C->F};
+        for (int m = 0; m < 2 && !rc; ++m) rc = bo_level(lv, nlev, l + 1, p, 0.5 * dt, nt, &me, 0.5 * m);
+        if (!rc) {
+            grid gc;
+            make_level_grid(&gc, C, BC_COPY);
+            fill_level_ghosts(C->u, &gc, &me, 1.0, nt);
+            restrict_to_parent(&gc, C->u, &g, L->u, C->F, nt);
+            fill_level_ghosts(L->u, &g, pr, theta0 + 0.5, nt);
+        }
+    }
+    if (!rc) {
+        memcpy(L->prev, cur, bytes);
+        L->has_prev = 1;
+    }
+done:
+    free(cur);
+    free(us);
+    for (int s = 0; s < 4; ++s) free(kk[s]);
+    return rc;
+}
+
+static int check_levels(const oz_level* lv, int nlev)
+{
+    if (!lv || nlev < 1) return -1;
+    for (int l = 0; l < nlev; ++l) {
+        const oz_level* L = &lv[l];
+        grid g;
+        if (!L->u || !L->prev) return -1;
+        if (make_grid(&g, L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0], L->x0[1],
+                      L->x0[2], l == 0 ? L->bc : BC_COPY))
+            return -1;
+        if (l == 0) {
+            if (L->bc == BC_COPY) return -1; /* the coarsest level needs a boundary of its own */
+            continue;
+        }
+        const oz_level* P = &lv[l - 1];
+        for (int d = 0; d < 3; ++d) {
+            if (L->n[d] % 2 || L->h[d] != 0.5 * P->h[d]) return -1;
+            /* prolongation stencil of every child ghost inside the parent's active cells */
+            double w[6];
+            int lo = prolong_1d(-L->ng, L->F[d], w), hi = prolong_1d(L->n[d] + L->ng - 1, L->F[d], w) + 5;
+            if (lo < 0 || hi >= P->n[d]) return -1;
+        }
+    }
+    return 0;
+}
+
+/* Advance the hierarchy lv[0..nlev) by nsteps steps of the coarsest level
+   (size dt0; level l takes 2^l steps of dt0 / 2^l per coarse step). */
+int oz_bo_advance(oz_level* lv, int nlev, const oz_params* p, double dt0, int nsteps, int nthreads)
+{
+    if (!p || !(dt0 > 0) || nsteps < 0 || check_levels(lv, nlev)) return -1;
+    int nt = nthreads < 1 ? 1 : nthreads;
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = bo_level(lv, nlev, 0, p, dt0, nt, NULL, 0.0);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* Probes for the pins: prolongation of the parent (three time levels,
+   pa[t] may be NULL) into every ghost of the child, and restriction. */
+int oz_prolong(const double* pa0, const double* pa1, const double* pa2, const double* wt, long sfp, const int* np,
+               int ngp, double* uc, long sfc, const int* nc, int ngc, const int* F, int nthreads)
+{
+    grid gp, gc;
+    if (!uc || !wt || !np || !nc || !F) return -1;
+    if (make_grid(&gp, sfp, np[0], np[1], np[2], ngp, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0, BC_COPY)) return -1;
+    if (make_grid(&gc, sfc, nc[0], nc[1], nc[2], ngc, 0.5, 0.5, 0.5, 0.0, 0.0, 0.0, BC_COPY)) return -1;
+    for (int d = 0; d < 3; ++d) {
+        double w[6];
+        int lo = prolong_1d(-ngc, F[d], w) + ngp, hi = prolong_1d(nc[d] + ngc - 1, F[d], w) + 5 + ngp;
+        if (lo < 0 || hi >= gp.N[d]) return -1;
+    }
+    const double* pa[3] = {pa0, pa1, pa2};
+    prolong_ghosts(&gp, pa, wt, &gc, uc, F, nthreads < 1 ? 1 : nthreads);
+    return 0;
+}
+
+int oz_restrict(const double* uc, long sfc, const int* nc, int ngc, double* up, long sfp, const int* np, int ngp,
+                const int* F, int nthreads)
+{
+    grid gp, gc;
+    if (!uc || !up || !np || !nc || !F) return -1;
+    if (make_grid(&gp, sfp, np[0], np[1], np[2], ngp, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0, BC_COPY)) return -1;
+    if (make_grid(&gc, sfc, nc[0], nc[1], nc[2], ngc, 0.5, 0.5, 0.5, 0.0, 0.0, 0.0, BC_COPY)) return -1;
+    for (int d = 0; d < 3; ++d)
+        if (nc[d] % 2 || F[d] < 0 || F[d] + nc[d] / 2 > np[d]) return -1;
+    restrict_to_parent(&gc, uc, &gp, up, F, nthreads < 1 ? 1 : nthreads);
+    return 0;
+}
+
+/* the weights themselves, for the pins */
+int oz_transfer_weights(double theta, int quadratic, double* wt3, double* prolong_even6, double* prolong_odd6,
+                        double* restrict4)
+{
+    static const double nodes[4] = {-1.5, -0.5, 0.5, 1.5};
+    time_weights(theta, quadratic, wt3);
+    prolong_1d(0, 0, prolong_even6);
+    prolong_1d(1, 0, prolong_odd6);
+    lagrange_weights(nodes, 4, 0.0, restrict4);
     return 0;
 }

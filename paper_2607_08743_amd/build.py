@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libz4c.so")
-SOURCES = [os.path.join(CSRC, "z4c_kernels.hip"), os.path.join(CSRC, "z4c_api.hip")]
+SOURCES = [os.path.join(CSRC, "z4c_kernels.hip"), os.path.join(CSRC, "z4c_constraints.hip"),
+           os.path.join(CSRC, "z4c_api.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -93,7 +93,7 @@ int check_geom(long sf, int nx, int ny, int nz, int ng, int bc, long* stored)
 {
     if (nx < 1 || ny < 1 || nz < 1) return fail(Z4C_EINVAL, "active extents must be >= 1");
     if (ng < 3) return fail(Z4C_EINVAL, "ghost width ng must be >= 3 (stencil reach)");
-    if (bc < Z4C_BC_PERIODIC || bc > Z4C_BC_COPY) return fail(Z4C_EINVAL, "unknown boundary kind");
+    if (bc < Z4C_BC_PERIODIC || bc > Z4C_BC_EQUATORIAL) return fail(Z4C_EINVAL, "unknown boundary kind");
     const long Nx = (long)nx + 2L * ng, Ny = (long)ny + 2L * ng, Nz = (long)nz + 2L * ng;
     if (Nx > (1L << 20) || Ny > (1L << 20) || Nz > (1L << 20)) return fail(Z4C_EINVAL, "extent too large");
     const long n = Nx * Ny * Nz;
@@ -302,7 +302,8 @@ int rk4_substep(int stage, double dt, const double* u_in, const double* u_n, dou
     if (e != hipSuccess) return hip_fail(e, "pending HIP error before rk4_substep");
     if ((e = tab[ti].launch(set, pd, MODE_STAGE, stage, pers, s)) != hipSuccess)
         return hip_fail(e, "rk4_substep fused launch");
-    if (bc == Z4C_BC_SOMMERFELD && (e = launch_sommerfeld(set, pd, MODE_STAGE, stage, s)) != hipSuccess)
+    if ((bc == Z4C_BC_SOMMERFELD || bc == Z4C_BC_EQUATORIAL) &&
+        (e = launch_sommerfeld(set, pd, MODE_STAGE, stage, s)) != hipSuccess)
         return hip_fail(e, "rk4_substep Sommerfeld launch");
     return Z4C_OK;
 }
@@ -334,6 +335,46 @@ int apply_ghosts(double* u, const double* shell, long sf, int nx, int ny, int nz
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pending HIP error before apply_ghosts");
     if ((e = launch_ghosts(set, (hipStream_t)stream)) != hipSuccess) return hip_fail(e, "apply_ghosts launch");
+    return Z4C_OK;
+}
+
+long z4c_constraints_workspace(int nx, int ny, int nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    const int n[3] = {nx, ny, nz};
+    return 4 * constraint_blocks(n);
+}
+
+int z4c_constraints(const double* u, double* c, double* norms, double* ws, long ws_len, long sf, int nx, int ny,
+                    int nz, int ng, double dx, double dy, double dz, void* stream)
+{
+    long stored = 0;
+    int rc;
+    if ((rc = check_geom(sf, nx, ny, nz, ng, Z4C_BC_PERIODIC, &stored)) ||
+        (rc = check_spacing(dx, dy, dz, 0.0, 0.0, 0.0)))
+        return rc;
+    if (!u || !norms || !ws) return fail(Z4C_EINVAL, "u, norms and ws must be non-NULL");
+    const long need = z4c_constraints_workspace(nx, ny, nz);
+    if (ws_len < need) return fail(Z4C_EINVAL, "workspace too small: need " + std::to_string(need) + " doubles");
+    auto span = [](const void* p, uintptr_t bytes, const void* q, uintptr_t qbytes) {
+        const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+        return a < b + qbytes && b < a + bytes;
+    };
+    const uintptr_t ub = (uintptr_t)sf * NF * 8, cb = (uintptr_t)sf * 4 * 8, wb = (uintptr_t)need * 8;
+    if (c && span(c, cb, u, ub)) return fail(Z4C_EINVAL, "c overlaps u");
+    if (span(ws, wb, u, ub) || (c && span(ws, wb, c, cb)) || span(ws, wb, norms, 32))
+        return fail(Z4C_EINVAL, "ws overlaps another argument");
+    if (span(norms, 32, u, ub) || (c && span(norms, 32, c, cb))) return fail(Z4C_EINVAL, "norms overlaps another argument");
+    const int n[3] = {nx, ny, nz};
+    const double h[3] = {dx, dy, dz}, o[3] = {0, 0, 0};
+    BoxSet set{};
+    set.nbox = 1;
+    set.box[0] = make_box(n, ng, Z4C_BC_PERIODIC, sf, h, o, 1.0);
+    set.box[0].u_in = u;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending HIP error before z4c_constraints");
+    if ((e = launch_constraints(set, c, norms, ws, (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "z4c_constraints launch");
     return Z4C_OK;
 }
 
@@ -442,7 +483,7 @@ int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z
     P->any_ghost_fill = P->any_sommerfeld = false;
     for (const z4c_box& x : P->boxes) {
         P->any_ghost_fill |= x.bc != Z4C_BC_SOMMERFELD;
-        P->any_sommerfeld |= x.bc == Z4C_BC_SOMMERFELD;
+        P->any_sommerfeld |= x.bc == Z4C_BC_SOMMERFELD || x.bc == Z4C_BC_EQUATORIAL;
     }
     P->graph = nullptr;
     P->exec = nullptr;

@@ -1,0 +1,304 @@
+// z4c_constraints.hip -- constraint monitor: Hamiltonian and momentum
+// constraints of the vacuum 3+1 system on every active point, and their
+// volume-normalised L2 norms (paper Sec. 2.3), with a reduction whose order is
+// fixed by the launch shape (bitwise reproducible run to run).
+//
+//   H   = R - At_ij At^ij + (2/3) K^2,              K = Khat + 2 Theta
+//   M^i = W^2 [ Dt_j At^ij - 3 At^ij d_j W / W - (2/3) gt^ij d_j K ]
+// with R built exactly as in the right-hand side (evolved Gt in its d Gt
+// term), Dt the covariant derivative of gt, and
+//   d_j At^ij = gt^ia gt^jb d_j At_ab + At_ab d_j(gt^ia gt^jb),
+//   d_j gt^ia = -gt^ic gt^ad d_j gt_cd.
+// The derivative stencils are the 4th-order centred ones of the evolution.
+#include <hip/hip_runtime.h>
+
+#include "z4c_internal.h"
+
+namespace z4c {
+
+namespace {
+
+constexpr int CX = 8, CY = 8, CZ = 4;  // brick of one block (one point per thread)
+constexpr int CNT = CX * CY * CZ;
+constexpr int CSX = CX + 4, CSY = CY + 4, CSXY = CSX * CSY, CTN = CSXY * (CZ + 4);  // halo 2
+
+__device__ __forceinline__ int sidx(int a, int b)
+{
+    return (a < b ? a : b) * (5 - (a < b ? a : b)) / 2 + (a < b ? b : a);
+}
+
+__device__ __forceinline__ void keep(double& x) { __asm__ volatile("" : "+v"(x)); }
+
+__device__ __forceinline__ double cd1(const double* t, int st, double i12h)
+{
+    return (8.0 * (t[st] - t[-st]) - (t[2 * st] - t[-2 * st])) * i12h;
+}
+
+__device__ __forceinline__ double cd2(const double* t, int st, double i12h2)
+{
+    const double c = t[0];
+    return (16.0 * ((t[st] - c) + (t[-st] - c)) - ((t[2 * st] - c) + (t[-2 * st] - c))) * i12h2;
+}
+
+__device__ __forceinline__ double cmix(const double* t, int sa, int sb, double scale)
+{
+    auto g = [&](int o) { return 8.0 * (t[o + sb] - t[o - sb]) - (t[o + 2 * sb] - t[o - 2 * sb]); };
+    return (8.0 * (g(sa) - g(-sa)) - (g(2 * sa) - g(-2 * sa))) * scale;
+}
+
+__global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))) constraints_kernel(BoxSet set, double* c_out, double* partial)
+{
+    __shared__ double tile[CTN];
+    __shared__ double red[4][CNT];
+    const BoxDev& B = set.box[0];
+    const int tid = threadIdx.x;
+    const int tx = tid % CX, ty = (tid / CX) % CY, tz = tid / (CX * CY);
+    const long w = blockIdx.x;
+    const int bxi = (int)(w % B.nb[0]), byi = (int)((w / B.nb[0]) % B.nb[1]), bzi = (int)(w / ((long)B.nb[0] * B.nb[1]));
+    const int ng = B.ng;
+    const int Nx = B.n[0] + 2 * ng, Ny = B.n[1] + 2 * ng, Nz = B.n[2] + 2 * ng;
+    const int i0 = bxi * CX, j0 = byi * CY, k0 = bzi * CZ;
+    const bool valid = (i0 + tx < B.n[0]) && (j0 + ty < B.n[1]) && (k0 + tz < B.n[2]);
+    const size_t sf = (size_t)B.sf;
+    const size_t p = ((size_t)(k0 + tz + ng) * Ny + (j0 + ty + ng)) * Nx + (i0 + tx + ng);
+    const int gx0 = i0 + ng - 2, gy0 = j0 + ng - 2, gz0 = k0 + ng - 2;
+    const double* t = tile + (tz + 2) * CSXY + (ty + 2) * CSX + (tx + 2);
+
+    double i12h[3], i12h2[3];
+    for (int d = 0; d < 3; ++d) {
+        i12h[d] = 1.0 / (12.0 * B.h[d]);
+        i12h2[d] = 1.0 / (12.0 * B.h[d] * B.h[d]);
+    }
+    const double imix[3] = {1.0 / (144.0 * B.h[0] * B.h[1]), 1.0 / (144.0 * B.h[0] * B.h[2]),
+                            1.0 / (144.0 * B.h[1] * B.h[2])};
+
+    auto stage = [&](int f) {
+        __syncthreads();
+        const double* src = B.u_in + f * sf;
+        for (int e = tid; e < CTN; e += CNT) {
+            const int lx = e % CSX, ly = (e / CSX) % CSY, lz = e / CSXY;
+            const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
+            tile[e] = (gi < Nx && gj < Ny && gk < Nz) ? src[((size_t)gk * Ny + gj) * Nx + gi] : 0.0;
+        }
+        __syncthreads();
+    };
+    auto grad = [&](double* d) {
+        d[0] = cd1(t, 1, i12h[0]);
+        d[1] = cd1(t, CSX, i12h[1]);
+        d[2] = cd1(t, CSXY, i12h[2]);
+        for (int c = 0; c < 3; ++c) keep(d[c]);
+    };
+    auto hess = [&](double* dd) {
+        dd[0] = cd2(t, 1, i12h2[0]);
+        dd[3] = cd2(t, CSX, i12h2[1]);
+        dd[5] = cd2(t, CSXY, i12h2[2]);
+        dd[1] = cmix(t, 1, CSX, imix[0]);
+        dd[2] = cmix(t, 1, CSXY, imix[1]);
+        dd[4] = cmix(t, CSX, CSXY, imix[2]);
+        for (int q = 0; q < 6; ++q) keep(dd[q]);
+    };
+    auto tr6 = [](const double* g, const double* x) {
+        return g[0] * x[0] + g[3] * x[3] + g[5] * x[5] + 2.0 * (g[1] * x[1] + g[2] * x[2] + g[4] * x[4]);
+    };
+
+    double gt[6], gu[6], dgt[6][3], Rt[6];
+    // conformal metric
+    for (int q = 0; q < 6; ++q) {
+        stage(F_GT + q);
+        gt[q] = t[0];
+        keep(gt[q]);
+    }
+    {
+        const double det = gt[0] * (gt[3] * gt[5] - gt[4] * gt[4]) - gt[1] * (gt[1] * gt[5] - gt[4] * gt[2])
+                         + gt[2] * (gt[1] * gt[4] - gt[3] * gt[2]);
+        const double id = valid ? 1.0 / det : 1.0;
+        gu[0] = (gt[3] * gt[5] - gt[4] * gt[4]) * id;
+        gu[1] = (gt[2] * gt[4] - gt[1] * gt[5]) * id;
+        gu[2] = (gt[1] * gt[4] - gt[2] * gt[3]) * id;
+        gu[3] = (gt[0] * gt[5] - gt[2] * gt[2]) * id;
+        gu[4] = (gt[2] * gt[1] - gt[0] * gt[4]) * id;
+        gu[5] = (gt[0] * gt[3] - gt[1] * gt[1]) * id;
+    }
+    for (int q = 0; q < 6; ++q) {
+        stage(F_GT + q);
+        grad(dgt[q]);
+        double dd[6];
+        hess(dd);
+        Rt[q] = -0.5 * tr6(gu, dd);
+        keep(Rt[q]);
+    }
+    double C1[3][6], C2[3][6], Gtd[3];
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j)
+                C1[k][sidx(i, j)] = 0.5 * (dgt[sidx(k, j)][i] + dgt[sidx(k, i)][j] - dgt[sidx(i, j)][k]);
+    for (int k = 0; k < 3; ++k)
+        for (int q = 0; q < 6; ++q)
+            C2[k][q] = gu[sidx(k, 0)] * C1[0][q] + gu[sidx(k, 1)] * C1[1][q] + gu[sidx(k, 2)] * C1[2][q];
+    for (int k = 0; k < 3; ++k) Gtd[k] = tr6(gu, C2[k]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                s += 0.5 * Gtd[k] * (C1[i][sidx(j, k)] + C1[j][sidx(i, k)]);
+                for (int l = 0; l < 3; ++l)
+                    for (int m = 0; m < 3; ++m)
+                        s += gu[sidx(l, m)] * (C2[k][sidx(l, i)] * C1[j][sidx(k, m)]
+                                               + C2[k][sidx(l, j)] * C1[i][sidx(k, m)]
+                                               + C2[k][sidx(i, m)] * C1[k][sidx(l, j)]);
+            }
+            Rt[sidx(i, j)] += s;
+        }
+    // evolved Gt in the Ricci tensor
+    for (int a = 0; a < 3; ++a) {
+        stage(F_GAM + a);
+        double d[3];
+        grad(d);
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j) Rt[sidx(i, j)] += 0.5 * (gt[sidx(a, i)] * d[j] + gt[sidx(a, j)] * d[i]);
+        for (int q = 0; q < 6; ++q) keep(Rt[q]);
+    }
+    // conformal factor
+    double W, dW[3], DDW[6];
+    stage(F_W);
+    W = t[0];
+    grad(dW);
+    hess(DDW);
+    for (int q = 0; q < 6; ++q) {
+        DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
+        keep(DDW[q]);
+    }
+    // trace of the extrinsic curvature
+    double K, dK[3];
+    stage(F_KH);
+    K = t[0];
+    grad(dK);
+    stage(F_TH);
+    K += 2.0 * t[0];
+    {
+        double d[3];
+        grad(d);
+        for (int c = 0; c < 3; ++c) {
+            dK[c] += 2.0 * d[c];
+            keep(dK[c]);
+        }
+    }
+    // traceless curvature
+    double At[6], dAt[6][3];
+    for (int q = 0; q < 6; ++q) {
+        stage(F_AT + q);
+        At[q] = t[0];
+        grad(dAt[q]);
+    }
+
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        const double trDDW = tr6(gu, DDW);
+        double dW2 = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) dW2 += gu[sidx(i, j)] * dW[i] * dW[j];
+        double W2R[6];
+        for (int q = 0; q < 6; ++q) W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - 2.0 * gt[q] * dW2;
+        const double R = tr6(gu, W2R);
+        double Auu[6];
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b2 = 0; b2 < 3; ++b2) s += gu[sidx(i, a)] * gu[sidx(j, b2)] * At[sidx(a, b2)];
+                Auu[sidx(i, j)] = s;
+            }
+        const double AA = tr6(Auu, At);
+        c[0] = R - AA + 2.0 * K * K / 3.0;
+        // d_j gt^ab = -gt^ac gt^bd d_j gt_cd
+        double dgu[3][6];
+        for (int j = 0; j < 3; ++j)
+            for (int a = 0; a < 3; ++a)
+                for (int b2 = a; b2 < 3; ++b2) {
+                    double s = 0.0;
+                    for (int cc = 0; cc < 3; ++cc)
+                        for (int d = 0; d < 3; ++d) s += gu[sidx(a, cc)] * gu[sidx(b2, d)] * dgt[sidx(cc, d)][j];
+                    dgu[j][sidx(a, b2)] = -s;
+                }
+        double trG[3];  // Gamma^j_jk
+        for (int k = 0; k < 3; ++k) trG[k] = C2[0][sidx(0, k)] + C2[1][sidx(1, k)] + C2[2][sidx(2, k)];
+        for (int a = 0; a < 3; ++a) {
+            double div = 0.0, chr = 0.0, aw = 0.0, gk = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int d = 0; d < 3; ++d)
+                        div += gu[sidx(a, cc)] * gu[sidx(j, d)] * dAt[sidx(cc, d)][j]
+                             + At[sidx(cc, d)] * (dgu[j][sidx(a, cc)] * gu[sidx(j, d)]
+                                                  + gu[sidx(a, cc)] * dgu[j][sidx(j, d)]);
+                for (int k = 0; k < 3; ++k) chr += C2[a][sidx(j, k)] * Auu[sidx(j, k)];
+                chr += trG[j] * Auu[sidx(a, j)];
+                aw += Auu[sidx(a, j)] * dW[j];
+                gk += gu[sidx(a, j)] * dK[j];
+            }
+            c[1 + a] = W * W * (div + chr - 3.0 * aw / W - 2.0 * gk / 3.0);
+        }
+        if (c_out)
+            for (int m = 0; m < 4; ++m) c_out[m * sf + p] = c[m];
+    }
+    // fixed-order block reduction of C^2
+    for (int m = 0; m < 4; ++m) red[m][tid] = c[m] * c[m];
+    __syncthreads();
+    for (int s = CNT / 2; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + s];
+        __syncthreads();
+    }
+    if (tid < 4) partial[w * 4 + tid] = red[tid][0];
+}
+
+// one block: fixed-order sum of the block partials, then the norms
+__global__ void __launch_bounds__(256) constraint_norms(const double* partial, long nblocks, double inv_cells,
+                                                        double* norms)
+{
+    __shared__ double red[4][256];
+    const int tid = threadIdx.x;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long b = tid; b < nblocks; b += 256)
+        for (int m = 0; m < 4; ++m) s[m] += partial[b * 4 + m];
+    for (int m = 0; m < 4; ++m) red[m][tid] = s[m];
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (tid < k)
+            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + k];
+        __syncthreads();
+    }
+    if (tid < 4) norms[tid] = sqrt(red[tid][0] * inv_cells);
+}
+
+__global__ void __launch_bounds__(256) zero_fill(double* x, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+}  // namespace
+
+long constraint_blocks(const int n[3])
+{
+    return (long)((n[0] + CX - 1) / CX) * ((n[1] + CY - 1) / CY) * ((n[2] + CZ - 1) / CZ);
+}
+
+hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, double* workspace, hipStream_t s)
+{
+    BoxSet one = set;
+    BoxDev& B = one.box[0];
+    B.nb[0] = (B.n[0] + CX - 1) / CX;
+    B.nb[1] = (B.n[1] + CY - 1) / CY;
+    B.nb[2] = (B.n[2] + CZ - 1) / CZ;
+    const long nb = constraint_blocks(B.n);
+    if (c_out) {
+        const long n = 4 * B.sf;
+        hipLaunchKernelGGL(zero_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c_out, n);
+    }
+    hipLaunchKernelGGL(constraints_kernel, dim3((unsigned)nb), dim3(CNT), 0, s, one, c_out, workspace);
+    const double cells = (double)B.n[0] * B.n[1] * B.n[2];
+    hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(256), 0, s, workspace, nb, 1.0 / cells, norms);
+    return hipGetLastError();
+}
+
+}  // namespace z4c

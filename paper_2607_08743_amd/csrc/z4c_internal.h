@@ -72,4 +72,9 @@ int tile_table(const TileEntry** out);  // returns the number of entries
 hipError_t launch_ghosts(const BoxSet& set, hipStream_t s);                  // periodic / copy fill
 hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, int stage, hipStream_t s);
 
+// constraint monitor (single box): per-point values (c may be NULL), block
+// partial sums of C^2 into ws, then the four L2 norms into norms
+long constraint_blocks(const int n[3]);
+hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, double* ws, hipStream_t s);
+
 }  // namespace z4c

@@ -128,6 +128,19 @@ __device__ __forceinline__ R ko6(const Pairs<R>& q)
     return (q.a3 - R(6) * q.a2) + R(15) * q.a1;
 }
 
+// A value known to be the same on every lane, moved to scalar registers.
+__device__ __forceinline__ float uniform(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // per-box derivative factors in the arithmetic type
 template <typename R>
 struct Factors {
@@ -195,6 +208,9 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     double gt[6], At[6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
+        // a few fields at a time: the loads of all 25 hoisted to the top
+        // would hold ~100 registers at once
+        if (f % 5 == 0) __asm__ volatile("" ::: "memory");
         const double k = kf(f);
         double v;
         if (stage == 1) {
@@ -252,17 +268,28 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     // the same NR rounds, so the tile is padded to NR * NT pairs.
     constexpr int NR = (TN / 2 + NT - 1) / NT;
     constexpr int TNP = DMA ? NR * NT * 2 : TN;
-    __shared__ __attribute__((aligned(16))) R tile0[TNP];
-    __shared__ __attribute__((aligned(16))) R tile1[DMA ? TNP : 2];
-    __shared__ __attribute__((aligned(16))) R tile2[DMA ? TNP : 2];
+    __shared__ __attribute__((aligned(16))) R tiles[DMA ? 3 * TNP : TNP];  // 3 buffers (DMA) or 1
     __shared__ R gyt[T::GYN];  // unscaled D1_y of the staged field (x-halo 2)
     __shared__ R gzt[T::GZN];  // unscaled D1_z of the staged field (x- and y-halo 2)
-    auto tilebuf = [&](int k) -> R* { return k == 0 ? tile0 : (k == 1 ? tile1 : tile2); };
+    // Per-thread slots for values that are produced early and consumed late
+    // (held advection terms, completed right-hand sides): parked in LDS
+    // they take no registers across the staging sequence.  Slot s of thread
+    // tid is park[s * NT + tid] (consecutive lanes, consecutive words).
+    constexpr int NPARK = 16;
+    __shared__ __attribute__((aligned(16))) R park[NPARK * NT];
+    // Buffer k of the tile.  The offset is made opaque to the compiler, so
+    // that it adds it to the per-lane offsets when used instead of keeping
+    // one precomputed address per buffer and lane offset live in registers.
+    auto tilebuf = [&](int k) -> R* {
+        int o = k * TNP;
+        __asm__ volatile("" : "+s"(o));
+        return tiles + o;
+    };
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
     const int cofs = (tz + 3) * SXY + (ty + 3) * SX + (tx + 3);
-    const R* tb = tile0;  // tile of the staged field
+    const R* tb = tiles;  // tile of the staged field
     const R* t = tb + cofs;
     constexpr int PX = T::PX;
     const R* ty_c = gyt + (tz * BY + ty) * PX + (tx + 2);        // own slot in the D1_y plane
@@ -319,17 +346,18 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // tile origin in stored coordinates (>= 0 because ng >= 3)
         const int gx0 = i0 + ng - 3, gy0 = j0 + ng - 3, gz0 = k0 + ng - 3;
 
+        // the factors are the same on every lane: keep them in scalar registers
         Factors<R> fc;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            fc.i12h[d] = R(1.0 / (12.0 * B.h[d]));
-            fc.i12h2[d] = R(1.0 / (12.0 * B.h[d] * B.h[d]));
-            fc.ko[d] = R(prm.ko_sigma / (64.0 * B.h[d]));
-            fc.i24h[d] = R(1.0 / (24.0 * B.h[d]));
+            fc.i12h[d] = uniform(R(1.0 / (12.0 * B.h[d])));
+            fc.i12h2[d] = uniform(R(1.0 / (12.0 * B.h[d] * B.h[d])));
+            fc.ko[d] = uniform(R(prm.ko_sigma / (64.0 * B.h[d])));
+            fc.i24h[d] = uniform(R(1.0 / (24.0 * B.h[d])));
         }
-        fc.imix[0] = R(1.0 / (144.0 * B.h[0] * B.h[1]));
-        fc.imix[1] = R(1.0 / (144.0 * B.h[0] * B.h[2]));
-        fc.imix[2] = R(1.0 / (144.0 * B.h[1] * B.h[2]));
+        fc.imix[0] = uniform(R(1.0 / (144.0 * B.h[0] * B.h[1])));
+        fc.imix[1] = uniform(R(1.0 / (144.0 * B.h[0] * B.h[2])));
+        fc.imix[2] = uniform(R(1.0 / (144.0 * B.h[1] * B.h[2])));
 
         // centre values needed before staging (the flat state on idle lanes
         // keeps the algebra finite); the others are taken from the tile
@@ -352,11 +380,11 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         auto seq = [](int i) -> int {
             return i < 6 ? F_GT + i
                  : i < 9 ? F_GAM + (i - 6)
-                 : i < 12 ? F_BE + (i - 9)
-                 : i == 12 ? F_W
-                 : i == 13 ? F_AL
-                 : i == 14 ? F_KH
-                 : i == 15 ? F_TH
+                 : i == 9 ? F_W
+                 : i == 10 ? F_AL
+                 : i == 11 ? F_KH
+                 : i == 12 ? F_TH
+                 : i < 16 ? F_BE + (i - 13)
                  : i < 22 ? F_AT + (i - 16)
                  : F_BB + (i - 22);
         };
@@ -509,27 +537,35 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             dd[4] = outer(tz_c, PX) * fc.imix[2];
         };
 
-        R ak[NF];  // advection + dissipation per field
+        // The right-hand side of each field is completed as soon as its inputs
+        // exist, and every derivative block is folded into the terms it feeds
+        // right after its field is staged, so that few values stay live across
+        // the staging sequence (this decides how many waves a SIMD can hold).
+        // Staging order: gt, Gt, W, alpha, Khat, Theta, beta, At, B.
+        double k[NF];  // completed right-hand sides, stored by finish_point
+        enum : int { P_AKGT = 0, P_AKGAM = 6, P_AKBE = 9, P_KKH = 12, P_KTH = 13, P_KAL = 14, P_KW = 15 };
+        auto put_lds = [&](int slot, R v) { park[slot * NT + tid] = v; };
+        auto get_lds = [&](int slot) { return park[slot * NT + tid]; };
 
         // --- conformal metric: first derivatives kept, second derivatives
         //     folded into -1/2 gt^lm d_l d_m gt_ij
-        R dgt[6][3], Rt[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            stage_field(q);
-            d1_planes();
-            const P3 pq = field_pairs();
-            ak[F_GT + q] = advko(pq);
-            R dd[6];
-            grad_hess(pq, dgt[q], dd);
-            Rt[q] = R(-0.5) * tr6(gu, dd);
-            pin(dgt[q]);
-            pin(Rt[q]);
-        }
-
-        // Christoffel symbols: first kind C1[k][ij] = Gamma_kij, second kind C2[k][ij]
+        R Rt[6];
         R C2[3][6], Gtd[3];
         {
+            R dgt[6][3];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                stage_field(q);
+                d1_planes();
+                const P3 pq = field_pairs();
+                put_lds(P_AKGT + q, advko(pq));
+                R dd[6];
+                grad_hess(pq, dgt[q], dd);
+                Rt[q] = R(-0.5) * tr6(gu, dd);
+                pin(dgt[q]);
+                pin(Rt[q]);
+            }
+            // Christoffel symbols: first kind C1[k][ij] = Gamma_kij, second kind C2[k][ij]
             R C1[3][6];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -580,199 +616,241 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             pin(Gtd);
         }
 
+        // --- At at the point (its stencils are staged near the end): At^ij,
+        //     At_ij At^ij and Gamma^a_jk At^jk now, so that C2 dies with the
+        //     lapse below
+        R At[6], Auu[6], AA, nG[3];  // nG: Gt source without advection/dissipation
+        {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) At[q] = centre(F_AT + q);
+            R Au[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Au[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] + gu[S(i, 2)] * At[S(2, j)];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j)
+                    Auu[S(i, j)] = Au[i][0] * gu[S(0, j)] + Au[i][1] * gu[S(1, j)] + Au[i][2] * gu[S(2, j)];
+            AA = tr6(Auu, At);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nG[a] = tr6(C2[a], Auu);  // scaled by 2 alpha below
+            pin(At);
+            pin(Auu);
+            pin(AA);
+            pin(nG);
+        }
+
         // --- evolved Gt: Rt_ij += 1/2 (gt_ki d_j Gt^k + gt_kj d_i Gt^k)
-        R Gam[3];
+        R Zu[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             stage_field(6 + a);
-            Gam[a] = tval(F_GAM + a);
+            const R Gam = tval(F_GAM + a);
             const P3 pq = field_pairs();
-            ak[F_GAM + a] = advko(pq);
+            put_lds(P_AKGAM + a, advko(pq));
             R d[3];
             grad(pq, d);
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = i; j < 3; ++j) Rt[S(i, j)] += R(0.5) * (gt[S(a, i)] * d[j] + gt[S(a, j)] * d[i]);
+            Zu[a] = R(0.5) * (Gam - Gtd[a]);
             pin(Rt);
+            pin(Zu[a]);
         }
 
-        // --- shift: first derivatives kept (dbe[comp][dir]); second derivatives
-        //     folded into gt^jk d_j d_k beta^i and d_j (d_k beta^k)
-        R dbe[3][3], lapb[3], gdivb[3] = {R(0), R(0), R(0)};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            stage_field(9 + a);
-            d1_planes();
-            const P3 pq = field_pairs();
-            ak[F_BE + a] = advko(pq);
-            R dd[6];
-            grad_hess(pq, dbe[a], dd);
-            lapb[a] = tr6(gu, dd);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) gdivb[j] += dd[S(j, a)];
-            pin(dbe[a]);
-            pin(lapb[a]);
-            pin(gdivb);
-        }
-
-        // --- conformal factor: DDW_ij = d_i d_j W - Gamma^k_ij d_k W
-        R dW[3], DDW[6], W;
+        // --- conformal factor: DDW_ij = d_i d_j W - Gamma^k_ij d_k W, folded
+        //     into W^2 R_ij (no division by W)
+        R W, dW[3], W2R[6], ak_w;
         {
-            stage_field(12);
+            stage_field(9);
             d1_planes();
             W = tval(F_W);
             const P3 pq = field_pairs();
-            ak[F_W] = advko(pq);
+            ak_w = advko(pq);
+            R DDW[6];
             grad_hess(pq, dW, DDW);
 #pragma unroll
             for (int q = 0; q < 6; ++q) DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
+            const R trDDW = tr6(gu, DDW);
+            R dW2 = R(0);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dW2 += gu[S(i, j)] * dW[i] * dW[j];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - R(2) * gt[q] * dW2;
             pin(dW);
-            pin(DDW);
+            pin(W2R);
         }
-        // --- lapse: DDa_ij = d_i d_j alpha - Gamma^k_ij d_k alpha
-        R da[3], DDa[6], al;
+        // --- lapse: DDa_ij = d_i d_j alpha - Gamma^k_ij d_k alpha, folded into
+        //     W^2 D_i D_j alpha and the trace-free source X_ij of At
+        R al, ak_al, Ric, Lapa, Xtf[6];
         {
-            stage_field(13);
+            stage_field(10);
             d1_planes();
             al = tval(F_AL);
             const P3 pq = field_pairs();
-            ak[F_AL] = advko(pq);
+            ak_al = advko(pq);
+            R da[3], DDa[6];
             grad_hess(pq, da, DDa);
 #pragma unroll
             for (int q = 0; q < 6; ++q) DDa[q] -= C2[0][q] * da[0] + C2[1][q] * da[1] + C2[2][q] * da[2];
-            pin(da);
-            pin(DDa);
+            R dWda = R(0);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dWda += gu[S(i, j)] * dW[i] * da[j];
+            R W2DDa[6];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j) {
+                    const int q = S(i, j);
+                    W2DDa[q] = W * W * DDa[q] + W * (dW[i] * da[j] + dW[j] * da[i] - gt[q] * dWda);
+                }
+            Ric = tr6(gu, W2R);
+            Lapa = tr6(gu, W2DDa);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Xtf[q] = -W2DDa[q] + al * W2R[q];
+            const R trX = tr6(gu, Xtf) * R(1.0 / 3.0);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Xtf[q] -= gt[q] * trX;
+            const R iW = R(1) / (W > R(prm.w_floor) ? W : R(prm.w_floor));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R t_ada = R(0), t_aw = R(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    t_ada += Auu[S(a, c)] * da[c];
+                    t_aw += Auu[S(a, c)] * dW[c];
+                }
+                nG[a] = R(-2) * t_ada + R(2) * al * nG[a] - R(6) * al * t_aw * iW;
+            }
+            pin(Xtf);
+            pin(nG);
+            pin(Ric);
+            pin(Lapa);
         }
         // --- Khat and Theta: only the combination 2 d Khat + d Theta is used
-        R dkt[3], Kh, Th;
+        const R kap1 = R(prm.kappa1), kap3 = R(prm.kappa3);
+        const R th1 = uniform(kap1 * (R(1) - R(prm.kappa2))), th2 = uniform(kap1 * (R(2) + R(prm.kappa2)));
+        R K;
         {
-            stage_field(14);
-            Kh = tval(F_KH);
+            stage_field(11);
+            const R Kh = tval(F_KH);
             const P3 pk = field_pairs();
-            ak[F_KH] = advko(pk);
+            const R ak_kh = advko(pk);
+            R dkt[3];
             grad(pk, dkt);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] *= R(2);
-            stage_field(15);
-            Th = tval(F_TH);
+            pin(dkt);
+            stage_field(12);
+            const R Th = tval(F_TH);
             const P3 pt = field_pairs();
-            ak[F_TH] = advko(pt);
+            const R ak_th = advko(pt);
             R d[3];
             grad(pt, d);
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] += d[j];
-            pin(dkt);
+            K = Kh + R(2) * Th;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R t_dk = gu[S(a, 0)] * dkt[0] + gu[S(a, 1)] * dkt[1] + gu[S(a, 2)] * dkt[2];
+                nG[a] -= R(2.0 / 3.0) * al * t_dk;
+            }
+            put_lds(P_KKH, -Lapa + al * (AA + K * K * R(1.0 / 3.0)) + al * th1 * Th + ak_kh);
+            put_lds(P_KTH, R(0.5) * al * (Ric - AA + R(2.0 / 3.0) * K * K) - al * th2 * Th + ak_th);
+            put_lds(P_KAL, R(-2) * al * (prm.lapse_uses_K ? K : Kh) + ak_al);
+            pin(nG);
         }
+
+        // --- shift: its first derivatives close the gt and At sources, the
+        //     second derivatives the Gt source
+        R kgt[6], kat[6];
+        {
+            R dbe[3][3], lapb[3], gdivb[3] = {R(0), R(0), R(0)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                stage_field(13 + a);
+                d1_planes();
+                const P3 pq = field_pairs();
+                put_lds(P_AKBE + a, advko(pq));
+                R dd[6];
+                grad_hess(pq, dbe[a], dd);
+                lapb[a] = tr6(gu, dd);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) gdivb[j] += dd[S(j, a)];
+                pin(dbe[a]);
+                pin(lapb[a]);
+                pin(gdivb);
+            }
+            const R divb = dbe[0][0] + dbe[1][1] + dbe[2][2];
+            put_lds(P_KW, W * (al * K - divb) * R(1.0 / 3.0) + ak_w);
+            R Au[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Au[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] + gu[S(i, 2)] * At[S(2, j)];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j) {
+                    const int q = S(i, j);
+                    R lg = R(0), la = R(0), aa = R(0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        lg += gt[S(i, c)] * dbe[c][j] + gt[S(j, c)] * dbe[c][i];
+                        la += At[S(i, c)] * dbe[c][j] + At[S(j, c)] * dbe[c][i];
+                        aa += At[S(i, c)] * Au[c][j];
+                    }
+                    kgt[q] = R(-2) * al * At[q] + lg - R(2.0 / 3.0) * gt[q] * divb + get_lds(P_AKGT + q);
+                    kat[q] = Xtf[q] + al * (K * At[q] - R(2) * aa) + la - R(2.0 / 3.0) * At[q] * divb;
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R t_gdb = R(0), t_zdb = R(0), t_dd2 = R(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    t_gdb += Gtd[c] * dbe[a][c];
+                    t_zdb += Zu[c] * dbe[a][c];
+                    t_dd2 += gu[S(a, c)] * gdivb[c];
+                }
+                nG[a] += lapb[a] + t_dd2 * R(1.0 / 3.0) + R(2.0 / 3.0) * Gtd[a] * divb - t_gdb
+                       - R(2) * al * kap1 * Zu[a] + R(2) * kap3 * (R(2.0 / 3.0) * Zu[a] * divb - t_zdb);
+            }
+            pin(kgt);
+            pin(kat);
+            pin(nG);
+        }
+
         // --- traceless curvature and B: advection and dissipation only
-        R At[6], Bv[3];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             stage_field(16 + q);
-            At[q] = tval(F_AT + q);
-            ak[F_AT + q] = advko(field_pairs());
+            k[F_GT + q] = double(kgt[q]);
+            k[F_AT + q] = double(kat[q] + advko(field_pairs()));
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             stage_field(22 + a);
-            Bv[a] = tval(F_BB + a);
-            ak[F_BB + a] = advko(field_pairs());
+            const R Bc = tval(F_BB + a);
+            const R ak_bb = advko(field_pairs());
+            k[F_GAM + a] = double(nG[a] + get_lds(P_AKGAM + a));
+            k[F_BE + a] = double(R(prm.shift_coeff) * Bc + get_lds(P_AKBE + a));
+            k[F_BB + a] = double(nG[a] - R(prm.eta) * Bc + ak_bb);
         }
+        k[F_KH] = double(get_lds(P_KKH));
+        k[F_TH] = double(get_lds(P_KTH));
+        k[F_AL] = double(get_lds(P_KAL));
+        k[F_W] = double(get_lds(P_KW));
 
         if (!valid) continue;  // no barrier below this point
-
-        // --- pointwise algebra
-        const R K = Kh + R(2) * Th;
-        const R divb = dbe[0][0] + dbe[1][1] + dbe[2][2];
-        R Zu[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Zu[a] = R(0.5) * (Gam[a] - Gtd[a]);
-
-        R Au[3][3], Auu[6];  // At^i_j, At^ij
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Au[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] + gu[S(i, 2)] * At[S(2, j)];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j)
-                Auu[S(i, j)] = Au[i][0] * gu[S(0, j)] + Au[i][1] * gu[S(1, j)] + Au[i][2] * gu[S(2, j)];
-        const R AA = tr6(Auu, At);
-
-        // W^2 R_ij (no division by W) and R
-        const R trDDW = tr6(gu, DDW);
-        R dW2 = R(0), dWda = R(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                dW2 += gu[S(i, j)] * dW[i] * dW[j];
-                dWda += gu[S(i, j)] * dW[i] * da[j];
-            }
-        R W2R[6], W2DDa[6];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                const int q = S(i, j);
-                W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - R(2) * gt[q] * dW2;
-                W2DDa[q] = W * W * DDa[q] + W * (dW[i] * da[j] + dW[j] * da[i] - gt[q] * dWda);
-            }
-        const R Ric = tr6(gu, W2R);
-        const R Lapa = tr6(gu, W2DDa);
-        R X[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) X[q] = -W2DDa[q] + al * W2R[q];
-        const R trX = tr6(gu, X) * R(1.0 / 3.0);
-
-        double k[NF];
-        k[F_W] = double(W * (al * K - divb) * R(1.0 / 3.0) + ak[F_W]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                const int q = S(i, j);
-                R lg = R(0), la = R(0), aa = R(0);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    lg += gt[S(i, c)] * dbe[c][j] + gt[S(j, c)] * dbe[c][i];
-                    la += At[S(i, c)] * dbe[c][j] + At[S(j, c)] * dbe[c][i];
-                    aa += At[S(i, c)] * Au[c][j];
-                }
-                k[F_GT + q] = double(R(-2) * al * At[q] + lg - R(2.0 / 3.0) * gt[q] * divb + ak[F_GT + q]);
-                k[F_AT + q] = double((X[q] - gt[q] * trX) + al * (K * At[q] - R(2) * aa) + la
-                                     - R(2.0 / 3.0) * At[q] * divb + ak[F_AT + q]);
-            }
-        const R kap1 = R(prm.kappa1), kap2 = R(prm.kappa2), kap3 = R(prm.kappa3);
-        k[F_KH] = double(-Lapa + al * (AA + K * K * R(1.0 / 3.0)) + al * kap1 * (R(1) - kap2) * Th + ak[F_KH]);
-        k[F_TH] = double(R(0.5) * al * (Ric - AA + R(2.0 / 3.0) * K * K) - al * kap1 * (R(2) + kap2) * Th + ak[F_TH]);
-        k[F_AL] = double(R(-2) * al * (prm.lapse_uses_K ? K : Kh) + ak[F_AL]);
-
-        const R iW = R(1) / (W > R(prm.w_floor) ? W : R(prm.w_floor));
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            R t_ada = R(0), t_aw = R(0), t_dk = R(0), t_gdb = R(0), t_zdb = R(0), t_dd2 = R(0), t_chr = R(0);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                t_ada += Auu[S(a, c)] * da[c];
-                t_aw += Auu[S(a, c)] * dW[c];
-                t_dk += gu[S(a, c)] * dkt[c];
-                t_gdb += Gtd[c] * dbe[a][c];
-                t_zdb += Zu[c] * dbe[a][c];
-                t_dd2 += gu[S(a, c)] * gdivb[c];
-            }
-            t_chr = tr6(C2[a], Auu);
-            const R nG = R(-2) * t_ada + R(2) * al * t_chr - R(6) * al * t_aw * iW - R(2.0 / 3.0) * al * t_dk
-                       + lapb[a] + t_dd2 * R(1.0 / 3.0) + R(2.0 / 3.0) * Gtd[a] * divb - t_gdb
-                       - R(2) * al * kap1 * Zu[a] + R(2) * kap3 * (R(2.0 / 3.0) * Zu[a] * divb - t_zdb);
-            const R Bc = Bv[a];
-            k[F_GAM + a] = double(nG + ak[F_GAM + a]);
-            k[F_BE + a] = double(R(prm.shift_coeff) * Bc + ak[F_BE + a]);
-            k[F_BB + a] = double(nG - R(prm.eta) * Bc + ak[F_BB + a]);
-        }
-
         finish_point(B, mode, stage, [&](int f) { return k[f]; }, p);
     }
 }
@@ -883,6 +961,15 @@ __device__ __forceinline__ int find_box(const BoxSet& set, long w)
     return bi;
 }
 
+// sign of field f under the reflection z -> -z: one factor -1 per z index
+__device__ __forceinline__ double z_sign(int f)
+{
+    return (f == F_GT + 2 || f == F_GT + 4 || f == F_AT + 2 || f == F_AT + 4 || f == F_GAM + 2 || f == F_BE + 2 ||
+            f == F_BB + 2)
+               ? -1.0
+               : 1.0;
+}
+
 __global__ void __launch_bounds__(256) ghost_fill(BoxSet set)
 {
     const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -891,13 +978,20 @@ __global__ void __launch_bounds__(256) ghost_fill(BoxSet set)
     const BoxDev& B = set.box[bi];
     if (B.bc == Z4C_BC_SOMMERFELD) return;
     const long q = w - set.shell_begin[bi];
+    const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng;
+    // the shell order starts with the ng layers below the active box
+    if (B.bc == Z4C_BC_EQUATORIAL && q >= (long)B.ng * Nx * Ny) return;
     int i, j, k;
     shell_point(q, B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
-    const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng;
     const size_t p = ((size_t)k * Ny + j) * Nx + i;
     double* u = const_cast<double*>(B.u_in);
     const size_t sf = (size_t)B.sf;
-    if (B.bc == Z4C_BC_PERIODIC) {
+    if (B.bc == Z4C_BC_EQUATORIAL) {
+        // layer ng-1-m below the symmetry plane mirrors layer ng+m above it
+        const size_t src = ((size_t)(2 * B.ng - 1 - k) * Ny + j) * Nx + i;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) u[f * sf + p] = z_sign(f) * u[f * sf + src];
+    } else if (B.bc == Z4C_BC_PERIODIC) {
         const size_t src = ((size_t)wrap(k, B.ng, B.n[2]) * Ny + wrap(j, B.ng, B.n[1])) * Nx + wrap(i, B.ng, B.n[0]);
 #pragma unroll
         for (int f = 0; f < NF; ++f) u[f * sf + p] = u[f * sf + src];
@@ -919,18 +1013,21 @@ __device__ __forceinline__ double dsomm(const double* u, size_t p, int i, int N,
     return s * (-4.0 * (u[p - o] - c) + (u[p - 2 * o] - c)) / (2.0 * h);
 }
 
-// Outgoing-wave update of every ghost point of Sommerfeld boxes:
-// d_t f = -(x^i/r) d_i f - (f - f_flat)/r (paper Sec. 2.2.2), then the same
-// RK4 stage update and enforcement as the interior.
+// Outgoing-wave update of the ghost points of Sommerfeld faces (every ghost
+// of a Sommerfeld box; those at and above the symmetry plane of an
+// equatorial box): d_t f = -(x^i/r) d_i f - (f - f_flat)/r (paper Sec.
+// 2.2.2), then the same RK4 stage update and enforcement as the interior.
 __global__ void __launch_bounds__(256) sommerfeld_ghosts(BoxSet set, int mode, int stage)
 {
     const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= set.shell_begin[set.nbox]) return;
     const int bi = find_box(set, w);
     const BoxDev& B = set.box[bi];
-    if (B.bc != Z4C_BC_SOMMERFELD) return;
+    if (B.bc != Z4C_BC_SOMMERFELD && B.bc != Z4C_BC_EQUATORIAL) return;
+    const long q = w - set.shell_begin[bi];
+    if (B.bc == Z4C_BC_EQUATORIAL && q < (long)B.ng * (B.n[0] + 2 * B.ng) * (B.n[1] + 2 * B.ng)) return;
     int i, j, k;
-    shell_point(w - set.shell_begin[bi], B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
+    shell_point(q, B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
     const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng, Nz = B.n[2] + 2 * B.ng;
     const size_t p = ((size_t)k * Ny + j) * Nx + i;
     const size_t sf = (size_t)B.sf;
@@ -955,9 +1052,11 @@ __global__ void __launch_bounds__(256) zero_ghost_rhs(BoxSet set)
     const int bi = find_box(set, w);
     const BoxDev& B = set.box[bi];
     if (B.bc == Z4C_BC_SOMMERFELD) return;
-    int i, j, k;
-    shell_point(w - set.shell_begin[bi], B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
+    const long q = w - set.shell_begin[bi];
     const int Nx = B.n[0] + 2 * B.ng, Ny = B.n[1] + 2 * B.ng;
+    if (B.bc == Z4C_BC_EQUATORIAL && q >= (long)B.ng * Nx * Ny) return;  // Sommerfeld faces
+    int i, j, k;
+    shell_point(q, B.n[0], B.n[1], B.n[2], B.ng, i, j, k);
     const size_t p = ((size_t)k * Ny + j) * Nx + i;
 #pragma unroll
     for (int f = 0; f < NF; ++f) B.u_out[f * (size_t)B.sf + p] = 0.0;
@@ -993,10 +1092,10 @@ hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, in
 static const TileEntry kTiles[] = {
     Z4C_TILE(double, Z4C_FP64, 8, 8, 4, 1),
     Z4C_TILE(double, Z4C_FP64, 16, 4, 4, 1),
-    Z4C_TILE(double, Z4C_FP64, 8, 4, 4, 2),
     Z4C_TILE(double, Z4C_FP64, 16, 8, 2, 1),
     Z4C_TILE(double, Z4C_FP64, 16, 2, 8, 1),
     Z4C_TILE(double, Z4C_FP64, 8, 4, 8, 1),
+    Z4C_TILE(double, Z4C_FP64, 8, 8, 8, 2),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 16, 4, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 2),

@@ -24,7 +24,7 @@ import numpy as np
 
 NF = 25
 NG = 3
-BC_PERIODIC, BC_SOMMERFELD, BC_COPY = 0, 1, 2
+BC_PERIODIC, BC_SOMMERFELD, BC_COPY, BC_EQUATORIAL = 0, 1, 2, 3
 
 FIELD_NAMES = ["W", "gt_xx", "gt_xy", "gt_xz", "gt_yy", "gt_yz", "gt_zz", "Khat",
                "At_xx", "At_xy", "At_xz", "At_yy", "At_yz", "At_zz", "Gt_x", "Gt_y", "Gt_z",
@@ -37,6 +37,11 @@ FLAT = np.array([1, 1, 0, 0, 1, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 0, 
 # scalars +, vector x/y components -, tensor xz/yz components -
 PI_PARITY = np.array([+1, +1, +1, -1, +1, -1, +1, +1, +1, +1, -1, +1, -1, +1, -1, -1, +1,
                       +1, +1, -1, -1, +1, -1, -1, +1], dtype=np.float64)
+
+
+# sign of each field under the reflection z -> -z: (-1)^(number of z indices)
+Z_PARITY = np.array([+1, +1, +1, -1, +1, -1, +1, +1, +1, +1, -1, +1, -1, +1, +1, +1, -1,
+                     +1, +1, +1, +1, -1, +1, +1, -1], dtype=np.float64)
 
 
 @dataclass
@@ -207,6 +212,29 @@ def config_punctures(n=128, extent=32.0):
     dt = 0.5 h (Courant factor 0.5, paper Sec. 2.2)."""
     g = centered_grid(n, extent / n, bc=BC_SOMMERFELD)
     return g, pi_symmetrize(brill_lindquist_state(g)), 0.5 * g.h[0]
+
+
+def z_symmetrize(u: np.ndarray) -> np.ndarray:
+    """Make a box that is symmetric about z = 0 (stored index k <-> Nz-1-k)
+    exactly reflection-symmetric: the average of u and its parity-signed
+    mirror image."""
+    return 0.5 * (u + u[:, ::-1, :, :] * Z_PARITY[:, None, None, None])
+
+
+def upper_half(u: np.ndarray, ng: int = NG) -> np.ndarray:
+    """Stored points of the z >= 0 half of a z-symmetric box (an even number
+    of active layers) together with ng layers below the plane."""
+    nz = u.shape[1] - 2 * ng
+    return np.ascontiguousarray(u[:, nz // 2:, :, :])
+
+
+def config_punctures_equatorial(n=128, extent=32.0):
+    """The z >= 0 half (n x n x n/2 cells) of the n^3 two-puncture box, with
+    equatorial reflection symmetry at z = 0 and Sommerfeld outer faces: the
+    same physical problem for half the cells (paper Sec. 2.4)."""
+    h = extent / n
+    g = Grid((n, n, n // 2), (h, h, h), (-0.5 * (n - 1) * h, -0.5 * (n - 1) * h, 0.5 * h), BC_EQUATORIAL)
+    return g, pi_symmetrize(brill_lindquist_state(g)), 0.5 * h
 
 
 HIERARCHY_SIZES = (160, 144, 128, 112, 96, 96, 80, 72, 64)

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "z4c.h")
 
 NF = 25
 OK, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4
-BC_PERIODIC, BC_SOMMERFELD, BC_COPY = 0, 1, 2
+BC_PERIODIC, BC_SOMMERFELD, BC_COPY, BC_EQUATORIAL = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 
 
@@ -78,12 +78,15 @@ def lib(path: str = LIB_PATH):
     L.z4c_plan_step.argtypes = [vp, i, i, vp]
     L.z4c_plan_autotune.argtypes = [vp, i, vp, ctypes.POINTER(Tile), ctypes.POINTER(ctypes.c_float)]
     L.z4c_plan_destroy.argtypes = [vp]
+    L.z4c_constraints_workspace.argtypes = [i, i, i]
+    L.z4c_constraints_workspace.restype = l
+    L.z4c_constraints.argtypes = [dp, dp, dp, dp, l, l, i, i, i, i, d, d, d, vp]
     L.z4c_strerror.argtypes = [i]
     L.z4c_strerror.restype = ctypes.c_char_p
     L.z4c_last_error.argtypes = []
     L.z4c_last_error.restype = ctypes.c_char_p
     for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
-                 "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy"):
+                 "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -93,7 +96,7 @@ def header_functions(path: str = HEADER):
     """Names of the functions declared in include/z4c.h."""
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|void|char\s*\*|const char\s*\*)\s*\**\s*(\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|long|void|char\s*\*|const char\s*\*)\s*\**\s*(\w+)\s*\(",
                                  text, flags=re.M)))
 
 
@@ -162,6 +165,32 @@ def apply_ghosts(u, g: _inputs.Grid, shell=None, stream=None):
             raise TypeError("shell must be a contiguous float64 CUDA tensor")
     check(lib().apply_ghosts(_ptr(u), _ptr(shell), ctypes.c_long(g.stored), int(g.n[0]), int(g.n[1]), int(g.n[2]),
                              int(g.ng), int(g.bc), _stream(stream)), "apply_ghosts")
+
+
+def constraints_workspace(g: _inputs.Grid) -> int:
+    """Doubles of device workspace z4c_constraints needs for this box."""
+    return int(lib().z4c_constraints_workspace(int(g.n[0]), int(g.n[1]), int(g.n[2])))
+
+
+def constraints(u, g: _inputs.Grid, c=None, norms=None, ws=None, stream=None):
+    """Hamiltonian and momentum constraints of u (ghosts valid).  c: None or a
+    (4, Nz, Ny, Nx) float64 CUDA tensor that receives H, M^x, M^y, M^z per
+    point.  Returns the (4,) tensor of L2 norms (allocated here unless given,
+    like the workspace)."""
+    import torch
+    _state_tensor(u, g, "u")
+    if c is not None and (c.dtype != torch.float64 or not c.is_cuda or not c.is_contiguous()
+                          or tuple(c.shape) != (4,) + tuple(g.shape[1:])):
+        raise TypeError("c must be a contiguous float64 CUDA tensor of shape (4, Nz, Ny, Nx)")
+    if norms is None:
+        norms = torch.empty(4, dtype=torch.float64, device=u.device)
+    nws = constraints_workspace(g)
+    if ws is None:
+        ws = torch.empty(max(nws, 1), dtype=torch.float64, device=u.device)
+    check(lib().z4c_constraints(_ptr(u), _ptr(c), _ptr(norms), _ptr(ws), ctypes.c_long(ws.numel()),
+                                ctypes.c_long(g.stored), int(g.n[0]), int(g.n[1]), int(g.n[2]), int(g.ng),
+                                float(g.h[0]), float(g.h[1]), float(g.h[2]), _stream(stream)), "z4c_constraints")
+    return norms
 
 
 def tiles(precision: int = FP64):

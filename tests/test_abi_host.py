@@ -160,3 +160,51 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(root, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text and "oz_" not in text, f
+
+
+def test_constraints_workspace_size(L):
+    # one partial per 8x8x4 brick of the active box, four constraints each
+    assert L.z4c_constraints_workspace(256, 256, 256) == 4 * 32 * 32 * 64
+    assert L.z4c_constraints_workspace(9, 8, 5) == 4 * 2 * 1 * 2
+    assert L.z4c_constraints_workspace(0, 8, 8) == 0
+
+
+def _cons(L, u=FAKE, c=None, norms=ctypes.c_void_p(0x20000000), ws=ctypes.c_void_p(0x30000000), ws_len=None,
+          sf=12 ** 3, n=(6, 6, 6), ng=3, h=(0.1, 0.1, 0.1)):
+    if ws_len is None:
+        ws_len = L.z4c_constraints_workspace(*n)
+    return L.z4c_constraints(u, c, norms, ws, ws_len, sf, n[0], n[1], n[2], ng, h[0], h[1], h[2], None)
+
+
+@pytest.mark.parametrize("case", ["null_u", "null_norms", "null_ws", "small_ws", "ng2", "sf", "dx", "c_alias",
+                                  "ws_alias", "norms_alias"])
+def test_constraints_validation(L, case):
+    kw = {}
+    if case == "null_u":
+        kw["u"] = None
+    elif case == "null_norms":
+        kw["norms"] = None
+    elif case == "null_ws":
+        kw["ws"] = None
+    elif case == "small_ws":
+        kw["ws_len"] = L.z4c_constraints_workspace(6, 6, 6) - 1
+    elif case == "ng2":
+        kw["ng"] = 2
+    elif case == "sf":
+        kw["sf"] = 12 ** 3 - 1
+    elif case == "dx":
+        kw["h"] = (0.1, 0.0, 0.1)
+    elif case == "c_alias":
+        kw["c"] = ctypes.c_void_p(0x10000 + 8 * 12 ** 3 * 24)   # inside u's 25 fields
+    elif case == "ws_alias":
+        kw["ws"] = ctypes.c_void_p(0x10000 + 8)
+    elif case == "norms_alias":
+        kw["norms"] = ctypes.c_void_p(0x10000 + 16)
+    assert _cons(L, **kw) == z4c.EINVAL
+    assert L.z4c_last_error().decode()
+
+
+def test_equatorial_ghosts_reject_shell(L):
+    # an equatorial box fills its mirrored layers itself: a shell is an error
+    assert L.apply_ghosts(FAKE, FAKE2, 12 ** 3, 6, 6, 6, 3, z4c.BC_EQUATORIAL, None) == z4c.EINVAL
+    assert "shell" in L.z4c_last_error().decode()

@@ -1,0 +1,130 @@
+"""GPU constraint monitor (Hamiltonian and momentum constraints, Sec. 2.3)
+against the FP64 oracle's monitor on the same seeded inputs, through the C
+ABI.  Bar: per-constraint norm-relative difference <= max(1e-12, 20 x the
+oracle's own one-ulp input sensitivity) -- on constraint-satisfying data H
+and M^i are O(h^4) cancellations of O(1) terms, so their rounding floor is
+set by those terms, not by the result -- and exact where the method is
+(flat space, pi symmetry, ghost entries, run-to-run determinism)."""
+import numpy as np
+import pytest
+import torch
+
+import analytic as A
+from gpu_helpers import normrel, to_dev, to_host
+from paper_2607_08743_amd import inputs as I
+from paper_2607_08743_amd import z4c
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+# parity of H, M^x, M^y, M^z under the pi rotation (x, y) -> (-x, -y)
+PI_PARITY_C = np.array([1.0, -1.0, -1.0, 1.0])
+
+
+def _ghosted(oz, u, g):
+    v = u.copy()
+    if g.bc == I.BC_PERIODIC:
+        oz.apply_ghosts(v, g.as_dict())
+    return v
+
+
+def _gpu(u, g):
+    du = to_dev(u)
+    c = torch.full((4,) + tuple(g.shape[1:]), float("nan"), dtype=torch.float64, device="cuda")
+    norms = z4c.constraints(du, g, c=c)
+    return to_host(c), to_host(norms)
+
+
+def _oracle_with_sensitivity(oz, u, g, seed=0):
+    c, n = oz.constraints(u, g.as_dict())
+    rng = np.random.default_rng(seed)
+    v = u + np.spacing(u) * rng.choice([-1.0, 1.0], size=u.shape)
+    c2, n2 = oz.constraints(v, g.as_dict())
+    m = g.active_mask()
+    sens_c = normrel(c2, c, m)
+    sens_n = np.abs(n2 - n) / np.maximum(np.abs(n), 1e-300)
+    return c, n, sens_c, sens_n
+
+
+def _check(oz, u, g, label):
+    print(f"case: constraints {label}", flush=True)
+    u = _ghosted(oz, u, g)
+    c, n = _gpu(u, g)
+    cr, nr, sc, sn = _oracle_with_sensitivity(oz, u, g)
+    m = g.active_mask()
+    e = normrel(c, cr, m)
+    en = np.abs(n - nr) / np.maximum(np.abs(nr), 1e-300)
+    print("H, M^i normrel:", " ".join(f"{x:.1e}" for x in e), " oracle sensitivity:",
+          " ".join(f"{x:.1e}" for x in sc))
+    print("L2 norms gpu:", n, "oracle:", nr, "rel:", en)
+    assert np.all(c[:, ~m] == 0.0), "ghost entries must be 0"
+    assert np.all(e <= np.maximum(TOL, 20 * sc)), e
+    assert np.all(en <= np.maximum(TOL, 20 * sn)), en
+    return c, n
+
+
+@pytest.mark.parametrize("case", ["strong_periodic", "ragged_periodic", "kerr_schild_copy", "punctures_sommerfeld"])
+def test_constraints_parity(oz, case):
+    if case == "strong_periodic":
+        g = I.centered_grid(24, 0.1, bc=I.BC_PERIODIC)
+        u = I.random_strong_field_state(g)
+    elif case == "ragged_periodic":
+        g = I.Grid((13, 11, 7), (0.1, 0.12, 0.09), (-0.6, -0.6, -0.3), I.BC_PERIODIC)
+        u = I.random_strong_field_state(g, seed=3)
+    elif case == "kerr_schild_copy":
+        g = I.centered_grid(16, 1.0 / 16, center=(3.0, 2.5, 2.0), bc=I.BC_COPY)
+        u = A.evaluate(A.conformal_state_fn(A.kerr_schild_prim(B_amp=0.3)), g)
+    else:
+        g, u, _ = I.config_punctures(32)
+    _check(oz, u, g, case)
+
+
+def test_constraints_flat_space_exact():
+    print("case: constraints flat space 20^3 periodic", flush=True)
+    g = I.centered_grid(20, 0.1, bc=I.BC_PERIODIC)
+    u = I.flat_state(g)
+    c, n = _gpu(u, g)
+    assert np.all(c == 0.0) and np.all(n == 0.0)
+
+
+def test_constraints_pi_symmetry_and_determinism():
+    """Two-puncture data symmetric under the pi rotation give bitwise
+    mirror-symmetric constraints; repeated calls give identical norms (the
+    reduction order is fixed); c = NULL gives the same norms."""
+    print("case: constraints punctures 64^3 pi symmetry + determinism", flush=True)
+    g, u, _ = I.config_punctures(64)
+    c, n = _gpu(u, g)
+    assert np.array_equal(c, c[:, :, ::-1, ::-1] * PI_PARITY_C[:, None, None, None])
+    du = to_dev(u)
+    ws = torch.empty(z4c.constraints_workspace(g), dtype=torch.float64, device="cuda")
+    runs = [to_host(z4c.constraints(du, g, ws=ws)) for _ in range(3)]
+    for r in runs:
+        assert np.array_equal(r, n)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_constraints_full_size_sampled(oz, n):
+    """At the benchmark sizes: the full-box GPU constraints at sampled 8^3
+    blocks (corners, where the stencils reach the Sommerfeld ghosts, the
+    punctures and the centre) against the oracle run on a cut-out of the
+    stored state that holds those blocks plus their 3-cell stencil margin."""
+    print(f"case: constraints punctures {n}^3 sampled blocks", flush=True)
+    g, u, _ = I.config_punctures(n)
+    c, nrm = _gpu(u, g)
+    assert np.all(np.isfinite(c)) and np.all(np.isfinite(nrm))
+    ng, b = g.ng, 8
+    h = g.h[0]
+    pc = int(round((5.0 - g.x0[0]) / h))   # active index nearest the puncture at x = +5
+    starts = [(0, 0, 0), (n - b, n - b, n - b), (0, n - b, n // 2), (pc - 4, n // 2 - 4, n // 2 - 4),
+              (n // 2 - 4, n // 2 - 4, n // 2 - 4)]
+    for (i0, j0, k0) in starts:
+        sub = np.ascontiguousarray(u[:, k0:k0 + b + 2 * ng, j0:j0 + b + 2 * ng, i0:i0 + b + 2 * ng])
+        gs = I.Grid((b, b, b), g.h, (g.x0[0] + i0 * h, g.x0[1] + j0 * h, g.x0[2] + k0 * h), I.BC_COPY, ng)
+        cr, _ = oz.constraints(sub, gs.as_dict())
+        got = c[:, k0 + ng:k0 + ng + b, j0 + ng:j0 + ng + b, i0 + ng:i0 + ng + b]
+        ref = cr[:, ng:ng + b, ng:ng + b, ng:ng + b]
+        # norm-relative over the whole box, as everywhere else: a pointwise
+        # relative error means nothing where a constraint crosses zero
+        scale = np.abs(c.reshape(4, -1)).max(axis=1)
+        d = np.abs(got - ref).reshape(4, -1).max(axis=1)
+        print((i0, j0, k0), "max |gpu - oracle| / max_box |C|:", d / scale)
+        assert np.all(d <= TOL * scale), d / scale

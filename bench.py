@@ -127,6 +127,33 @@ def constraint_monitor_rate(z4c, torch, g, u0, n, reps=5):
     return out
 
 
+def mixed_hierarchy_error(z4c, I, torch, boxes, steps=50):
+    """Per-field max relative error of the mixed-precision hierarchy after
+    `steps` RK4 steps against the float64 path (which matches the oracle to
+    1e-12): max over boxes of max|mixed - fp64| / max|fp64|, and of the same
+    difference over how far the field moved, max|fp64 - initial|."""
+    res = {}
+    for prec in (z4c.FP64, z4c.MIXED):
+        plan = z4c.Plan(boxes, params=z4c.default_params(precision=prec))
+        plan.step(steps)
+        torch.cuda.synchronize()
+        res[prec] = [u.cpu().numpy() for u in plan.u]
+        plan.close()
+    norm = [0.0] * 25
+    moved = [0.0] * 25
+    for bx, a, b in zip(boxes, res[z4c.MIXED], res[z4c.FP64]):
+        m = bx.grid.active_mask()
+        for f in range(25):
+            d = float(abs(a[f][m] - b[f][m]).max())
+            s = float(abs(b[f][m]).max())
+            mv = float(abs(b[f][m] - bx.state[f][m]).max())
+            norm[f] = max(norm[f], d / s if s > 0 else d)
+            moved[f] = max(moved[f], d / mv if mv > 1e-8 else 0.0)
+    return {"steps": steps, "per_field_normrel": dict(zip(I.FIELD_NAMES, norm)),
+            "per_field_rel_to_change": dict(zip(I.FIELD_NAMES, moved)),
+            "reference": "float64 GPU path (oracle parity <= 1e-12)"}
+
+
 def cpu_baseline(I):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     one RK4 step of the 128^3 puncture box (same data recipe), all host
@@ -236,7 +263,8 @@ def main():
                                 "active_cells": act_h, "tile": list(best_h.as_tuple()), "finite": fin_h}
         sec_hm, best_hm, _, fin_hm = run(boxes, pm, None)
         extras["hierarchy9_mixed"] = {"value": act_h * args.steps / sec_hm, "ms_per_step": 1e3 * sec_hm / args.steps,
-                                      "tile": list(best_hm.as_tuple()), "finite": fin_hm}
+                                      "tile": list(best_hm.as_tuple()), "finite": fin_hm,
+                                      "error_after_50_steps": mixed_hierarchy_error(z4c, I, torch, boxes)}
 
     out = {
         "metric": "zone-updates/s for Z4c RHS+RK4 substep (FP64 vs mixed) + % HBM roofline",

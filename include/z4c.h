@@ -211,6 +211,58 @@ int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float*
 
 int z4c_plan_destroy(void* plan);
 
+/* ---------------------------------------------------------------------- */
+/* Box-in-box hierarchy with Berger-Oliger time subcycling (Sec. 2.2.1):  */
+/* level l advances with dt0 / 2^l, two steps per parent step; the        */
+/* child's ghost zone comes from the parent by 6th-order Lagrange         */
+/* prolongation, interpolated in time between the parent's time levels    */
+/* (2nd order; 1st order while the parent has no earlier level); after    */
+/* both child steps the parent cells the child covers are overwritten by  */
+/* the 4th-order Lagrange restriction of the child.                       */
+/* ---------------------------------------------------------------------- */
+
+/* One level (one box).  Geometry as for z4c_box.  Level 0: bc is
+ * Z4C_BC_PERIODIC, Z4C_BC_SOMMERFELD or Z4C_BC_EQUATORIAL.  Levels >= 1: bc
+ * must be Z4C_BC_COPY (ghosts come from the parent), n even, dx half the
+ * parent's, and the lower faces on parent cell faces: F[d] is the parent
+ * active cell index of that face, x0[d] = parent x0[d] + (F[d] - 1/4) *
+ * parent dx[d] (checked); the 6-point stencils of every ghost must fall in
+ * the parent's active cells.  All six arrays are caller-owned device arrays
+ * of 25 fields with stride sf: u the state (advanced in place), u_a, u_b,
+ * acc the RK4 scratch, prev and cur the level's time levels kept for its
+ * child (any contents on entry). */
+typedef struct z4c_level {
+    int n[3];
+    int ng;
+    int bc;
+    long sf;
+    double dx[3];
+    double x0[3];
+    int F[3];
+    double* u;
+    double* u_a;
+    double* u_b;
+    double* acc;
+    double* prev;
+    double* cur;
+} z4c_level;
+
+/* Create a hierarchy of nlev (1..16) levels advanced with coarse step dt0.
+ * tile == NULL: the library default shape with a persistent launch.
+ * Allocates one ghost-shell buffer per level >= 1 in device memory
+ * (25 x (stored - active) doubles; Z4C_ENOMEM if that fails). */
+int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, double dt0, const z4c_tile* tile,
+                    void** hier);
+
+/* Advance every level by nsteps coarse steps on `stream`.  Ghosts of the
+ * levels' states are not refreshed at the end (call apply_ghosts or read
+ * the active cells).  use_graph: from the second coarse step on (every level
+ * then holds an earlier time level) one coarse step is captured as a HIP
+ * graph on first use and replayed. */
+int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream);
+
+int z4c_hier_destroy(void* hier);
+
 /* Static description of a status code, and the detail of the last failing
  * call on this thread. */
 const char* z4c_strerror(int status);

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libz4c.so")
 SOURCES = [os.path.join(CSRC, "z4c_kernels.hip"), os.path.join(CSRC, "z4c_constraints.hip"),
-           os.path.join(CSRC, "z4c_api.hip")]
+           os.path.join(CSRC, "z4c_hierarchy.hip"), os.path.join(CSRC, "z4c_api.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -614,4 +614,301 @@ int z4c_plan_destroy(void* plan)
     return Z4C_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Box-in-box hierarchy with Berger-Oliger subcycling
+// ---------------------------------------------------------------------------
+struct HierLevel {
+    z4c_level L;
+    double* shell;  // device: ghost shell filled by prolongation (levels >= 1)
+    long nshell;
+    bool has_prev;  // prev holds this level one step earlier
+    BoxSet fused[4];
+    BoxSet fill[4];  // ghost fill of the stage inputs u, a, b, a
+};
+
+struct z4c_hier_s {
+    std::vector<HierLevel> lv;
+    ParamsDev prm;
+    int precision;
+    int tile_index;
+    int persistent;
+    double dt0;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipStream_t capture;
+};
+
+// Lagrange weights of the parent time levels (nodes -1, 0, 1 in units of
+// the parent step) at theta; linear in (0, 1) without an earlier level.
+static void hier_time_weights(double theta, bool quadratic, double wt[3])
+{
+    if (quadratic) {
+        wt[0] = 0.5 * theta * (theta - 1.0);
+        wt[1] = (1.0 - theta) * (1.0 + theta);
+        wt[2] = 0.5 * theta * (theta + 1.0);
+    } else {
+        wt[0] = 0.0;
+        wt[1] = 1.0 - theta;
+        wt[2] = theta;
+    }
+}
+
+static hipError_t hier_prolong(z4c_hier_s* H, int l, double theta, hipStream_t s)
+{
+    HierLevel& C = H->lv[l];
+    const HierLevel& P = H->lv[l - 1];
+    ProlongArgs a{};
+    hier_time_weights(theta, P.has_prev, a.wt);
+    a.pa[0] = P.has_prev ? P.L.prev : nullptr;
+    a.pa[1] = P.L.cur;
+    a.pa[2] = P.L.u;
+    a.sfp = P.L.sf;
+    for (int d = 0; d < 3; ++d) {
+        a.Np[d] = P.L.n[d] + 2 * P.L.ng;
+        a.nc[d] = C.L.n[d];
+        a.F[d] = C.L.F[d];
+    }
+    a.ngp = P.L.ng;
+    a.shell = C.shell;
+    a.nshell = C.nshell;
+    a.ngc = C.L.ng;
+    return launch_prolong(a, s);
+}
+
+static hipError_t hier_restrict(z4c_hier_s* H, int l, hipStream_t s)
+{
+    const HierLevel& C = H->lv[l];
+    HierLevel& P = H->lv[l - 1];
+    RestrictArgs a{};
+    a.uc = C.L.u;
+    a.sfc = C.L.sf;
+    a.ngc = C.L.ng;
+    a.up = P.L.u;
+    a.sfp = P.L.sf;
+    a.ngp = P.L.ng;
+    for (int d = 0; d < 3; ++d) {
+        a.Nc[d] = C.L.n[d] + 2 * C.L.ng;
+        a.nc[d] = C.L.n[d];
+        a.Np[d] = P.L.n[d] + 2 * P.L.ng;
+        a.F[d] = C.L.F[d];
+    }
+    return launch_restrict(a, s);
+}
+
+// One RK4 step of level l starting at theta0 (fraction of the parent step),
+// then, if it has a child, the child's two steps, its ghost fill at the end
+// time and the restriction.  Stage inputs get their ghosts at the stage
+// times theta0 + {0, 1/4, 1/4, 1/2}.
+static hipError_t hier_level_step(z4c_hier_s* H, int l, double theta0, hipStream_t s)
+{
+    const TileEntry* tab = nullptr;
+    tile_table(&tab);
+    const TileEntry& T = tab[H->tile_index];
+    HierLevel& L = H->lv[l];
+    const int nlev = (int)H->lv.size();
+    const bool outer = l == 0 && (L.L.bc == Z4C_BC_SOMMERFELD || L.L.bc == Z4C_BC_EQUATORIAL);
+    const long n = (long)NF * L.L.sf;
+    hipError_t e;
+    auto fill = [&](int st) -> hipError_t {
+        if (l == 0 && L.L.bc == Z4C_BC_SOMMERFELD) return hipSuccess;
+        return launch_ghosts(L.fill[st], s);
+    };
+    auto stage = [&](int st) -> hipError_t {
+        hipError_t r = T.launch(L.fused[st], H->prm, MODE_STAGE, st + 1, H->persistent, s);
+        if (r == hipSuccess && outer) r = launch_sommerfeld(L.fused[st], H->prm, MODE_STAGE, st + 1, s);
+        return r;
+    };
+    if (l > 0 && theta0 == 0.0 && (e = hier_prolong(H, l, 0.0, s)) != hipSuccess) return e;
+    if ((e = fill(0)) != hipSuccess) return e;
+    if (l + 1 < nlev && (e = launch_copy(L.L.cur, L.L.u, n, s)) != hipSuccess) return e;
+    if ((e = stage(0)) != hipSuccess) return e;
+    if (l > 0 && (e = hier_prolong(H, l, theta0 + 0.25, s)) != hipSuccess) return e;
+    if ((e = fill(1)) != hipSuccess || (e = stage(1)) != hipSuccess) return e;
+    if ((e = fill(2)) != hipSuccess || (e = stage(2)) != hipSuccess) return e;
+    if (l > 0 && (e = hier_prolong(H, l, theta0 + 0.5, s)) != hipSuccess) return e;
+    if ((e = fill(3)) != hipSuccess || (e = stage(3)) != hipSuccess) return e;
+    if (l + 1 < nlev) {
+        if ((e = hier_level_step(H, l + 1, 0.0, s)) != hipSuccess) return e;
+        if ((e = hier_level_step(H, l + 1, 0.5, s)) != hipSuccess) return e;
+        if ((e = hier_prolong(H, l + 1, 1.0, s)) != hipSuccess) return e;
+        if ((e = launch_ghosts(H->lv[l + 1].fill[0], s)) != hipSuccess) return e;
+        if ((e = hier_restrict(H, l + 1, s)) != hipSuccess) return e;
+        if ((e = launch_copy(L.L.prev, L.L.cur, n, s)) != hipSuccess) return e;
+        L.has_prev = true;
+    }
+    return hipSuccess;
+}
+
+static void hier_drop_graph(z4c_hier_s* H)
+{
+    if (H->exec) (void)hipGraphExecDestroy(H->exec);
+    if (H->graph) (void)hipGraphDestroy(H->graph);
+    H->exec = nullptr;
+    H->graph = nullptr;
+}
+
+static void hier_free(z4c_hier_s* H)
+{
+    hier_drop_graph(H);
+    for (HierLevel& L : H->lv)
+        if (L.shell) (void)hipFree(L.shell);
+    if (H->capture) (void)hipStreamDestroy(H->capture);
+    delete H;
+}
+
+int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, double dt0, const z4c_tile* tile,
+                    void** hier)
+{
+    int rc;
+    if (!hier) return fail(Z4C_EINVAL, "hier is NULL");
+    *hier = nullptr;
+    if ((rc = check_params(p))) return rc;
+    if (!levels || nlev < 1 || nlev > MAXBOX) return fail(Z4C_EINVAL, "need 1..16 levels");
+    if (!finite_pos(dt0)) return fail(Z4C_EINVAL, "dt0 must be finite and > 0");
+    for (int l = 0; l < nlev; ++l) {
+        const z4c_level& x = levels[l];
+        const std::string tag = "level " + std::to_string(l) + ": ";
+        long stored = 0;
+        if ((rc = check_geom(x.sf, x.n[0], x.n[1], x.n[2], x.ng, x.bc, &stored)) ||
+            (rc = check_spacing(x.dx[0], x.dx[1], x.dx[2], x.x0[0], x.x0[1], x.x0[2])))
+            return fail(rc, tag + z4c_last_error());
+        const double* arr[6] = {x.u, x.u_a, x.u_b, x.acc, x.prev, x.cur};
+        for (int i = 0; i < 6; ++i) {
+            if (!arr[i]) return fail(Z4C_EINVAL, tag + "all six state arrays are required");
+            for (int j = 0; j < i; ++j)
+                if (overlap(arr[i], arr[j], x.sf)) return fail(Z4C_EINVAL, tag + "state arrays overlap");
+        }
+        if (l == 0) {
+            if (x.bc == Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "the coarsest level needs its own boundary");
+            continue;
+        }
+        if (x.bc != Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "levels >= 1 take Z4C_BC_COPY (filled from the parent)");
+        const z4c_level& P = levels[l - 1];
+        for (int d = 0; d < 3; ++d) {
+            if (x.n[d] % 2) return fail(Z4C_EINVAL, tag + "active extents must be even");
+            if (x.dx[d] != 0.5 * P.dx[d]) return fail(Z4C_EINVAL, tag + "dx must be half the parent's");
+            const double want = P.x0[d] + (x.F[d] - 0.25) * P.dx[d];
+            if (std::fabs(x.x0[d] - want) > 1e-9 * P.dx[d])
+                return fail(Z4C_EINVAL, tag + "x0 does not put the lower faces on parent cell F");
+            // first / last parent cell read by the ghost stencils: floor(a/2) - 3 for
+            // a = -ng, and floor(a/2) + 3 for a = n + ng - 1
+            const int a_lo = -x.ng, a_hi = x.n[d] + x.ng - 1;
+            const int lo = x.F[d] + (a_lo >= 0 ? a_lo / 2 : -((1 - a_lo) / 2)) - 3;
+            const int hi = x.F[d] + a_hi / 2 + 3;
+            if (lo < 0 || hi >= P.n[d])
+                return fail(Z4C_EINVAL, tag + "prolongation stencil leaves the parent's active cells");
+        }
+    }
+    int pers = 1;
+    int ti;
+    if (tile) {
+        ti = find_tile(p->precision, tile);
+        if (ti < 0) return fail(Z4C_EUNSUPPORTED, "tile shape not compiled for this precision");
+        pers = tile->persistent ? 1 : 0;
+    } else {
+        ti = default_tile_index(p->precision);
+        if (ti < 0) return fail(Z4C_EUNSUPPORTED, "no tile compiled for this precision");
+    }
+    const TileEntry* tab = nullptr;
+    tile_table(&tab);
+    z4c_hier_s* H = new z4c_hier_s{};
+    H->prm = to_dev(p);
+    H->precision = p->precision;
+    H->tile_index = ti;
+    H->persistent = pers;
+    H->dt0 = dt0;
+    H->lv.resize(nlev);
+    for (int l = 0; l < nlev; ++l) {
+        HierLevel& L = H->lv[l];
+        L.L = levels[l];
+        L.shell = nullptr;
+        L.has_prev = false;
+        L.nshell = l > 0 ? shell_size(L.L.n, L.L.ng) : 0;
+        if (l > 0) {
+            hipError_t e = hipMalloc((void**)&L.shell, (size_t)NF * L.nshell * sizeof(double));
+            if (e != hipSuccess) {
+                L.shell = nullptr;
+                hier_free(H);
+                return fail(Z4C_ENOMEM, "ghost shell allocation failed");
+            }
+        }
+        const double dt = dt0 / (double)(1L << l);
+        double* ins[4] = {L.L.u, L.L.u_a, L.L.u_b, L.L.u_a};
+        double* outs[4] = {L.L.u_a, L.L.u_b, L.L.u_a, L.L.u};
+        for (int st = 0; st < 4; ++st) {
+            BoxDev d = make_box(L.L.n, L.L.ng, L.L.bc, L.L.sf, L.L.dx, L.L.x0, dt);
+            d.u_in = ins[st];
+            d.u_n = L.L.u;
+            d.acc = L.L.acc;
+            d.u_out = outs[st];
+            d.shell = L.shell;
+            BoxSet& F = L.fused[st];
+            F = BoxSet{};
+            F.nbox = 1;
+            F.box[0] = d;
+            finalize_set(F, tab[ti].tile);
+            L.fill[st] = F;
+        }
+    }
+    *hier = H;
+    return Z4C_OK;
+}
+
+int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream)
+{
+    if (!hier) return fail(Z4C_EINVAL, "hier is NULL");
+    if (nsteps < 0) return fail(Z4C_EINVAL, "nsteps must be >= 0");
+    z4c_hier_s* H = (z4c_hier_s*)hier;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending HIP error before z4c_hier_advance");
+    auto primed = [&]() {
+        for (size_t l = 0; l + 1 < H->lv.size(); ++l)
+            if (!H->lv[l].has_prev) return false;
+        return true;
+    };
+    int done = 0;
+    // until every parent holds an earlier level the schedule changes from
+    // step to step: launch those steps directly
+    while (done < nsteps && (!use_graph || !primed())) {
+        if ((e = hier_level_step(H, 0, 0.0, s)) != hipSuccess) return hip_fail(e, "hierarchy step launch");
+        ++done;
+    }
+    if (done == nsteps) return Z4C_OK;
+    if (!H->exec) {
+        if (!H->capture && (e = hipStreamCreateWithFlags(&H->capture, hipStreamNonBlocking)) != hipSuccess) {
+            H->capture = nullptr;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        // captured on a private stream; the instantiated graph runs on `s`
+        if ((e = hipStreamBeginCapture(H->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = hier_level_step(H, 0, 0.0, H->capture);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(H->capture, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le, "hierarchy step launch during capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        H->graph = g;
+        H->exec = x;
+    }
+    for (; done < nsteps; ++done)
+        if ((e = hipGraphLaunch(H->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return Z4C_OK;
+}
+
+int z4c_hier_destroy(void* hier)
+{
+    if (!hier) return fail(Z4C_EINVAL, "hier is NULL");
+    hier_free((z4c_hier_s*)hier);
+    return Z4C_OK;
+}
+
 }  // extern "C"

@@ -77,4 +77,33 @@ hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, in
 long constraint_blocks(const int n[3]);
 hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, double* ws, hipStream_t s);
 
+// Inter-level transfers of the Berger-Oliger hierarchy.
+struct ProlongArgs {
+    const double* pa[3];  // parent time levels (earlier, start, end of the parent step); NULL = weight 0
+    double wt[3];         // their time weights
+    long sfp;
+    int Np[3];            // parent stored extents
+    int ngp;
+    double* shell;        // child ghost shell (25 x nshell, canonical order)
+    long nshell;
+    int nc[3];            // child active extents
+    int ngc;
+    int F[3];             // parent active cell index of the child's lower faces
+};
+struct RestrictArgs {
+    const double* uc;  // child state (active cells and one ghost layer read)
+    long sfc;
+    int Nc[3];
+    int ngc;
+    int nc[3];
+    double* up;  // parent state: covered active cells overwritten
+    long sfp;
+    int Np[3];
+    int ngp;
+    int F[3];
+};
+hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
+hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, long n, hipStream_t s);
+
 }  // namespace z4c

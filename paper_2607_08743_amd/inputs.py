@@ -267,3 +267,23 @@ def config_hierarchy(sizes=HIERARCHY_SIZES, h0=2.0, noise=1e-10):
             sh = sh + np.random.default_rng(100 + lev).uniform(-noise, noise, sh.shape)
         boxes.append(Box(g, u, np.ascontiguousarray(sh), 0.5 * h, lev))
     return boxes
+
+
+def bo_level_grids(nlev=6, n=64, h0=4.0, bc0=BC_SOMMERFELD, ng=NG):
+    """Fixed levels of a box-in-box hierarchy for Berger-Oliger subcycling
+    (paper Sec. 2.2.1): level l is an n^3 box centred on the origin with
+    h = h0 / 2^l, so each child covers the central half of its parent; its
+    lower faces sit on parent cell F = n/4.  Returns [(grid, F)]."""
+    out = []
+    for lev in range(nlev):
+        h = h0 / 2 ** lev
+        g = centered_grid(n, h, bc=bc0 if lev == 0 else BC_COPY, ng=ng)
+        out.append((g, (0, 0, 0) if lev == 0 else (n // 4,) * 3))
+    return out
+
+
+def config_bo_hierarchy(nlev=6, n=64, h0=4.0):
+    """Two-puncture Brill-Lindquist data on every level of bo_level_grids,
+    pi-symmetrised; coarse step dt0 = 0.5 h0 (level l: 0.5 h0 / 2^l)."""
+    levels = [(g, pi_symmetrize(brill_lindquist_state(g)), F) for g, F in bo_level_grids(nlev, n, h0)]
+    return levels, 0.5 * h0

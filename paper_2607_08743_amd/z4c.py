@@ -51,6 +51,13 @@ class Box(ctypes.Structure):
                 ("acc", ctypes.c_void_p), ("shell", ctypes.c_void_p)]
 
 
+class Level(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("ng", ctypes.c_int), ("bc", ctypes.c_int), ("sf", ctypes.c_long),
+                ("dx", ctypes.c_double * 3), ("x0", ctypes.c_double * 3), ("F", ctypes.c_int * 3),
+                ("u", ctypes.c_void_p), ("u_a", ctypes.c_void_p), ("u_b", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("cur", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -78,6 +85,9 @@ def lib(path: str = LIB_PATH):
     L.z4c_plan_step.argtypes = [vp, i, i, vp]
     L.z4c_plan_autotune.argtypes = [vp, i, vp, ctypes.POINTER(Tile), ctypes.POINTER(ctypes.c_float)]
     L.z4c_plan_destroy.argtypes = [vp]
+    L.z4c_hier_create.argtypes = [ctypes.POINTER(Level), i, pp, d, ctypes.POINTER(Tile), ctypes.POINTER(vp)]
+    L.z4c_hier_advance.argtypes = [vp, i, i, vp]
+    L.z4c_hier_destroy.argtypes = [vp]
     L.z4c_constraints_workspace.argtypes = [i, i, i]
     L.z4c_constraints_workspace.restype = l
     L.z4c_constraints.argtypes = [dp, dp, dp, dp, l, l, i, i, i, i, d, d, d, vp]
@@ -86,7 +96,8 @@ def lib(path: str = LIB_PATH):
     L.z4c_last_error.argtypes = []
     L.z4c_last_error.restype = ctypes.c_char_p
     for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
-                 "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints"):
+                 "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints",
+                 "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -276,6 +287,52 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().z4c_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hierarchy:
+    """Box-in-box hierarchy with Berger-Oliger subcycling: levels[l] = (grid,
+    state, F) with F the parent active cell index of the level's lower faces
+    (ignored for level 0).  Owns the six device arrays of every level; u[l]
+    is level l's state."""
+
+    def __init__(self, levels, dt0: float, params: Params = None, tile: Tile = None, device="cuda"):
+        import torch
+        self.params = params or default_params()
+        self.grids = [lv[0] for lv in levels]
+        self.u, self._keep, cl = [], [], []
+        for g, state, F in levels:
+            u = torch.as_tensor(state, dtype=torch.float64, device=device).contiguous().clone()
+            extra = [torch.zeros_like(u) for _ in range(5)]
+            self.u.append(u)
+            self._keep.append(extra)
+            c = Level()
+            c.n[:] = [int(v) for v in g.n]
+            c.ng, c.bc, c.sf = int(g.ng), int(g.bc), int(g.stored)
+            c.dx[:] = [float(v) for v in g.h]
+            c.x0[:] = [float(v) for v in g.x0]
+            c.F[:] = [int(v) for v in F]
+            c.u = u.data_ptr()
+            c.u_a, c.u_b, c.acc, c.prev, c.cur = [t.data_ptr() for t in extra]
+            cl.append(c)
+        self._cl = (Level * len(cl))(*cl)
+        h = ctypes.c_void_p()
+        check(lib().z4c_hier_create(self._cl, len(cl), ctypes.byref(self.params), float(dt0),
+                                    None if tile is None else ctypes.byref(tile), ctypes.byref(h)), "z4c_hier_create")
+        self._h = h
+
+    def advance(self, nsteps: int = 1, use_graph: bool = True, stream=None):
+        check(lib().z4c_hier_advance(self._h, int(nsteps), int(bool(use_graph)), _stream(stream)), "z4c_hier_advance")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().z4c_hier_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -208,3 +208,46 @@ def test_equatorial_ghosts_reject_shell(L):
     # an equatorial box fills its mirrored layers itself: a shell is an error
     assert L.apply_ghosts(FAKE, FAKE2, 12 ** 3, 6, 6, 6, 3, z4c.BC_EQUATORIAL, None) == z4c.EINVAL
     assert "shell" in L.z4c_last_error().decode()
+
+
+def _level(n=16, dx=1.0, x0=None, F=(4, 4, 4), bc=2, base=0x100000):
+    L = z4c.Level()
+    L.n[:] = [n] * 3
+    L.ng, L.bc = 3, bc
+    L.sf = (n + 6) ** 3
+    L.dx[:] = [dx] * 3
+    L.x0[:] = [x0 if x0 is not None else -0.5 * (n - 1) * dx] * 3
+    L.F[:] = list(F)
+    size = 25 * L.sf * 8
+    L.u, L.u_a, L.u_b, L.acc, L.prev, L.cur = [base + k * size for k in range(6)]
+    return L
+
+
+@pytest.mark.parametrize("case", ["dx", "x0", "stencil", "odd", "bc0", "bc1", "null"])
+def test_hierarchy_validation(L, case):
+    """z4c_hier_create rejects inconsistent level geometry before it would
+    touch the GPU."""
+    n = 16
+    parent = _level(n, 1.0, bc=z4c.BC_SOMMERFELD)
+    x0c = -0.5 * (n - 1) * 1.0 + (4 - 0.25) * 1.0
+    child = _level(n, 0.5, x0=x0c, base=0x800000000)
+    if case == "dx":
+        child.dx[:] = [0.4] * 3
+    elif case == "x0":
+        child.x0[:] = [x0c + 0.1] * 3
+    elif case == "stencil":
+        child.F[:] = [1, 4, 4]
+        child.x0[0] = -0.5 * (n - 1) + (1 - 0.25)
+    elif case == "odd":
+        child.n[:] = [15, 16, 16]
+    elif case == "bc0":
+        parent.bc = z4c.BC_COPY
+    elif case == "bc1":
+        child.bc = z4c.BC_PERIODIC
+    elif case == "null":
+        child.cur = None
+    arr = (z4c.Level * 2)(parent, child)
+    h = ctypes.c_void_p()
+    p = z4c.default_params()
+    assert L.z4c_hier_create(arr, 2, ctypes.byref(p), 0.5, None, ctypes.byref(h)) == z4c.EINVAL
+    assert not h.value

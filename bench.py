@@ -220,6 +220,11 @@ def main():
         v = [int(x) for x in args.tile.split(",")]
         tile = z4c.Tile(*v)
     sec, best, table, finite = run([box], params, tile)
+    tune = []
+    for k, t in enumerate(z4c.tiles(params.precision)):
+        for pers in (0, 1):
+            if 2 * k + pers < len(table):
+                tune.append([t.bx, t.by, t.bz, t.waves, pers, round(table[2 * k + pers], 3)])
     if not finite:
         raise RuntimeError("non-finite state after the timed steps")
     active = g.active
@@ -274,6 +279,7 @@ def main():
         "config": {"workload": f"single {args.n}^3 box + 3 ghosts, two Brill-Lindquist punctures (m=0.5 each, "
                                f"separation 10), alpha=W, Sommerfeld outer boundary, dx={g.h[0]}, FP64, "
                                f"RK4 steps of dt=0.5dx", "tile": list(best.as_tuple()),
+                   "autotune_ms_per_step": tune,
                    "zone_substeps_per_s": 4 * value},
         "roofline": roof,
         "extras": extras,

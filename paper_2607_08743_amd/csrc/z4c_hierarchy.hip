@@ -31,24 +31,28 @@ constexpr double lagrange_weight(int first, int count, int m, double x)
     return num / den;
 }
 
-// 1-D prolongation weights: a child cell in the lower half of its parent cell
-// (offset -1/4) uses parent cells -3..+2, one in the upper half (+1/4) cells
-// -2..+3, relative to the containing parent cell.
+// 1-D prolongation weights.  A child cell in the upper half of its parent
+// cell (offset +1/4) uses parent cells -2..+3 relative to the containing
+// one, a child in the lower half (-1/4) the mirror image -3..+2.  Both are
+// summed nearest node first (offsets s*{0, 1, -1, 2, -2, 3}, s = +-1) with
+// the same weights, so that mirror-image child points add mirror-image
+// terms in the same order and round identically (pi symmetry is kept bit
+// for bit).
 struct ProlongW {
-    double lo[6], hi[6];
+    double w[6];  // weight of the node at offset kOff[m] (upper half)
 };
+__constant__ int kOff[6] = {0, 1, -1, 2, -2, 3};
 constexpr ProlongW make_prolong_w()
 {
+    constexpr int off[6] = {0, 1, -1, 2, -2, 3};
     ProlongW w{};
-    for (int m = 0; m < 6; ++m) {
-        w.lo[m] = lagrange_weight(-3, 6, m, -0.25);
-        w.hi[m] = lagrange_weight(-2, 6, m, 0.25);
-    }
+    for (int m = 0; m < 6; ++m) w.w[m] = lagrange_weight(-2, 6, off[m] + 2, 0.25);
     return w;
 }
 __constant__ ProlongW kProlong = make_prolong_w();
 
-// restriction: child centres at -3/2, -1/2, 1/2, 3/2 child cells from the parent centre
+// restriction: child centres at -3/2, -1/2, 1/2, 3/2 child cells from the
+// parent centre, weights (r0, r1, r1, r0), summed as r1 (c1 + c2) + r0 (c0 + c3)
 constexpr double kR0 = -1.0 / 16.0, kR1 = 9.0 / 16.0;
 static_assert(lagrange_weight(-1, 4, 0, 0.5) == kR0 && lagrange_weight(-1, 4, 1, 0.5) == kR1,
               "4-point midpoint weights");
@@ -94,13 +98,13 @@ __device__ __forceinline__ void shell_index(long q, int nx, int ny, int nz, int 
     i = (int)(q % Nx);
 }
 
-// child active index a -> first parent active index of its 6-point stencil
-// and which weight row applies
-__device__ __forceinline__ int prolong_first(int a, int F, bool& upper)
+// child active index a -> parent active index of the containing cell and the
+// side of it the child lies on (+1 upper half, -1 lower half)
+__device__ __forceinline__ int prolong_cell(int a, int F, int& side)
 {
     const int half = a >= 0 ? a / 2 : -((1 - a) / 2);  // floor(a / 2)
-    upper = (a - 2 * half) != 0;
-    return F + half + (upper ? -2 : -3);
+    side = (a - 2 * half) != 0 ? 1 : -1;
+    return F + half;
 }
 
 __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
@@ -109,35 +113,41 @@ __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
     if (q >= a.nshell) return;
     int i, j, k;
     shell_index(q, a.nc[0], a.nc[1], a.nc[2], a.ngc, i, j, k);
-    bool ux, uy, uz;
-    const int lx = prolong_first(i - a.ngc, a.F[0], ux) + a.ngp;
-    const int ly = prolong_first(j - a.ngc, a.F[1], uy) + a.ngp;
-    const int lz = prolong_first(k - a.ngc, a.F[2], uz) + a.ngp;
-    const double* wx = ux ? kProlong.hi : kProlong.lo;
-    const double* wy = uy ? kProlong.hi : kProlong.lo;
-    const double* wz = uz ? kProlong.hi : kProlong.lo;
+    int sx, sy, sz;
+    const int px = prolong_cell(i - a.ngc, a.F[0], sx) + a.ngp;
+    const int py = prolong_cell(j - a.ngc, a.F[1], sy) + a.ngp;
+    const int pz = prolong_cell(k - a.ngc, a.F[2], sz) + a.ngp;
     const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
-    const long base = lz * NxNy + (long)ly * Nx + lx;
+    long ox[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) ox[m] = px + sx * kOff[m];
     for (int f = 0; f < NF; ++f) {
         double s = 0.0;
         for (int c = 0; c < 6; ++c) {
-            double sy = 0.0;
+            const long zc = (long)(pz + sz * kOff[c]) * NxNy;
+            double syy = 0.0;
             for (int b = 0; b < 6; ++b) {
-                const long row = f * a.sfp + base + c * NxNy + b * Nx;
-                double sx = 0.0;
+                const long row = f * a.sfp + zc + (long)(py + sy * kOff[b]) * Nx;
+                double sxx = 0.0;
 #pragma unroll
                 for (int m = 0; m < 6; ++m) {
                     double v = 0.0;
                     for (int t = 0; t < 3; ++t)
-                        if (a.pa[t]) v += a.wt[t] * a.pa[t][row + m];
-                    sx += wx[m] * v;
+                        if (a.pa[t]) v += a.wt[t] * a.pa[t][row + ox[m]];
+                    sxx += kProlong.w[m] * v;
                 }
-                sy += wy[b] * sx;
+                syy += kProlong.w[b] * sxx;
             }
-            s += wz[c] * sy;
+            s += kProlong.w[c] * syy;
         }
         a.shell[f * a.nshell + q] = s;
     }
+}
+
+// one direction of the restriction stencil, in the mirror-symmetric order
+__device__ __forceinline__ double rsum(double c0, double c1, double c2, double c3)
+{
+    return kR1 * (c1 + c2) + kR0 * (c0 + c3);
 }
 
 __global__ void __launch_bounds__(256) restrict_cover(RestrictArgs a)
@@ -149,21 +159,20 @@ __global__ void __launch_bounds__(256) restrict_cover(RestrictArgs a)
     const long Ncx = a.Nc[0], NcxNcy = (long)a.Nc[0] * a.Nc[1];
     const long cb = (long)(2 * z - 1 + a.ngc) * NcxNcy + (long)(2 * y - 1 + a.ngc) * Ncx + (2 * x - 1 + a.ngc);
     const long pq = ((long)(a.F[2] + z + a.ngp) * a.Np[1] + (a.F[1] + y + a.ngp)) * a.Np[0] + (a.F[0] + x + a.ngp);
-    const double r[4] = {kR0, kR1, kR1, kR0};
     for (int f = 0; f < NF; ++f) {
         const double* u = a.uc + f * a.sfc + cb;
-        double s = 0.0;
+        double pl[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            double sy = 0.0;
+            double rw[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const double* row = u + c * NcxNcy + b * Ncx;
-                sy += r[b] * (((r[0] * row[0] + r[1] * row[1]) + r[2] * row[2]) + r[3] * row[3]);
+                rw[b] = rsum(row[0], row[1], row[2], row[3]);
             }
-            s += r[c] * sy;
+            pl[c] = rsum(rw[0], rw[1], rw[2], rw[3]);
         }
-        a.up[f * a.sfp + pq] = s;
+        a.up[f * a.sfp + pq] = rsum(pl[0], pl[1], pl[2], pl[3]);
     }
 }
 

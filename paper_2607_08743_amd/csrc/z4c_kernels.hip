@@ -275,8 +275,13 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     // (held advection terms, completed right-hand sides): parked in LDS
     // they take no registers across the staging sequence.  Slot s of thread
     // tid is park[s * NT + tid] (consecutive lanes, consecutive words).
-    constexpr int NPARK = 16;
-    __shared__ __attribute__((aligned(16))) R park[NPARK * NT];
+    // Slots beyond the LDS share of one block (160 KB over the blocks a CU
+    // holds at WAVES waves per SIMD) stay in registers.
+    constexpr int BPC = (WAVES * 4 * 64) / NT > 0 ? (WAVES * 4 * 64) / NT : 1;  // blocks per CU
+    constexpr int LDS_OTHER = (int)sizeof(R) * ((DMA ? 3 * TNP : TNP) + T::GYN + T::GZN);
+    constexpr int PARK_FIT = (163840 / BPC - LDS_OTHER - 512) / (NT * (int)sizeof(R));
+    constexpr int NPARK = PARK_FIT < 0 ? 0 : (PARK_FIT > 16 ? 16 : PARK_FIT);
+    __shared__ __attribute__((aligned(16))) R park[(NPARK > 0 ? NPARK : 1) * NT];
     // Buffer k of the tile.  The offset is made opaque to the compiler, so
     // that it adds it to the per-lane offsets when used instead of keeping
     // one precomputed address per buffer and lane offset live in registers.
@@ -314,15 +319,21 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     // walk it NS bricks at a time: bricks processed together, and in
     // consecutive rounds, are neighbours (x fastest, then y), so most of
     // their halos come from that XCD's L2.
+    // With groups (persistent launches) NS is the group size, so that every
+    // round of an XCD covers one compact group of gx x gy x gz bricks whose
+    // halos overlap in that XCD's L2.
     const long G = gridDim.x;
     const long b = blockIdx.x;
     const long total = set.brick_begin[set.nbox];
     const bool split = G % 8 == 0;
-    const long NS = split ? G / 8 : G;              // blocks per XCD
+    const long NS = split ? G / 8 : G;                                 // blocks per XCD
     const long slot = split ? b / 8 : b;
-    const long C = split ? (total + 7) / 8 : total;  // bricks per XCD
+    const long C = split ? (total + 8 * NS - 1) / (8 * NS) * NS : total;  // work slots per XCD
     const long first = (split ? (b % 8) * C : 0) + slot;
     const long last = split ? ((b % 8) + 1) * C < total ? ((b % 8) + 1) * C : total : total;
+    const int gx = set.grp[0] > 0 ? set.grp[0] : 1, gy = set.grp[1] > 0 ? set.grp[1] : 1,
+              gz = set.grp[2] > 0 ? set.grp[2] : 1;
+    const long G3 = (long)gx * gy * gz;
 
     for (long w = first; w < last; w += NS) {
         if (DMA && w != first) {
@@ -334,9 +345,13 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         while (w >= set.brick_begin[bi + 1]) ++bi;
         const BoxDev& B = set.box[bi];
         const long lw = w - set.brick_begin[bi];
-        const int bxi = (int)(lw % B.nb[0]);
-        const int byi = (int)((lw / B.nb[0]) % B.nb[1]);
-        const int bzi = (int)(lw / ((long)B.nb[0] * B.nb[1]));
+        const long gi = lw / G3;
+        const int r = (int)(lw % G3);
+        const int ngx = (B.nb[0] + gx - 1) / gx, ngy = (B.nb[1] + gy - 1) / gy;
+        const int bxi = (int)(gi % ngx) * gx + r % gx;
+        const int byi = (int)((gi / ngx) % ngy) * gy + (r / gx) % gy;
+        const int bzi = (int)(gi / ((long)ngx * ngy)) * gz + r / (gx * gy);
+        if (bxi >= B.nb[0] || byi >= B.nb[1] || bzi >= B.nb[2]) continue;  // empty slot of a partial group
         const int ng = B.ng;
         const int Nx = B.n[0] + 2 * ng, Ny = B.n[1] + 2 * ng, Nz = B.n[2] + 2 * ng;
         const int i0 = bxi * BX, j0 = byi * BY, k0 = bzi * BZ;  // active-relative brick origin
@@ -544,8 +559,14 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // Staging order: gt, Gt, W, alpha, Khat, Theta, beta, At, B.
         double k[NF];  // completed right-hand sides, stored by finish_point
         enum : int { P_AKGT = 0, P_AKGAM = 6, P_AKBE = 9, P_KKH = 12, P_KTH = 13, P_KAL = 14, P_KW = 15 };
-        auto put_lds = [&](int slot, R v) { park[slot * NT + tid] = v; };
-        auto get_lds = [&](int slot) { return park[slot * NT + tid]; };
+        R park_r[16];
+        auto put_lds = [&](int slot, R v) {
+            if (slot < NPARK)
+                park[slot * NT + tid] = v;
+            else
+                park_r[slot] = v;
+        };
+        auto get_lds = [&](int slot) { return slot < NPARK ? park[slot * NT + tid] : park_r[slot]; };
 
         // --- conformal metric: first derivatives kept, second derivatives
         //     folded into -1/2 gt^lm d_l d_m gt_ij
@@ -855,6 +876,30 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     }
 }
 
+// Factor n bricks into a compact gx x gy x gz group (gx >= gy >= gz, as
+// close to a cube as the factors of n allow).
+inline void brick_groups(long n, int g[3])
+{
+    int best[3] = {(int)n, 1, 1};
+    long score = n;  // largest side
+    for (long z = 1; z * z * z <= n; ++z) {
+        if (n % z) continue;
+        for (long y = z; y * y <= n / z; ++y) {
+            if ((n / z) % y) continue;
+            const long x = n / z / y;
+            if (x < score || (x == score && z > best[2])) {
+                score = x;
+                best[0] = (int)x;
+                best[1] = (int)y;
+                best[2] = (int)z;
+            }
+        }
+    }
+    g[0] = best[0];
+    g[1] = best[1];
+    g[2] = best[2];
+}
+
 // DMA staging moves 16-byte pairs: every tile row must start on an even
 // element of a 16-byte aligned field (odd ghost width, even nx, even field
 // stride, aligned base).
@@ -873,6 +918,8 @@ hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int s
     const long total = set.brick_begin[set.nbox];
     if (total <= 0) return hipSuccess;
     long grid = total;
+    const BoxSet* run = &set;
+    BoxSet grouped;
     if (persistent) {
         static int cap = 0;  // CUs x resident blocks, computed once per process
         if (cap == 0) {
@@ -884,10 +931,25 @@ hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int s
             cap = cus * (per > 0 ? per : 1);
         }
         if (grid > cap) grid = cap;
+        // enough bricks for whole rounds: deal them in compact groups of
+        // (blocks per XCD) bricks
+        if (total >= cap && cap % 8 == 0 && set.grp[0] == 0) {
+            grouped = set;
+            brick_groups(cap / 8, grouped.grp);
+            for (int b = 0; b < grouped.nbox; ++b) {
+                const BoxDev& B = grouped.box[b];
+                const long n = (long)((B.nb[0] + grouped.grp[0] - 1) / grouped.grp[0]) *
+                               ((B.nb[1] + grouped.grp[1] - 1) / grouped.grp[1]) *
+                               ((B.nb[2] + grouped.grp[2] - 1) / grouped.grp[2]) * (cap / 8);
+                grouped.brick_begin[b + 1] = grouped.brick_begin[b] + n;
+            }
+            run = &grouped;
+            grid = cap;
+        }
     }
     grid = (grid + 7) / 8 * 8;  // whole XCD rounds (idle blocks exit at once)
     hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES, DMA>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s,
-                       set, p, mode, stage);
+                       *run, p, mode, stage);
     return hipGetLastError();
 }
 
@@ -1096,6 +1158,7 @@ static const TileEntry kTiles[] = {
     Z4C_TILE(double, Z4C_FP64, 16, 2, 8, 1),
     Z4C_TILE(double, Z4C_FP64, 8, 4, 8, 1),
     Z4C_TILE(double, Z4C_FP64, 8, 8, 8, 2),
+    Z4C_TILE(double, Z4C_FP64, 8, 8, 4, 2),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 16, 4, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 2),

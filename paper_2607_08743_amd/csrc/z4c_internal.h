@@ -42,11 +42,9 @@ struct BoxDev {
 };
 
 // Several boxes in one launch.  brick_begin / shell_begin are exclusive
-// prefix sums of the per-box work counts of the fused and the ghost kernels
-// (the fused count includes the empty slots of partial brick groups).
+// prefix sums of the per-box work counts of the fused and the ghost kernels.
 struct BoxSet {
     int nbox;
-    int grp[3];  // fused kernel: bricks are dealt in groups of grp[0] x grp[1] x grp[2] (0 = 1)
     long brick_begin[MAXBOX + 1];
     long shell_begin[MAXBOX + 1];
     BoxDev box[MAXBOX];

@@ -20,11 +20,15 @@
 // run in registers and each thread writes its point once.  The path is a
 // bandwidth/ALU-bound stencil, not a contraction: no MFMA.
 //
-// Precision.  R = double for Z4C_FP64.  For Z4C_MIXED R = float: the flat
-// value of each field is subtracted in float64 before the conversion, so
-// differences of nearly-flat data keep their float32 precision; k is promoted
-// to float64 for the RK4 update and the enforcement.
+// Precision.  R = double for Z4C_FP64.  For Z4C_MIXED R = float: the tiles
+// are still float64 (DMA path) and every stencil difference is formed in
+// float64 and then rounded to float32, so nearly-flat data keep their
+// precision; the register path (boxes the DMA path cannot take) subtracts
+// each field's flat value in float64 before the conversion.  k is promoted to
+// float64 for the RK4 update and the enforcement.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "z4c_internal.h"
 
@@ -43,6 +47,24 @@ typedef __attribute__((address_space(3))) void lds_void;
 // unconstrained, and lgkmcnt = 0
 #define VM_N(n) ((((n) & 0xF) | ((((n) >> 4) & 0x3) << 14)) | (0x7 << 4) | (0xF << 8))
 #define LGKM0 (0xF | (0x3 << 14) | (0x7 << 4))
+
+// One LDS-DMA load: every lane moves the 16 bytes at `src` to LDS address
+// `dst` + 16 * lane (dst uniform).  Issued as inline assembly so that the
+// compiler's wait-count insertion does not see it: it would otherwise treat
+// every outstanding tile load as a pending write to any LDS address and drain
+// all of them (vmcnt(0)) before the next LDS read, which defeats loading
+// tiles ahead of their use.  The kernel waits for these loads itself
+// (per-field vmcnt waits and a barrier before a tile is read); the loads
+// complete in issue order with the compiler's own loads, so its waits for
+// those stay correct (they may only wait longer).
+__device__ __forceinline__ void lds_dma16(const void* src, lds_void* dst)
+{
+    const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long)dst);
+    __asm__ volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                     :
+                     : "v"(src), "s"(m)
+                     : "memory", "m0");
+}
 
 // Workgroup barrier without a memory fence (s_barrier alone): the caller
 // waits for exactly the LDS writes it needs with s_waitcnt, so that later
@@ -101,18 +123,19 @@ struct Pairs {
     R a1, a2, a3, b1, b2, b3;
 };
 
-template <typename R>
-__device__ __forceinline__ Pairs<R> pairs(const R* t, int st)
+// the differences are formed in the tile's type TT and then rounded to R
+template <typename R, typename TT>
+__device__ __forceinline__ Pairs<R> pairs(const TT* t, int st)
 {
-    const R c = t[0];
-    const R p1 = t[st], m1 = t[-st], p2 = t[2 * st], m2 = t[-2 * st], p3 = t[3 * st], m3 = t[-3 * st];
+    const TT c = t[0];
+    const TT p1 = t[st], m1 = t[-st], p2 = t[2 * st], m2 = t[-2 * st], p3 = t[3 * st], m3 = t[-3 * st];
     Pairs<R> q;
-    q.b1 = p1 - m1;
-    q.b2 = p2 - m2;
-    q.b3 = p3 - m3;
-    q.a1 = (p1 - c) + (m1 - c);
-    q.a2 = (p2 - c) + (m2 - c);
-    q.a3 = (p3 - c) + (m3 - c);
+    q.b1 = R(p1 - m1);
+    q.b2 = R(p2 - m2);
+    q.b3 = R(p3 - m3);
+    q.a1 = R((p1 - c) + (m1 - c));
+    q.a2 = R((p2 - c) + (m2 - c));
+    q.a3 = R((p3 - c) + (m3 - c));
     return q;
 }
 
@@ -249,7 +272,10 @@ struct Brick {
     static constexpr int SXY = SX * SY;
     static constexpr int TN = SXY * (BZ + 6);
     // D1_y f on x in [-2, BX+2) x the brick, D1_z f on x, y in [-2, B+2) x the brick
-    static constexpr int PX = BX + 4;
+    // row pitch of the D1 planes: BX + 4 entries are used; 8-wide bricks pad
+    // to the tile pitch BX + 6 so that rows y and y+4 fall in disjoint LDS
+    // banks (see the lane order in fused_stage)
+    static constexpr int PX = BX == 8 ? BX + 6 : BX + 4;
     static constexpr int GYN = PX * BY * BZ;
     static constexpr int GZN = PX * (BY + 4) * BZ;
     static constexpr int NGY = (GYN + NT - 1) / NT;
@@ -263,39 +289,54 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
 {
     using T = Brick<R, BX, BY, BZ>;
     constexpr int NT = T::NT, SX = T::SX, SXY = T::SXY, TN = T::TN;
-    static_assert(!DMA || (sizeof(R) == 8 && SX % 2 == 0 && NT % 64 == 0), "DMA staging: float64, even rows");
+    static_assert(!DMA || (SX % 2 == 0 && NT % 64 == 0), "DMA staging: even rows, whole waves");
+    // tile type: the DMA path stages float64 tiles in both precisions
+    using TT = typename std::conditional<DMA, double, R>::type;
     // DMA staging moves pairs of doubles (16 bytes per lane); every wave issues
     // the same NR rounds, so the tile is padded to NR * NT pairs.
     constexpr int NR = (TN / 2 + NT - 1) / NT;
     constexpr int TNP = DMA ? NR * NT * 2 : TN;
-    __shared__ __attribute__((aligned(16))) R tiles[DMA ? 3 * TNP : TNP];  // 3 buffers (DMA) or 1
     __shared__ R gyt[T::GYN];  // unscaled D1_y of the staged field (x-halo 2)
     __shared__ R gzt[T::GZN];  // unscaled D1_z of the staged field (x- and y-halo 2)
     // Per-thread slots for values that are produced early and consumed late
     // (held advection terms, completed right-hand sides): parked in LDS
     // they take no registers across the staging sequence.  Slot s of thread
     // tid is park[s * NT + tid] (consecutive lanes, consecutive words).
-    // Slots beyond the LDS share of one block (160 KB over the blocks a CU
-    // holds at WAVES waves per SIMD) stay in registers.
+    // The LDS share of one block (160 KB over the blocks a CU holds at WAVES
+    // waves per SIMD) holds NBUF tile buffers (the DMA path keeps NBUF - 1
+    // fields in flight ahead of the one in use; measured: more than two
+    // ahead gains nothing and costs park slots) and the park slots; slots
+    // beyond the share stay in registers.
     constexpr int BPC = (WAVES * 4 * 64) / NT > 0 ? (WAVES * 4 * 64) / NT : 1;  // blocks per CU
-    constexpr int LDS_OTHER = (int)sizeof(R) * ((DMA ? 3 * TNP : TNP) + T::GYN + T::GZN);
-    constexpr int PARK_FIT = (163840 / BPC - LDS_OTHER - 512) / (NT * (int)sizeof(R));
+    constexpr int BUDGET = 163840 / BPC - 512;
+    constexpr int PLANES = (int)sizeof(R) * (T::GYN + T::GZN);
+    constexpr int BUFB = (int)sizeof(TT) * TNP;
+    constexpr int NBUF = DMA ? 3 : 1;
+    constexpr int DIST = NBUF - 1;  // fields in flight ahead of the staged one
+    static_assert(!DMA || DIST * NR <= 63, "outstanding loads beyond the vmcnt range");
+    constexpr int PARK_FIT = (BUDGET - PLANES - NBUF * BUFB) / (NT * (int)sizeof(R));
     constexpr int NPARK = PARK_FIT < 0 ? 0 : (PARK_FIT > 16 ? 16 : PARK_FIT);
+    __shared__ __attribute__((aligned(16))) TT tiles[NBUF * TNP];
     __shared__ __attribute__((aligned(16))) R park[(NPARK > 0 ? NPARK : 1) * NT];
     // Buffer k of the tile.  The offset is made opaque to the compiler, so
     // that it adds it to the per-lane offsets when used instead of keeping
     // one precomputed address per buffer and lane offset live in registers.
-    auto tilebuf = [&](int k) -> R* {
+    auto tilebuf = [&](int k) -> TT* {
         int o = k * TNP;
         __asm__ volatile("" : "+s"(o));
         return tiles + o;
     };
 
     const int tid = threadIdx.x;
-    const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
+    // Lane order.  A 64-bit LDS read serves 16 lanes per pass.  With 8-wide
+    // bricks those are two rows of 8 points; rows y and y+4 sit 4 * 14 * 8
+    // bytes apart, i.e. in disjoint halves of the 32 banks, so each wave's
+    // rows are taken in the order 0, 4, 1, 5, 2, 6, 3, 7.
+    const int q8 = (tid / BX) % BY;
+    const int tx = tid % BX, ty = (BX == 8 && BY == 8) ? (((q8 & 1) << 2) | (q8 >> 1)) : q8, tz = tid / (BX * BY);
     const int cofs = (tz + 3) * SXY + (ty + 3) * SX + (tx + 3);
-    const R* tb = tiles;  // tile of the staged field
-    const R* t = tb + cofs;
+    const TT* tb = tiles;  // tile of the staged field
+    const TT* t = tb + cofs;
     constexpr int PX = T::PX;
     const R* ty_c = gyt + (tz * BY + ty) * PX + (tx + 2);        // own slot in the D1_y plane
     const R* tz_c = gzt + (tz * (BY + 4) + ty + 2) * PX + (tx + 2);  // own slot in the D1_z plane
@@ -305,13 +346,13 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     for (int r = 0; r < T::NGY; ++r) {
         const int e = tid + r * NT;
         const int x = e % PX, y = (e / PX) % BY, z = e / (PX * BY);
-        gy_src[r] = (z + 3) * SXY + (y + 3) * SX + (x + 1);
+        gy_src[r] = x < BX + 4 ? (z + 3) * SXY + (y + 3) * SX + (x + 1) : -1;  // -1: row padding
     }
 #pragma unroll
     for (int r = 0; r < T::NGZ; ++r) {
         const int e = tid + r * NT;
         const int x = e % PX, y = (e / PX) % (BY + 4), z = e / (PX * (BY + 4));
-        gz_src[r] = (z + 3) * SXY + (y + 1) * SX + (x + 1);
+        gz_src[r] = x < BX + 4 ? (z + 3) * SXY + (y + 1) * SX + (x + 1) : -1;
     }
 
     // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD one
@@ -319,21 +360,15 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     // walk it NS bricks at a time: bricks processed together, and in
     // consecutive rounds, are neighbours (x fastest, then y), so most of
     // their halos come from that XCD's L2.
-    // With groups (persistent launches) NS is the group size, so that every
-    // round of an XCD covers one compact group of gx x gy x gz bricks whose
-    // halos overlap in that XCD's L2.
     const long G = gridDim.x;
     const long b = blockIdx.x;
     const long total = set.brick_begin[set.nbox];
     const bool split = G % 8 == 0;
-    const long NS = split ? G / 8 : G;                                 // blocks per XCD
+    const long NS = split ? G / 8 : G;              // blocks per XCD
     const long slot = split ? b / 8 : b;
-    const long C = split ? (total + 8 * NS - 1) / (8 * NS) * NS : total;  // work slots per XCD
+    const long C = split ? (total + 7) / 8 : total;  // bricks per XCD
     const long first = (split ? (b % 8) * C : 0) + slot;
     const long last = split ? ((b % 8) + 1) * C < total ? ((b % 8) + 1) * C : total : total;
-    const int gx = set.grp[0] > 0 ? set.grp[0] : 1, gy = set.grp[1] > 0 ? set.grp[1] : 1,
-              gz = set.grp[2] > 0 ? set.grp[2] : 1;
-    const long G3 = (long)gx * gy * gz;
 
     for (long w = first; w < last; w += NS) {
         if (DMA && w != first) {
@@ -345,13 +380,9 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         while (w >= set.brick_begin[bi + 1]) ++bi;
         const BoxDev& B = set.box[bi];
         const long lw = w - set.brick_begin[bi];
-        const long gi = lw / G3;
-        const int r = (int)(lw % G3);
-        const int ngx = (B.nb[0] + gx - 1) / gx, ngy = (B.nb[1] + gy - 1) / gy;
-        const int bxi = (int)(gi % ngx) * gx + r % gx;
-        const int byi = (int)((gi / ngx) % ngy) * gy + (r / gx) % gy;
-        const int bzi = (int)(gi / ((long)ngx * ngy)) * gz + r / (gx * gy);
-        if (bxi >= B.nb[0] || byi >= B.nb[1] || bzi >= B.nb[2]) continue;  // empty slot of a partial group
+        const int bxi = (int)(lw % B.nb[0]);
+        const int byi = (int)((lw / B.nb[0]) % B.nb[1]);
+        const int bzi = (int)(lw / ((long)B.nb[0] * B.nb[1]));
         const int ng = B.ng;
         const int Nx = B.n[0] + 2 * ng, Ny = B.n[1] + 2 * ng, Nz = B.n[2] + 2 * ng;
         const int i0 = bxi * BX, j0 = byi * BY, k0 = bzi * BZ;  // active-relative brick origin
@@ -382,6 +413,15 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         for (int q = 0; q < 6; ++q) gt[q] = centre(F_GT + q);
         inv6(gt, gu);
         const R be[3] = {centre(F_BE), centre(F_BE + 1), centre(F_BE + 2)};
+        // At at the point is needed after the metric.  With one wave per SIMD
+        // it is loaded here, ahead of the tile loads, so that waiting for it
+        // never waits for those; with two, registers are too scarce for that.
+        constexpr bool EARLY_AT = WAVES == 1;
+        R At[6];
+        if constexpr (EARLY_AT) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) At[q] = centre(F_AT + q);
+        }
         // advection + dissipation weights of the odd (O) and even (KO6) parts, per direction
         R wodd[3], wev[3];
 #pragma unroll
@@ -446,11 +486,9 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         }
         auto dma_issue = [&](int f, int k) {
             const double* src = B.u_in + f * sf;
-            R* dst = tilebuf(k) + 2 * 64 * wave;
+            TT* dst = tilebuf(k) + 2 * 64 * wave;
 #pragma unroll
-            for (int r = 0; r < NR; ++r)
-                __builtin_amdgcn_global_load_lds((const void*)(src + doff[r]), (lds_void*)(dst + 2 * NT * r), 16, 0,
-                                                 0);
+            for (int r = 0; r < NR; ++r) lds_dma16(src + doff[r], (lds_void*)(dst + 2 * NT * r));
         };
         auto prefetch = [&](int f) {
             const double* src = B.u_in + f * sf;
@@ -458,25 +496,40 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             for (int r = 0; r < NE; ++r) pre[r] = goff[r] >= 0 ? src[goff[r]] : 0.0;
             pre_f = f;
         };
+        // wait until at most `later` fields' tile loads of this wave are in flight
+        auto wait_fields = [&](int later) {
+            if (later >= 6)
+                __builtin_amdgcn_s_waitcnt(VM_N(6 * NR));
+            else if (later == 5)
+                __builtin_amdgcn_s_waitcnt(VM_N(5 * NR));
+            else if (later == 4)
+                __builtin_amdgcn_s_waitcnt(VM_N(4 * NR));
+            else if (later == 3)
+                __builtin_amdgcn_s_waitcnt(VM_N(3 * NR));
+            else if (later == 2)
+                __builtin_amdgcn_s_waitcnt(VM_N(2 * NR));
+            else if (later == 1)
+                __builtin_amdgcn_s_waitcnt(VM_N(NR));
+            else
+                __builtin_amdgcn_s_waitcnt(VM_N(0));
+        };
         // make element i of the sequence the staged field
         auto stage_field = [&](int i) {
             if constexpr (DMA) {
-                // wait until this wave's loads of field i have landed (the loads
-                // of field i+1, issued later, may still be in flight), then
+                // wait until this wave's loads of field i have landed (those of
+                // the later fields already issued may still be in flight), then
                 // until every wave has, and has finished reading field i-1
-                if (i + 1 < NSEQ)
-                    __builtin_amdgcn_s_waitcnt(VM_N(NR));
-                else
-                    __builtin_amdgcn_s_waitcnt(VM_N(0));
+                const int later = (NSEQ - 1 - i) < (DIST - 1) ? (NSEQ - 1 - i) : (DIST - 1);
+                wait_fields(later);
                 __builtin_amdgcn_s_waitcnt(LGKM0);
                 bar();
-                if (i + 2 < NSEQ) dma_issue(seq(i + 2), (i + 2) % 3);
-                tb = tilebuf(i % 3);
+                if (i + DIST < NSEQ) dma_issue(seq(i + DIST), (i + DIST) % NBUF);
+                tb = tilebuf(i % NBUF);
                 t = tb + cofs;
             } else {
                 const double off = sizeof(R) == 4 ? flat_of(pre_f) : 0.0;
                 __syncthreads();
-                R* tw = tilebuf(0);
+                TT* tw = tilebuf(0);
 #pragma unroll
                 for (int r = 0; r < NE; ++r) {
                     const int e = tid + r * NT;
@@ -487,15 +540,16 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             }
         };
         if constexpr (DMA) {
-            dma_issue(seq(0), 0);
-            dma_issue(seq(1), 1);
+#pragma unroll
+            for (int k = 0; k < DIST; ++k) dma_issue(seq(k), k);
         } else {
             prefetch(seq(0));
         }
 
-        // centre value of the staged field (its flat value restored in float32 mode)
+        // centre value of the staged field (its flat value restored when the
+        // register path staged it in float32)
         auto tval = [&](int f) {
-            R v = t[0] + R(sizeof(R) == 4 ? flat_of(f) : 0.0);
+            R v = R(t[0]) + R((sizeof(R) == 4 && !DMA) ? flat_of(f) : 0.0);
             pin(v);
             return v;
         };
@@ -503,7 +557,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         struct P3 {
             Pairs<R> x, y, z;
         };
-        auto field_pairs = [&]() { return P3{pairs(t, 1), pairs(t, SX), pairs(t, SXY)}; };
+        auto field_pairs = [&]() { return P3{pairs<R>(t, 1), pairs<R>(t, SX), pairs<R>(t, SXY)}; };
         // advection along the shift plus Kreiss-Oliger dissipation
         auto advko = [&](const P3& q) {
             R a = (wodd[0] * odd5(q.x) + wev[0] * ko6(q.x)) + (wodd[1] * odd5(q.y) + wev[1] * ko6(q.y))
@@ -521,17 +575,17 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // that each mixed derivative needs 4 LDS reads instead of 16.
         auto d1_planes = [&]() {
             auto u1 = [&](int c, int st) {
-                return R(8) * (tb[c + st] - tb[c - st]) - (tb[c + 2 * st] - tb[c - 2 * st]);
+                return R(TT(8) * (tb[c + st] - tb[c - st]) - (tb[c + 2 * st] - tb[c - 2 * st]));
             };
 #pragma unroll
             for (int r = 0; r < T::NGY; ++r) {
                 const int e = tid + r * NT;
-                if (r + 1 < T::NGY || e < T::GYN) gyt[e] = u1(gy_src[r], SX);
+                if ((r + 1 < T::NGY || e < T::GYN) && gy_src[r] >= 0) gyt[e] = u1(gy_src[r], SX);
             }
 #pragma unroll
             for (int r = 0; r < T::NGZ; ++r) {
                 const int e = tid + r * NT;
-                if (r + 1 < T::NGZ || e < T::GZN) gzt[e] = u1(gz_src[r], SXY);
+                if ((r + 1 < T::NGZ || e < T::GZN) && gz_src[r] >= 0) gzt[e] = u1(gz_src[r], SXY);
             }
             if constexpr (DMA) {
                 __builtin_amdgcn_s_waitcnt(LGKM0);
@@ -640,10 +694,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- At at the point (its stencils are staged near the end): At^ij,
         //     At_ij At^ij and Gamma^a_jk At^jk now, so that C2 dies with the
         //     lapse below
-        R At[6], Auu[6], AA, nG[3];  // nG: Gt source without advection/dissipation
+        R Auu[6], AA, nG[3];  // nG: Gt source without advection/dissipation
         {
+            if constexpr (!EARLY_AT) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) At[q] = centre(F_AT + q);
+                for (int q = 0; q < 6; ++q) At[q] = centre(F_AT + q);
+            }
             R Au[3][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
@@ -876,30 +932,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     }
 }
 
-// Factor n bricks into a compact gx x gy x gz group (gx >= gy >= gz, as
-// close to a cube as the factors of n allow).
-inline void brick_groups(long n, int g[3])
-{
-    int best[3] = {(int)n, 1, 1};
-    long score = n;  // largest side
-    for (long z = 1; z * z * z <= n; ++z) {
-        if (n % z) continue;
-        for (long y = z; y * y <= n / z; ++y) {
-            if ((n / z) % y) continue;
-            const long x = n / z / y;
-            if (x < score || (x == score && z > best[2])) {
-                score = x;
-                best[0] = (int)x;
-                best[1] = (int)y;
-                best[2] = (int)z;
-            }
-        }
-    }
-    g[0] = best[0];
-    g[1] = best[1];
-    g[2] = best[2];
-}
-
 // DMA staging moves 16-byte pairs: every tile row must start on an even
 // element of a 16-byte aligned field (odd ghost width, even nx, even field
 // stride, aligned base).
@@ -919,33 +951,17 @@ hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int s
     if (total <= 0) return hipSuccess;
     long grid = total;
     const BoxSet* run = &set;
-    BoxSet grouped;
+    static int cap = 0;  // resident blocks per CU, x CUs; computed once per process
+    if (cap == 0) {
+        int dev = 0, cus = 0, per = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES, DMA>, BX * BY * BZ,
+                                                           0);
+        cap = cus * (per > 0 ? per : 1);
+    }
     if (persistent) {
-        static int cap = 0;  // CUs x resident blocks, computed once per process
-        if (cap == 0) {
-            int dev = 0, cus = 0, per = 0;
-            (void)hipGetDevice(&dev);
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES, DMA>,
-                                                               BX * BY * BZ, 0);
-            cap = cus * (per > 0 ? per : 1);
-        }
         if (grid > cap) grid = cap;
-        // enough bricks for whole rounds: deal them in compact groups of
-        // (blocks per XCD) bricks
-        if (total >= cap && cap % 8 == 0 && set.grp[0] == 0) {
-            grouped = set;
-            brick_groups(cap / 8, grouped.grp);
-            for (int b = 0; b < grouped.nbox; ++b) {
-                const BoxDev& B = grouped.box[b];
-                const long n = (long)((B.nb[0] + grouped.grp[0] - 1) / grouped.grp[0]) *
-                               ((B.nb[1] + grouped.grp[1] - 1) / grouped.grp[1]) *
-                               ((B.nb[2] + grouped.grp[2] - 1) / grouped.grp[2]) * (cap / 8);
-                grouped.brick_begin[b + 1] = grouped.brick_begin[b] + n;
-            }
-            run = &grouped;
-            grid = cap;
-        }
     }
     grid = (grid + 7) / 8 * 8;  // whole XCD rounds (idle blocks exit at once)
     hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES, DMA>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s,
@@ -956,7 +972,7 @@ hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int s
 template <typename R, int BX, int BY, int BZ, int WAVES>
 hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s)
 {
-    if constexpr (sizeof(R) == 8 && BX % 2 == 0 && (BX * BY * BZ) % 64 == 0) {
+    if constexpr (BX % 2 == 0 && (BX * BY * BZ) % 64 == 0) {
         if (dma_compatible(set)) return launch_variant<R, BX, BY, BZ, WAVES, true>(set, p, mode, stage, persistent, s);
     }
     return launch_variant<R, BX, BY, BZ, WAVES, false>(set, p, mode, stage, persistent, s);
@@ -1163,6 +1179,7 @@ static const TileEntry kTiles[] = {
     Z4C_TILE(float, Z4C_MIXED, 16, 4, 4, 1),
     Z4C_TILE(float, Z4C_MIXED, 8, 8, 4, 2),
     Z4C_TILE(float, Z4C_MIXED, 16, 8, 2, 2),
+    Z4C_TILE(float, Z4C_MIXED, 8, 8, 8, 2),
 };
 
 int tile_table(const TileEntry** out)

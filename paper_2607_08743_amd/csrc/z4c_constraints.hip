@@ -10,7 +10,12 @@
 //   d_j At^ij = gt^ia gt^jb d_j At_ab + At_ab d_j(gt^ia gt^jb),
 //   d_j gt^ia = -gt^ic gt^ad d_j gt_cd.
 // The derivative stencils are the 4th-order centred ones of the evolution.
+// Fields are staged one at a time through LDS like in the fused kernel
+// (16-byte LDS-DMA loads two fields ahead, or register loads for boxes whose
+// rows are not 16-byte aligned).
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
 
 #include "z4c_internal.h"
 
@@ -20,7 +25,18 @@ namespace {
 
 constexpr int CX = 8, CY = 8, CZ = 4;  // brick of one block (one point per thread)
 constexpr int CNT = CX * CY * CZ;
-constexpr int CSX = CX + 4, CSY = CY + 4, CSXY = CSX * CSY, CTN = CSXY * (CZ + 4);  // halo 2
+
+// Tile geometry: halo 3 on the DMA path (tile rows then start on even
+// elements, as 16-byte loads need), halo 2 on the register path.
+template <bool DMA>
+struct CTile {
+    static constexpr int H = DMA ? 3 : 2;
+    static constexpr int SX = CX + 2 * H, SY = CY + 2 * H, SXY = SX * SY, TN = SXY * (CZ + 2 * H);
+    static constexpr int NR = (TN / 2 + CNT - 1) / CNT;      // 16-byte rounds per thread (DMA)
+    static constexpr int TNP = DMA ? NR * CNT * 2 : TN;       // padded tile
+    static constexpr int NE = (TN + CNT - 1) / CNT;           // elements per thread (register path)
+    static constexpr int NBUF = DMA ? 3 : 1;
+};
 
 __device__ __forceinline__ int sidx(int a, int b)
 {
@@ -46,9 +62,20 @@ __device__ __forceinline__ double cmix(const double* t, int sa, int sb, double s
     return (8.0 * (g(sa) - g(-sa)) - (g(2 * sa) - g(-2 * sa))) * scale;
 }
 
-__global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))) constraints_kernel(BoxSet set, double* c_out, double* partial)
+// Fields in staging order: gt (derivatives), Gt, W, Khat, Theta, At.
+__device__ __forceinline__ int cseq(int i)
 {
-    __shared__ double tile[CTN];
+    return i < 6 ? F_GT + i : i < 9 ? F_GAM + (i - 6) : i == 9 ? F_W : i == 10 ? F_KH : i == 11 ? F_TH : F_AT + (i - 12);
+}
+constexpr int CNSEQ = 18;
+
+template <bool DMA>
+__global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+constraints_kernel(BoxSet set, double* c_out, double* partial)
+{
+    using T = CTile<DMA>;
+    constexpr int SX = T::SX, SXY = T::SXY, TN = T::TN, TNP = T::TNP, NR = T::NR, NE = T::NE;
+    __shared__ __attribute__((aligned(16))) double tiles[T::NBUF * TNP];
     __shared__ double red[4][CNT];
     const BoxDev& B = set.box[0];
     const int tid = threadIdx.x;
@@ -61,10 +88,12 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
     const bool valid = (i0 + tx < B.n[0]) && (j0 + ty < B.n[1]) && (k0 + tz < B.n[2]);
     const size_t sf = (size_t)B.sf;
     const size_t p = ((size_t)(k0 + tz + ng) * Ny + (j0 + ty + ng)) * Nx + (i0 + tx + ng);
-    const int gx0 = i0 + ng - 2, gy0 = j0 + ng - 2, gz0 = k0 + ng - 2;
-    const double* t = tile + (tz + 2) * CSXY + (ty + 2) * CSX + (tx + 2);
+    const int gx0 = i0 + ng - T::H, gy0 = j0 + ng - T::H, gz0 = k0 + ng - T::H;
+    const int cofs = (tz + T::H) * SXY + (ty + T::H) * SX + (tx + T::H);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     double i12h[3], i12h2[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         i12h[d] = 1.0 / (12.0 * B.h[d]);
         i12h2[d] = 1.0 / (12.0 * B.h[d] * B.h[d]);
@@ -72,46 +101,90 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
     const double imix[3] = {1.0 / (144.0 * B.h[0] * B.h[1]), 1.0 / (144.0 * B.h[0] * B.h[2]),
                             1.0 / (144.0 * B.h[1] * B.h[2])};
 
-    auto stage = [&](int f) {
-        __syncthreads();
-        const double* src = B.u_in + f * sf;
-        for (int e = tid; e < CTN; e += CNT) {
-            const int lx = e % CSX, ly = (e / CSX) % CSY, lz = e / CSXY;
+    // per-thread offsets of its tile slots in one field (element pairs on the
+    // DMA path; slots outside the stored box read a harmless valid address
+    // there and are filled with 0 on the register path)
+    int off[DMA ? NR : NE];
+#pragma unroll
+    for (int r = 0; r < (DMA ? NR : NE); ++r) {
+        const int e = DMA ? 2 * (r * CNT + tid) : tid + r * CNT;
+        int o = DMA ? 0 : -1;
+        if (e < TN) {
+            const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
             const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
-            tile[e] = (gi < Nx && gj < Ny && gk < Nz) ? src[((size_t)gk * Ny + gj) * Nx + gi] : 0.0;
+            if (gi < Nx && gj < Ny && gk < Nz) o = (gk * Ny + gj) * Nx + gi;
         }
-        __syncthreads();
+        off[r] = o;
+    }
+    auto tilebuf = [&](int k) -> double* {
+        int o = k * TNP;
+        __asm__ volatile("" : "+s"(o));
+        return tiles + o;
     };
+    auto dma_issue = [&](int f, int k) {
+        const double* src = B.u_in + f * sf;
+        double* dst = tilebuf(k) + 2 * 64 * wave;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) lds_dma16(src + off[r], (lds_void*)(dst + 2 * CNT * r));
+    };
+    const double* t = tiles + cofs;
+    // make element i of the sequence the staged field
+    auto stage = [&](int i) {
+        if constexpr (DMA) {
+            if (i + 1 < CNSEQ)
+                __builtin_amdgcn_s_waitcnt(VM_N(NR));
+            else
+                __builtin_amdgcn_s_waitcnt(VM_N(0));
+            __builtin_amdgcn_s_waitcnt(LGKM0);
+            bar();
+            if (i + 2 < CNSEQ) dma_issue(cseq(i + 2), (i + 2) % 3);
+            t = tilebuf(i % 3) + cofs;
+        } else {
+            const double* src = B.u_in + cseq(i) * sf;
+            double v[NE];
+#pragma unroll
+            for (int r = 0; r < NE; ++r) v[r] = off[r] >= 0 ? src[off[r]] : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < NE; ++r)
+                if (r + 1 < NE || tid + r * CNT < TN) tiles[tid + r * CNT] = v[r];
+            __syncthreads();
+        }
+    };
+    if constexpr (DMA) {
+        dma_issue(cseq(0), 0);
+        dma_issue(cseq(1), 1);
+    }
     auto grad = [&](double* d) {
         d[0] = cd1(t, 1, i12h[0]);
-        d[1] = cd1(t, CSX, i12h[1]);
-        d[2] = cd1(t, CSXY, i12h[2]);
+        d[1] = cd1(t, SX, i12h[1]);
+        d[2] = cd1(t, SXY, i12h[2]);
+#pragma unroll
         for (int c = 0; c < 3; ++c) keep(d[c]);
     };
     auto hess = [&](double* dd) {
         dd[0] = cd2(t, 1, i12h2[0]);
-        dd[3] = cd2(t, CSX, i12h2[1]);
-        dd[5] = cd2(t, CSXY, i12h2[2]);
-        dd[1] = cmix(t, 1, CSX, imix[0]);
-        dd[2] = cmix(t, 1, CSXY, imix[1]);
-        dd[4] = cmix(t, CSX, CSXY, imix[2]);
+        dd[3] = cd2(t, SX, i12h2[1]);
+        dd[5] = cd2(t, SXY, i12h2[2]);
+        dd[1] = cmix(t, 1, SX, imix[0]);
+        dd[2] = cmix(t, 1, SXY, imix[1]);
+        dd[4] = cmix(t, SX, SXY, imix[2]);
+#pragma unroll
         for (int q = 0; q < 6; ++q) keep(dd[q]);
     };
     auto tr6 = [](const double* g, const double* x) {
         return g[0] * x[0] + g[3] * x[3] + g[5] * x[5] + 2.0 * (g[1] * x[1] + g[2] * x[2] + g[4] * x[4]);
     };
 
+    // conformal metric at the point (loaded after the first tiles, so one
+    // round trip covers both) and its inverse
     double gt[6], gu[6], dgt[6][3], Rt[6];
-    // conformal metric
-    for (int q = 0; q < 6; ++q) {
-        stage(F_GT + q);
-        gt[q] = t[0];
-        keep(gt[q]);
-    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gt[q] = valid ? B.u_in[(F_GT + q) * sf + p] : (q == 0 || q == 3 || q == 5 ? 1.0 : 0.0);
     {
         const double det = gt[0] * (gt[3] * gt[5] - gt[4] * gt[4]) - gt[1] * (gt[1] * gt[5] - gt[4] * gt[2])
                          + gt[2] * (gt[1] * gt[4] - gt[3] * gt[2]);
-        const double id = valid ? 1.0 / det : 1.0;
+        const double id = 1.0 / det;
         gu[0] = (gt[3] * gt[5] - gt[4] * gt[4]) * id;
         gu[1] = (gt[2] * gt[4] - gt[1] * gt[5]) * id;
         gu[2] = (gt[1] * gt[4] - gt[2] * gt[3]) * id;
@@ -119,8 +192,9 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
         gu[4] = (gt[2] * gt[1] - gt[0] * gt[4]) * id;
         gu[5] = (gt[0] * gt[3] - gt[1] * gt[1]) * id;
     }
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
-        stage(F_GT + q);
+        stage(q);
         grad(dgt[q]);
         double dd[6];
         hess(dd);
@@ -128,20 +202,31 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
         keep(Rt[q]);
     }
     double C1[3][6], C2[3][6], Gtd[3];
+#pragma unroll
     for (int k = 0; k < 3; ++k)
+#pragma unroll
         for (int i = 0; i < 3; ++i)
+#pragma unroll
             for (int j = i; j < 3; ++j)
                 C1[k][sidx(i, j)] = 0.5 * (dgt[sidx(k, j)][i] + dgt[sidx(k, i)][j] - dgt[sidx(i, j)][k]);
+#pragma unroll
     for (int k = 0; k < 3; ++k)
+#pragma unroll
         for (int q = 0; q < 6; ++q)
             C2[k][q] = gu[sidx(k, 0)] * C1[0][q] + gu[sidx(k, 1)] * C1[1][q] + gu[sidx(k, 2)] * C1[2][q];
+#pragma unroll
     for (int k = 0; k < 3; ++k) Gtd[k] = tr6(gu, C2[k]);
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = i; j < 3; ++j) {
             double s = 0.0;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 s += 0.5 * Gtd[k] * (C1[i][sidx(j, k)] + C1[j][sidx(i, k)]);
+#pragma unroll
                 for (int l = 0; l < 3; ++l)
+#pragma unroll
                     for (int m = 0; m < 3; ++m)
                         s += gu[sidx(l, m)] * (C2[k][sidx(l, i)] * C1[j][sidx(k, m)]
                                                + C2[k][sidx(l, j)] * C1[i][sidx(k, m)]
@@ -150,34 +235,40 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
             Rt[sidx(i, j)] += s;
         }
     // evolved Gt in the Ricci tensor
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        stage(F_GAM + a);
+        stage(6 + a);
         double d[3];
         grad(d);
+#pragma unroll
         for (int i = 0; i < 3; ++i)
+#pragma unroll
             for (int j = i; j < 3; ++j) Rt[sidx(i, j)] += 0.5 * (gt[sidx(a, i)] * d[j] + gt[sidx(a, j)] * d[i]);
+#pragma unroll
         for (int q = 0; q < 6; ++q) keep(Rt[q]);
     }
     // conformal factor
     double W, dW[3], DDW[6];
-    stage(F_W);
+    stage(9);
     W = t[0];
     grad(dW);
     hess(DDW);
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
         DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
         keep(DDW[q]);
     }
     // trace of the extrinsic curvature
     double K, dK[3];
-    stage(F_KH);
+    stage(10);
     K = t[0];
     grad(dK);
-    stage(F_TH);
+    stage(11);
     K += 2.0 * t[0];
     {
         double d[3];
         grad(d);
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             dK[c] += 2.0 * d[c];
             keep(dK[c]);
@@ -185,8 +276,9 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
     // traceless curvature
     double At[6], dAt[6][3];
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
-        stage(F_AT + q);
+        stage(12 + q);
         At[q] = t[0];
         grad(dAt[q]);
     }
@@ -195,16 +287,23 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (valid) {
         const double trDDW = tr6(gu, DDW);
         double dW2 = 0.0;
+#pragma unroll
         for (int i = 0; i < 3; ++i)
+#pragma unroll
             for (int j = 0; j < 3; ++j) dW2 += gu[sidx(i, j)] * dW[i] * dW[j];
         double W2R[6];
+#pragma unroll
         for (int q = 0; q < 6; ++q) W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - 2.0 * gt[q] * dW2;
         const double R = tr6(gu, W2R);
         double Auu[6];
+#pragma unroll
         for (int i = 0; i < 3; ++i)
+#pragma unroll
             for (int j = i; j < 3; ++j) {
                 double s = 0.0;
+#pragma unroll
                 for (int a = 0; a < 3; ++a)
+#pragma unroll
                     for (int b2 = 0; b2 < 3; ++b2) s += gu[sidx(i, a)] * gu[sidx(j, b2)] * At[sidx(a, b2)];
                 Auu[sidx(i, j)] = s;
             }
@@ -212,24 +311,35 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
         c[0] = R - AA + 2.0 * K * K / 3.0;
         // d_j gt^ab = -gt^ac gt^bd d_j gt_cd
         double dgu[3][6];
+#pragma unroll
         for (int j = 0; j < 3; ++j)
+#pragma unroll
             for (int a = 0; a < 3; ++a)
+#pragma unroll
                 for (int b2 = a; b2 < 3; ++b2) {
                     double s = 0.0;
+#pragma unroll
                     for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
                         for (int d = 0; d < 3; ++d) s += gu[sidx(a, cc)] * gu[sidx(b2, d)] * dgt[sidx(cc, d)][j];
                     dgu[j][sidx(a, b2)] = -s;
                 }
         double trG[3];  // Gamma^j_jk
+#pragma unroll
         for (int k = 0; k < 3; ++k) trG[k] = C2[0][sidx(0, k)] + C2[1][sidx(1, k)] + C2[2][sidx(2, k)];
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
             double div = 0.0, chr = 0.0, aw = 0.0, gk = 0.0;
+#pragma unroll
             for (int j = 0; j < 3; ++j) {
+#pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
                     for (int d = 0; d < 3; ++d)
                         div += gu[sidx(a, cc)] * gu[sidx(j, d)] * dAt[sidx(cc, d)][j]
                              + At[sidx(cc, d)] * (dgu[j][sidx(a, cc)] * gu[sidx(j, d)]
                                                   + gu[sidx(a, cc)] * dgu[j][sidx(j, d)]);
+#pragma unroll
                 for (int k = 0; k < 3; ++k) chr += C2[a][sidx(j, k)] * Auu[sidx(j, k)];
                 chr += trG[j] * Auu[sidx(a, j)];
                 aw += Auu[sidx(a, j)] * dW[j];
@@ -238,13 +348,16 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1))
             c[1 + a] = W * W * (div + chr - 3.0 * aw / W - 2.0 * gk / 3.0);
         }
         if (c_out)
+#pragma unroll
             for (int m = 0; m < 4; ++m) c_out[m * sf + p] = c[m];
     }
     // fixed-order block reduction of C^2
+#pragma unroll
     for (int m = 0; m < 4; ++m) red[m][tid] = c[m] * c[m];
     __syncthreads();
     for (int s = CNT / 2; s > 0; s >>= 1) {
         if (tid < s)
+#pragma unroll
             for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + s];
         __syncthreads();
     }
@@ -295,7 +408,12 @@ hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, d
         const long n = 4 * B.sf;
         hipLaunchKernelGGL(zero_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c_out, n);
     }
-    hipLaunchKernelGGL(constraints_kernel, dim3((unsigned)nb), dim3(CNT), 0, s, one, c_out, workspace);
+    // 16-byte tile loads need tile rows on even elements of an aligned field
+    const bool dma = B.ng % 2 == 1 && B.n[0] % 2 == 0 && B.sf % 2 == 0 && ((uintptr_t)B.u_in & 15) == 0;
+    if (dma)
+        hipLaunchKernelGGL(constraints_kernel<true>, dim3((unsigned)nb), dim3(CNT), 0, s, one, c_out, workspace);
+    else
+        hipLaunchKernelGGL(constraints_kernel<false>, dim3((unsigned)nb), dim3(CNT), 0, s, one, c_out, workspace);
     const double cells = (double)B.n[0] * B.n[1] * B.n[2];
     hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(256), 0, s, workspace, nb, 1.0 / cells, norms);
     return hipGetLastError();

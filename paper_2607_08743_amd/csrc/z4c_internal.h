@@ -77,6 +77,45 @@ hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, in
 long constraint_blocks(const int n[3]);
 hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, double* ws, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Device helpers shared by the stencil kernels (LDS tile staging).
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt immediates (gfx9 encoding): vmcnt <= n with the other counters
+// unconstrained, and lgkmcnt = 0
+#define VM_N(n) ((((n) & 0xF) | ((((n) >> 4) & 0x3) << 14)) | (0x7 << 4) | (0xF << 8))
+#define LGKM0 (0xF | (0x3 << 14) | (0x7 << 4))
+
+// One LDS-DMA load: every lane moves the 16 bytes at `src` to LDS address
+// `dst` + 16 * lane (dst uniform).  Issued as inline assembly so that the
+// compiler's wait-count insertion does not see it: it would otherwise treat
+// every outstanding tile load as a pending write to any LDS address and drain
+// all of them (vmcnt(0)) before the next LDS read, which defeats loading
+// tiles ahead of their use.  The kernels wait for these loads themselves
+// (per-field vmcnt waits and a barrier before a tile is read); the loads
+// complete in issue order with the compiler's own loads, so its waits for
+// those stay correct (they may only wait longer).
+__device__ __forceinline__ void lds_dma16(const void* src, lds_void* dst)
+{
+    const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long)dst);
+    __asm__ volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                     :
+                     : "v"(src), "s"(m)
+                     : "memory", "m0");
+}
+
+// Workgroup barrier without a memory fence (s_barrier alone): the caller
+// waits for exactly the LDS writes it needs with s_waitcnt, so that later
+// tiles' loads stay in flight across it.  The empty asm statements keep the
+// compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void bar()
+{
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 // Inter-level transfers of the Berger-Oliger hierarchy.
 struct ProlongArgs {
     const double* pa[3];  // parent time levels (earlier, start, end of the parent step); NULL = weight 0

@@ -41,42 +41,6 @@ namespace {
 // compiler sinks each staged field's stencil arithmetic to the end of the
 // kernel, where the results are used, and keeps every loaded LDS value alive
 // across all later barriers (hundreds of spilled registers).
-typedef __attribute__((address_space(3))) void lds_void;
-
-// s_waitcnt immediates (gfx9 encoding): vmcnt <= n with the other counters
-// unconstrained, and lgkmcnt = 0
-#define VM_N(n) ((((n) & 0xF) | ((((n) >> 4) & 0x3) << 14)) | (0x7 << 4) | (0xF << 8))
-#define LGKM0 (0xF | (0x3 << 14) | (0x7 << 4))
-
-// One LDS-DMA load: every lane moves the 16 bytes at `src` to LDS address
-// `dst` + 16 * lane (dst uniform).  Issued as inline assembly so that the
-// compiler's wait-count insertion does not see it: it would otherwise treat
-// every outstanding tile load as a pending write to any LDS address and drain
-// all of them (vmcnt(0)) before the next LDS read, which defeats loading
-// tiles ahead of their use.  The kernel waits for these loads itself
-// (per-field vmcnt waits and a barrier before a tile is read); the loads
-// complete in issue order with the compiler's own loads, so its waits for
-// those stay correct (they may only wait longer).
-__device__ __forceinline__ void lds_dma16(const void* src, lds_void* dst)
-{
-    const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long)dst);
-    __asm__ volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-                     :
-                     : "v"(src), "s"(m)
-                     : "memory", "m0");
-}
-
-// Workgroup barrier without a memory fence (s_barrier alone): the caller
-// waits for exactly the LDS writes it needs with s_waitcnt, so that later
-// tiles' loads stay in flight across it.  The empty asm statements keep the
-// compiler from moving memory accesses across the barrier.
-__device__ __forceinline__ void bar()
-{
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    __asm__ volatile("" ::: "memory");
-}
-
 template <typename R>
 __device__ __forceinline__ void pin(R& x)
 {
@@ -303,15 +267,18 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
     // they take no registers across the staging sequence.  Slot s of thread
     // tid is park[s * NT + tid] (consecutive lanes, consecutive words).
     // The LDS share of one block (160 KB over the blocks a CU holds at WAVES
-    // waves per SIMD) holds NBUF tile buffers (the DMA path keeps NBUF - 1
-    // fields in flight ahead of the one in use; measured: more than two
-    // ahead gains nothing and costs park slots) and the park slots; slots
-    // beyond the share stay in registers.
+    // waves per SIMD) holds NBUF tile buffers -- the DMA path keeps NBUF - 1
+    // fields in flight ahead of the one in use -- and the park slots; slots
+    // beyond the share stay in registers.  One wave per SIMD has no other
+    // wave to cover a late tile, so it gets as many buffers as fit next to all
+    // 16 park slots (at most 7); two-wave shapes keep 3 so that their park
+    // slots stay in LDS.
     constexpr int BPC = (WAVES * 4 * 64) / NT > 0 ? (WAVES * 4 * 64) / NT : 1;  // blocks per CU
     constexpr int BUDGET = 163840 / BPC - 512;
     constexpr int PLANES = (int)sizeof(R) * (T::GYN + T::GZN);
     constexpr int BUFB = (int)sizeof(TT) * TNP;
-    constexpr int NBUF = DMA ? 3 : 1;
+    constexpr int NB_FIT = (BUDGET - PLANES - 16 * NT * (int)sizeof(R)) / BUFB;
+    constexpr int NBUF = !DMA ? 1 : (WAVES > 1 || NB_FIT < 3) ? 3 : (NB_FIT > 7 ? 7 : NB_FIT);
     constexpr int DIST = NBUF - 1;  // fields in flight ahead of the staged one
     static_assert(!DMA || DIST * NR <= 63, "outstanding loads beyond the vmcnt range");
     constexpr int PARK_FIT = (BUDGET - PLANES - NBUF * BUFB) / (NT * (int)sizeof(R));
@@ -404,31 +371,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         fc.imix[0] = uniform(R(1.0 / (144.0 * B.h[0] * B.h[1])));
         fc.imix[1] = uniform(R(1.0 / (144.0 * B.h[0] * B.h[2])));
         fc.imix[2] = uniform(R(1.0 / (144.0 * B.h[1] * B.h[2])));
-
-        // centre values needed before staging (the flat state on idle lanes
-        // keeps the algebra finite); the others are taken from the tile
-        auto centre = [&](int f) { return valid ? R(B.u_in[f * sf + p]) : R(flat_of(f)); };
-        R gt[6], gu[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gt[q] = centre(F_GT + q);
-        inv6(gt, gu);
-        const R be[3] = {centre(F_BE), centre(F_BE + 1), centre(F_BE + 2)};
-        // At at the point is needed after the metric.  With one wave per SIMD
-        // it is loaded here, ahead of the tile loads, so that waiting for it
-        // never waits for those; with two, registers are too scarce for that.
-        constexpr bool EARLY_AT = WAVES == 1;
-        R At[6];
-        if constexpr (EARLY_AT) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) At[q] = centre(F_AT + q);
-        }
-        // advection + dissipation weights of the odd (O) and even (KO6) parts, per direction
-        R wodd[3], wev[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            wodd[d] = be[d] * fc.i24h[d];
-            wev[d] = (be[d] < R(0) ? -be[d] : be[d]) * fc.i24h[d] + fc.ko[d];
-        }
 
         // Field order of the staging sequence.
         constexpr int NSEQ = 25;
@@ -546,6 +488,45 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             prefetch(seq(0));
         }
 
+        enum : int { P_AKGT = 0, P_AKGAM = 6, P_AKBE = 9, P_KKH = 12, P_KTH = 13, P_KAL = 14, P_KW = 15 };
+        constexpr int P_AT0 = P_AKGAM;  // At at the point, until the Gt fields are staged (slots 6-11)
+        R park_r[16];
+        auto put_lds = [&](int slot, R v) {
+            if (slot < NPARK)
+                park[slot * NT + tid] = v;
+            else
+                park_r[slot] = v;
+        };
+        auto get_lds = [&](int slot) { return slot < NPARK ? park[slot * NT + tid] : park_r[slot]; };
+
+        // Centre values needed before staging (the flat state on idle lanes
+        // keeps the algebra finite); the others are taken from the tiles.
+        // They are loaded after the first tiles' loads, so that waiting for
+        // them (the compiler waits for all of its loads at their first use)
+        // is one round trip for both.  At is needed after the metric; it is
+        // parked in the slots that stay free until the Gt fields are staged.
+        auto centre = [&](int f) { return valid ? R(B.u_in[f * sf + p]) : R(flat_of(f)); };
+        R gt[6], gu[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gt[q] = centre(F_GT + q);
+        const R be[3] = {centre(F_BE), centre(F_BE + 1), centre(F_BE + 2)};
+        {
+            R At0[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) At0[q] = centre(F_AT + q);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) put_lds(P_AT0 + q, At0[q]);
+        }
+        inv6(gt, gu);
+        // advection + dissipation weights of the odd (O) and even (KO6) parts, per direction
+        R wodd[3], wev[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            wodd[d] = be[d] * fc.i24h[d];
+            wev[d] = (be[d] < R(0) ? -be[d] : be[d]) * fc.i24h[d] + fc.ko[d];
+        }
+
+
         // centre value of the staged field (its flat value restored when the
         // register path staged it in float32)
         auto tval = [&](int f) {
@@ -612,16 +593,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // the staging sequence (this decides how many waves a SIMD can hold).
         // Staging order: gt, Gt, W, alpha, Khat, Theta, beta, At, B.
         double k[NF];  // completed right-hand sides, stored by finish_point
-        enum : int { P_AKGT = 0, P_AKGAM = 6, P_AKBE = 9, P_KKH = 12, P_KTH = 13, P_KAL = 14, P_KW = 15 };
-        R park_r[16];
-        auto put_lds = [&](int slot, R v) {
-            if (slot < NPARK)
-                park[slot * NT + tid] = v;
-            else
-                park_r[slot] = v;
-        };
-        auto get_lds = [&](int slot) { return slot < NPARK ? park[slot * NT + tid] : park_r[slot]; };
-
         // --- conformal metric: first derivatives kept, second derivatives
         //     folded into -1/2 gt^lm d_l d_m gt_ij
         R Rt[6];
@@ -694,12 +665,10 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // --- At at the point (its stencils are staged near the end): At^ij,
         //     At_ij At^ij and Gamma^a_jk At^jk now, so that C2 dies with the
         //     lapse below
-        R Auu[6], AA, nG[3];  // nG: Gt source without advection/dissipation
+        R At[6], Auu[6], AA, nG[3];  // nG: Gt source without advection/dissipation
         {
-            if constexpr (!EARLY_AT) {
 #pragma unroll
-                for (int q = 0; q < 6; ++q) At[q] = centre(F_AT + q);
-            }
+            for (int q = 0; q < 6; ++q) At[q] = get_lds(P_AT0 + q);
             R Au[3][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i)

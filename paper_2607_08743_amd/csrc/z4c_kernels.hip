@@ -181,7 +181,7 @@ __device__ __forceinline__ void enforce(double* gt, double* At)
 // returns the right-hand side of field f.  Fields outside gt/At are stored as
 // soon as they are updated; the 12 metric and curvature values wait for the
 // enforcement.
-template <typename KF>
+template <bool BULK, typename KF>
 __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stage, KF kf, size_t p)
 {
     const size_t sf = (size_t)B.sf;
@@ -192,24 +192,35 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     }
     const double dt = B.dt;
     const double c = stage == 3 ? dt : (stage == 4 ? dt / 6.0 : 0.5 * dt);
+    // stage 1 and 4 update u_in and acc, stages 2 and 3 update u_n (and acc)
+    const double* base = stage == 1 ? B.u_in : (stage == 4 ? B.acc : B.u_n);
+    const bool upd = stage == 2 || stage == 3;
+    // BULK: every load is issued before the first is used (one round trip
+    // per point; the caller has the registers to spare); otherwise five
+    // fields at a time.  The empty asm keeps the loads from being hoisted
+    // above this point, into code that has no registers for them.
+    double b0[BULK ? NF : 1], b1[BULK ? NF : 1];
+    __asm__ volatile("" ::: "memory");
+    if constexpr (BULK) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) b0[f] = base[f * sf + p];
+        if (upd) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) b1[f] = B.acc[f * sf + p];
+        }
+    }
     double gt[6], At[6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        // a few fields at a time: the loads of all 25 hoisted to the top
-        // would hold ~100 registers at once
-        if (f % 5 == 0) __asm__ volatile("" ::: "memory");
+        if constexpr (!BULK)
+            if (f % 5 == 0) __asm__ volatile("" ::: "memory");
         const double k = kf(f);
-        double v;
-        if (stage == 1) {
-            const double u0 = B.u_in[f * sf + p];
-            v = u0 + c * k;
+        const double u0 = BULK ? b0[f] : base[f * sf + p];
+        const double v = u0 + c * k;
+        if (stage == 1)
             B.acc[f * sf + p] = u0 + (dt / 6.0) * k;
-        } else if (stage == 4) {
-            v = B.acc[f * sf + p] + c * k;
-        } else {
-            v = B.u_n[f * sf + p] + c * k;
-            B.acc[f * sf + p] += (dt / 3.0) * k;
-        }
+        else if (upd)
+            B.acc[f * sf + p] = (BULK ? b1[f] : B.acc[f * sf + p]) + (dt / 3.0) * k;
         if (f >= F_GT && f < F_GT + 6)
             gt[f - F_GT] = v;
         else if (f >= F_AT && f < F_AT + 6)
@@ -897,7 +908,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         k[F_W] = double(get_lds(P_KW));
 
         if (!valid) continue;  // no barrier below this point
-        finish_point(B, mode, stage, [&](int f) { return k[f]; }, p);
+        finish_point<true>(B, mode, stage, [&](int f) { return k[f]; }, p);
     }
 }
 
@@ -1089,7 +1100,7 @@ __global__ void __launch_bounds__(256) sommerfeld_ghosts(BoxSet set, int mode, i
                         + (z * ir) * dsomm(u, p, k, Nz, (long)Nx * Ny, B.h[2]);
         return -dr - (u[p] - flat_of(f)) * ir;
     };
-    finish_point(B, mode, stage, kf, p);
+    finish_point<false>(B, mode, stage, kf, p);
 }
 
 __global__ void __launch_bounds__(256) zero_ghost_rhs(BoxSet set)

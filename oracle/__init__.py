@@ -110,10 +110,14 @@ def lib():
         L.oz_restrict.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_int, ip,
                                   ctypes.c_int]
         L.oz_transfer_weights.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
+        L.oz_bo_advance_moving.argtypes = [ctypes.POINTER(OzLevel), ctypes.c_int, ctypes.c_int, dp,
+                                           ctypes.POINTER(OzParams), ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        L.oz_interp_beta.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp, dp, dp, dp]
+        L.oz_regrid.argtypes = [ctypes.POINTER(OzLevel), ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
         L.oz_mixed_2d.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         for name in ("oz_rhs", "oz_rhs_points", "oz_apply_ghosts", "oz_enforce", "oz_stage_points", "oz_rk4",
                      "oz_stencil_1d", "oz_mixed_2d", "oz_constraints", "oz_bo_advance", "oz_prolong", "oz_restrict",
-                     "oz_transfer_weights"):
+                     "oz_transfer_weights", "oz_bo_advance_moving", "oz_interp_beta", "oz_regrid"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -238,10 +242,7 @@ class Level:
         self.has_prev = 0
 
 
-def bo_advance(levels, dt0, nsteps, p=None, nthreads=None) -> None:
-    """Berger-Oliger advance of the hierarchy by nsteps coarse steps of dt0
-    (level l takes 2^l steps of dt0 / 2^l each)."""
-    p = p or params()
+def _level_array(levels):
     arr = (OzLevel * len(levels))()
     for L, lv in zip(arr, levels):
         g = lv.grid
@@ -255,10 +256,62 @@ def bo_advance(levels, dt0, nsteps, p=None, nthreads=None) -> None:
         L.F[:] = list(lv.F)
         L.bc = int(g.bc)
         L.has_prev = lv.has_prev
-    _check(lib().oz_bo_advance(arr, len(levels), ctypes.byref(p), float(dt0), int(nsteps),
-                               nthreads or threads_default()), "bo_advance")
+    return arr
+
+
+def _level_back(arr, levels):
+    from dataclasses import replace
     for L, lv in zip(arr, levels):
         lv.has_prev = L.has_prev
+        lv.F = tuple(int(x) for x in L.F)
+        x0 = tuple(float(x) for x in L.x0)
+        if x0 != tuple(float(x) for x in lv.grid.x0):
+            lv.grid = replace(lv.grid, x0=x0)
+
+
+def bo_advance(levels, dt0, nsteps, p=None, nthreads=None) -> None:
+    """Berger-Oliger advance of the hierarchy by nsteps coarse steps of dt0
+    (level l takes 2^l steps of dt0 / 2^l each)."""
+    p = p or params()
+    arr = _level_array(levels)
+    _check(lib().oz_bo_advance(arr, len(levels), ctypes.byref(p), float(dt0), int(nsteps),
+                               nthreads or threads_default()), "bo_advance")
+    _level_back(arr, levels)
+
+
+def bo_advance_moving(levels, lmove, xp, dt0, nsteps, p=None, nthreads=None) -> np.ndarray:
+    """As bo_advance, with levels lmove.. following the puncture that starts
+    at xp (tracked on the finest level, dx/dt = -beta); after every coarse
+    step each moving patch shifts by two of its cells toward the puncture
+    when its centre is more than two cells away.  Returns the final
+    puncture position; level grids and F are updated in place."""
+    p = p or params()
+    x = np.ascontiguousarray(xp, dtype=np.float64).copy()
+    arr = _level_array(levels)
+    _check(lib().oz_bo_advance_moving(arr, len(levels), int(lmove), _dp(x), ctypes.byref(p), float(dt0),
+                                      int(nsteps), nthreads or threads_default()), "bo_advance_moving")
+    _level_back(arr, levels)
+    return x
+
+
+def regrid(levels, lmove, xp, nthreads=None) -> None:
+    """One regrid of the moving levels toward xp, without a time step."""
+    x = np.ascontiguousarray(xp, dtype=np.float64)
+    arr = _level_array(levels)
+    _check(lib().oz_regrid(arr, len(levels), int(lmove), _dp(x), nthreads or threads_default()), "regrid")
+    _level_back(arr, levels)
+
+
+def interp_beta(u, g, x) -> np.ndarray:
+    """4-point Lagrange interpolation of the shift of state u (grid g) at x."""
+    _state(u)
+    nn, _k1 = _ivec(g.n)
+    h = np.ascontiguousarray(g.h, dtype=np.float64)
+    x0 = np.ascontiguousarray(g.x0, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    b = np.zeros(3)
+    _check(lib().oz_interp_beta(_dp(u), u[0].size, nn, int(g.ng), _dp(h), _dp(x0), _dp(xx), _dp(b)), "interp_beta")
+    return b
 
 
 def prolong(parent_levels, wt, np_, ngp, uc, nc, ngc, F, nthreads=None) -> None:

@@ -1060,12 +1060,13 @@ static void fill_level_ghosts(double* u, const grid* g, const parent_ref* pr, do
 }
 
 static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt, int nt, const parent_ref* pr,
-                    double theta0);
+                    double theta0, double* xp);
+static int interp_beta(const oz_level* L, const double x[3], double b[3]);
 
 /* one RK4 step of level l (the textbook form of oz_rk4), ghosts of every
    stage input filled at that stage's time, then its children */
 static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt, int nt, const parent_ref* pr,
-                    double theta0)
+                    double theta0, double* xp)
 {
     oz_level* L = &lv[l];
     grid g;
@@ -1085,6 +1086,17 @@ static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt
     const double cstage[3] = {0.5, 0.5, 1.0};
     fill_level_ghosts(L->u, &g, pr, theta0, nt);
     memcpy(cur, L->u, bytes);
+    /* puncture tracking on the finest level: Heun's method for dx/dt = -beta,
+       beta at the start of the step at x, at its end at the predicted point */
+    const int track = xp && l == nlev - 1;
+    double b0[3], xs[3];
+    if (track) {
+        if (interp_beta(L, xp, b0)) {
+            rc = -2;
+            goto done;
+        }
+        for (int d = 0; d < 3; ++d) xs[d] = xp[d] - dt * b0[d];
+    }
     for (int s = 0; s < 4; ++s) {
         const double* src = s == 0 ? L->u : us;
         rhs_all(src, kk[s], &g, p, nt);
@@ -1114,10 +1126,18 @@ static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt
                 enforce_point(L->u, sf, q);
             }
     fill_level_ghosts(L->u, &g, pr, theta0 + 0.5, nt);
+    if (track) {
+        double b1[3];
+        if (interp_beta(L, xs, b1)) {
+            rc = -2;
+            goto done;
+        }
+        for (int d = 0; d < 3; ++d) xp[d] = xp[d] - 0.5 * dt * (b0[d] + b1[d]);
+    }
     if (l + 1 < nlev) {
         oz_level* C = &lv[l + 1];
         parent_ref me = {&g, {L->has_prev ? L->prev : NULL, cur, L->u}, L->has_prev, C->F};
-        for (int m = 0; m < 2 && !rc; ++m) rc = bo_level(lv, nlev, l + 1, p, 0.5 * dt, nt, &me, 0.5 * m);
+        for (int m = 0; m < 2 && !rc; ++m) rc = bo_level(lv, nlev, l + 1, p, 0.5 * dt, nt, &me, 0.5 * m, xp);
         if (!rc) {
             grid gc;
             make_level_grid(&gc, C, BC_COPY);
@@ -1170,7 +1190,7 @@ int oz_bo_advance(oz_level* lv, int nlev, const oz_params* p, double dt0, int ns
     if (!p || !(dt0 > 0) || nsteps < 0 || check_levels(lv, nlev)) return -1;
     int nt = nthreads < 1 ? 1 : nthreads;
     for (int s = 0; s < nsteps; ++s) {
-        int rc = bo_level(lv, nlev, 0, p, dt0, nt, NULL, 0.0);
+        int rc = bo_level(lv, nlev, 0, p, dt0, nt, NULL, 0.0, NULL);
         if (rc) return rc;
     }
     return 0;
@@ -1218,4 +1238,157 @@ int oz_transfer_weights(double theta, int quadratic, double* wt3, double* prolon
     prolong_1d(1, 0, prolong_odd6);
     lagrange_weights(nodes, 4, 0.0, restrict4);
     return 0;
+}
+
+
+/* ------------------------------------------------------------------ */
+/* Moving levels (Sec. 2.2.1): the finest level tracks the puncture    */
+/* with dx^i/dt = -beta^i (beta interpolated at the puncture); after   */
+/* each coarse step every moving patch whose centre is more than two   */
+/* of its cells from the puncture (per direction) shifts by two of its */
+/* cells -- one parent cell, so parent and child cell faces stay       */
+/* aligned -- toward it; its cells that were already covered keep      */
+/* their values, newly covered ones are prolonged from the parent.     */
+/* Readings: one patch per level tracking one puncture; Heun's method  */
+/* for the track with beta from the finest level by 4-point Lagrange   */
+/* interpolation in each direction; after a shift the level's earlier  */
+/* time level is dropped (its child interpolates linearly once).       */
+/* ------------------------------------------------------------------ */
+
+/* 4-point Lagrange interpolation of beta at x from level L (nodes: the
+   cell centres i0-1 .. i0+2 around x in each direction) */
+static int interp_beta(const oz_level* L, const double x[3], double b[3])
+{
+    static const double nodes[4] = {-1.0, 0.0, 1.0, 2.0};
+    grid g;
+    make_level_grid(&g, L, BC_COPY);
+    double w[3][4];
+    int lo[3];
+    for (int d = 0; d < 3; ++d) {
+        const double sc = (x[d] - L->x0[d]) / L->h[d]; /* active-index coordinate */
+        const int i0 = (int)floor(sc);
+        lo[d] = i0 - 1 + L->ng;
+        if (lo[d] < 0 || lo[d] + 3 >= g.N[d]) return -1;
+        lagrange_weights(nodes, 4, sc - i0, w[d]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i)
+                    s += w[2][k] * w[1][j] * w[0][i] * L->u[(IBE + a) * L->sf + lin(&g, lo[0] + i, lo[1] + j, lo[2] + k)];
+        b[a] = s;
+    }
+    return 0;
+}
+
+/* shift of level l toward the puncture xp: -1, 0 or +1 parent cells per direction */
+static int patch_shift(const oz_level* L, const double xp[3], int sh[3])
+{
+    int any = 0;
+    for (int d = 0; d < 3; ++d) {
+        const double c = L->x0[d] + 0.5 * (L->n[d] - 1) * L->h[d];
+        sh[d] = xp[d] - c > 2.0 * L->h[d] ? 1 : (xp[d] - c < -2.0 * L->h[d] ? -1 : 0);
+        any |= sh[d] != 0;
+    }
+    return any;
+}
+
+static int regrid(oz_level* lv, int nlev, int lmove, const double xp[3], int nt)
+{
+    for (int l = lmove; l < nlev; ++l) {
+        oz_level* L = &lv[l];
+        const oz_level* P = &lv[l - 1];
+        int sh[3];
+        if (!patch_shift(L, xp, sh)) continue;
+        grid g, gp;
+        make_level_grid(&g, L, BC_COPY);
+        make_level_grid(&gp, P, BC_COPY);
+        const size_t bytes = (size_t)NF * (size_t)L->sf * sizeof(double);
+        double* nu = malloc(bytes);
+        if (!nu) return -3;
+        memcpy(nu, L->u, bytes);
+        int F[3];
+        for (int d = 0; d < 3; ++d) F[d] = L->F[d] + sh[d];
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int k = 0; k < L->n[2]; ++k)
+            for (int j = 0; j < L->n[1]; ++j)
+                for (int i = 0; i < L->n[0]; ++i) {
+                    const int a[3] = {i, j, k};
+                    int src[3], inside = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        src[d] = a[d] + 2 * sh[d];
+                        inside &= src[d] >= 0 && src[d] < L->n[d];
+                    }
+                    const long q = lin(&g, i + L->ng, j + L->ng, k + L->ng);
+                    if (inside) {
+                        const long qs = lin(&g, src[0] + L->ng, src[1] + L->ng, src[2] + L->ng);
+                        for (int f = 0; f < NF; ++f) nu[f * L->sf + q] = L->u[f * L->sf + qs];
+                        continue;
+                    }
+                    double wx[6], wy[6], wz[6];
+                    const int lx = prolong_1d(i, F[0], wx) + P->ng;
+                    const int ly = prolong_1d(j, F[1], wy) + P->ng;
+                    const int lz = prolong_1d(k, F[2], wz) + P->ng;
+                    for (int f = 0; f < NF; ++f) {
+                        double s = 0.0;
+                        for (int c = 0; c < 6; ++c)
+                            for (int b = 0; b < 6; ++b)
+                                for (int m = 0; m < 6; ++m)
+                                    s += wz[c] * wy[b] * wx[m] * P->u[f * P->sf + lin(&gp, lx + m, ly + b, lz + c)];
+                        nu[f * L->sf + q] = s;
+                    }
+                }
+        memcpy(L->u, nu, bytes);
+        free(nu);
+        for (int d = 0; d < 3; ++d) {
+            L->F[d] = F[d];
+            L->x0[d] += 2.0 * sh[d] * L->h[d];
+            if (l + 1 < nlev) lv[l + 1].F[d] -= 2 * sh[d];
+        }
+        L->has_prev = 0;
+    }
+    return check_levels(lv, nlev) ? -4 : 0;
+}
+
+/* Advance a hierarchy whose levels lmove.. follow the puncture at xp (in/out):
+   per coarse step, the subcycled step with tracking, then the regrid. */
+int oz_bo_advance_moving(oz_level* lv, int nlev, int lmove, double* xp, const oz_params* p, double dt0, int nsteps,
+                         int nthreads)
+{
+    if (!xp || lmove < 1 || lmove >= nlev) return -1;
+    if (!p || !(dt0 > 0) || nsteps < 0 || check_levels(lv, nlev)) return -1;
+    int nt = nthreads < 1 ? 1 : nthreads;
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = bo_level(lv, nlev, 0, p, dt0, nt, NULL, 0.0, xp);
+        if (rc) return rc;
+        if ((rc = regrid(lv, nlev, lmove, xp, nt))) return rc;
+    }
+    return 0;
+}
+
+/* probe: 4-point Lagrange interpolation of the shift of one level at x */
+int oz_interp_beta(const double* u, long sf, const int* n, int ng, const double* h, const double* x0, const double* x,
+                   double* b)
+{
+    if (!u || !n || !h || !x0 || !x || !b) return -1;
+    oz_level L;
+    memset(&L, 0, sizeof(L));
+    L.u = (double*)u;
+    L.prev = (double*)u;
+    L.sf = sf;
+    L.ng = ng;
+    for (int d = 0; d < 3; ++d) {
+        L.n[d] = n[d];
+        L.h[d] = h[d];
+        L.x0[d] = x0[d];
+    }
+    return interp_beta(&L, x, b);
+}
+
+/* probe: one regrid of the moving levels toward xp (no time step) */
+int oz_regrid(oz_level* lv, int nlev, int lmove, const double* xp, int nthreads)
+{
+    if (!xp || lmove < 1 || lmove >= nlev || check_levels(lv, nlev)) return -1;
+    return regrid(lv, nlev, lmove, xp, nthreads < 1 ? 1 : nthreads);
 }

@@ -261,6 +261,23 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
  * graph on first use and replayed. */
 int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream);
 
+/* Moving levels (Sec. 2.2.1): levels lmove.. (1 <= lmove < nlev) follow the
+ * puncture that starts at xp (3 doubles, host).  On the finest level it is
+ * tracked with dx^i/dt = -beta^i (Heun's method per step, beta by 4-point
+ * Lagrange interpolation in each direction).  After every coarse step
+ * z4c_hier_advance reads it back (a stream synchronisation) and shifts each
+ * moving patch whose centre is more than two of its cells from it, per
+ * direction, by two cells toward it -- one parent cell, so F moves by one
+ * and x0 by one parent dx; cells it covered before keep their values, newly
+ * covered ones are prolonged from the parent.  A shift that would take a
+ * patch's stencils out of its parent fails with Z4C_EINVAL.  Allocates 80
+ * bytes of device memory. */
+int z4c_hier_set_moving(void* hier, int lmove, const double* xp);
+
+/* Current puncture position (xp, 3 doubles) and, if not NULL, every level's
+ * F and x0 (3 per level); synchronises with the device. */
+int z4c_hier_puncture(void* hier, double* xp, int* F, double* x0);
+
 int z4c_hier_destroy(void* hier);
 
 /* Static description of a status code, and the detail of the last failing

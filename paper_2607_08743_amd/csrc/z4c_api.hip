@@ -636,7 +636,72 @@ struct z4c_hier_s {
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipStream_t capture;
+    int lmove;      // first moving level (0: none)
+    double* track;  // device: puncture x[3], b0[3], xs[3], error flag
 };
+
+// Geometry of level x against its parent P: 2:1 spacing, lower faces on
+// parent cell F, every ghost's prolongation stencil in P's active cells.
+static int hier_check_level(const z4c_level& x, const z4c_level& P, const std::string& tag)
+{
+    for (int d = 0; d < 3; ++d) {
+        if (x.n[d] % 2) return fail(Z4C_EINVAL, tag + "active extents must be even");
+        if (x.dx[d] != 0.5 * P.dx[d]) return fail(Z4C_EINVAL, tag + "dx must be half the parent's");
+        const double want = P.x0[d] + (x.F[d] - 0.25) * P.dx[d];
+        if (std::fabs(x.x0[d] - want) > 1e-9 * P.dx[d])
+            return fail(Z4C_EINVAL, tag + "x0 does not put the lower faces on parent cell F");
+        // first / last parent cell read by the ghost stencils: floor(a/2) - 3 for
+        // a = -ng, and floor(a/2) + 3 for a = n + ng - 1
+        const int a_lo = -x.ng, a_hi = x.n[d] + x.ng - 1;
+        const int lo = x.F[d] + (a_lo >= 0 ? a_lo / 2 : -((1 - a_lo) / 2)) - 3;
+        const int hi = x.F[d] + a_hi / 2 + 3;
+        if (lo < 0 || hi >= P.n[d]) return fail(Z4C_EINVAL, tag + "prolongation stencil leaves the parent's active cells");
+    }
+    return Z4C_OK;
+}
+
+// (Re)build the stage and ghost-fill sets of level l from its geometry.
+static void hier_build_sets(z4c_hier_s* H, int l)
+{
+    const TileEntry* tab = nullptr;
+    tile_table(&tab);
+    HierLevel& L = H->lv[l];
+    const double dt = H->dt0 / (double)(1L << l);
+    double* ins[4] = {L.L.u, L.L.u_a, L.L.u_b, L.L.u_a};
+    double* outs[4] = {L.L.u_a, L.L.u_b, L.L.u_a, L.L.u};
+    for (int st = 0; st < 4; ++st) {
+        BoxDev d = make_box(L.L.n, L.L.ng, L.L.bc, L.L.sf, L.L.dx, L.L.x0, dt);
+        d.u_in = ins[st];
+        d.u_n = L.L.u;
+        d.acc = L.L.acc;
+        d.u_out = outs[st];
+        d.shell = L.shell;
+        BoxSet& F = L.fused[st];
+        F = BoxSet{};
+        F.nbox = 1;
+        F.box[0] = d;
+        finalize_set(F, tab[H->tile_index].tile);
+        L.fill[st] = F;
+    }
+}
+
+static hipError_t hier_track(z4c_hier_s* H, int l, int mode, hipStream_t s)
+{
+    const HierLevel& L = H->lv[l];
+    TrackArgs a{};
+    a.state = H->track;
+    a.u = L.L.u;
+    a.sf = L.L.sf;
+    for (int d = 0; d < 3; ++d) {
+        a.N[d] = L.L.n[d] + 2 * L.L.ng;
+        a.x0[d] = L.L.x0[d];
+        a.h[d] = L.L.dx[d];
+    }
+    a.ng = L.L.ng;
+    a.dt = H->dt0 / (double)(1L << l);
+    a.mode = mode;
+    return launch_track(a, s);
+}
 
 // Lagrange weights of the parent time levels (nodes -1, 0, 1 in units of
 // the parent step) at theta; linear in (0, 1) without an earlier level.
@@ -721,12 +786,15 @@ static hipError_t hier_level_step(z4c_hier_s* H, int l, double theta0, hipStream
     if (l > 0 && theta0 == 0.0 && (e = hier_prolong(H, l, 0.0, s)) != hipSuccess) return e;
     if ((e = fill(0)) != hipSuccess) return e;
     if (l + 1 < nlev && (e = launch_copy(L.L.cur, L.L.u, n, s)) != hipSuccess) return e;
+    const bool track = H->lmove > 0 && l == nlev - 1;
+    if (track && (e = hier_track(H, l, 0, s)) != hipSuccess) return e;
     if ((e = stage(0)) != hipSuccess) return e;
     if (l > 0 && (e = hier_prolong(H, l, theta0 + 0.25, s)) != hipSuccess) return e;
     if ((e = fill(1)) != hipSuccess || (e = stage(1)) != hipSuccess) return e;
     if ((e = fill(2)) != hipSuccess || (e = stage(2)) != hipSuccess) return e;
     if (l > 0 && (e = hier_prolong(H, l, theta0 + 0.5, s)) != hipSuccess) return e;
     if ((e = fill(3)) != hipSuccess || (e = stage(3)) != hipSuccess) return e;
+    if (track && (e = hier_track(H, l, 1, s)) != hipSuccess) return e;
     if (l + 1 < nlev) {
         if ((e = hier_level_step(H, l + 1, 0.0, s)) != hipSuccess) return e;
         if ((e = hier_level_step(H, l + 1, 0.5, s)) != hipSuccess) return e;
@@ -752,6 +820,7 @@ static void hier_free(z4c_hier_s* H)
     hier_drop_graph(H);
     for (HierLevel& L : H->lv)
         if (L.shell) (void)hipFree(L.shell);
+    if (H->track) (void)hipFree(H->track);
     if (H->capture) (void)hipStreamDestroy(H->capture);
     delete H;
 }
@@ -783,21 +852,7 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
             continue;
         }
         if (x.bc != Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "levels >= 1 take Z4C_BC_COPY (filled from the parent)");
-        const z4c_level& P = levels[l - 1];
-        for (int d = 0; d < 3; ++d) {
-            if (x.n[d] % 2) return fail(Z4C_EINVAL, tag + "active extents must be even");
-            if (x.dx[d] != 0.5 * P.dx[d]) return fail(Z4C_EINVAL, tag + "dx must be half the parent's");
-            const double want = P.x0[d] + (x.F[d] - 0.25) * P.dx[d];
-            if (std::fabs(x.x0[d] - want) > 1e-9 * P.dx[d])
-                return fail(Z4C_EINVAL, tag + "x0 does not put the lower faces on parent cell F");
-            // first / last parent cell read by the ghost stencils: floor(a/2) - 3 for
-            // a = -ng, and floor(a/2) + 3 for a = n + ng - 1
-            const int a_lo = -x.ng, a_hi = x.n[d] + x.ng - 1;
-            const int lo = x.F[d] + (a_lo >= 0 ? a_lo / 2 : -((1 - a_lo) / 2)) - 3;
-            const int hi = x.F[d] + a_hi / 2 + 3;
-            if (lo < 0 || hi >= P.n[d])
-                return fail(Z4C_EINVAL, tag + "prolongation stencil leaves the parent's active cells");
-        }
+        if ((rc = hier_check_level(x, levels[l - 1], tag))) return rc;
     }
     int pers = 1;
     int ti;
@@ -832,25 +887,106 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
                 return fail(Z4C_ENOMEM, "ghost shell allocation failed");
             }
         }
-        const double dt = dt0 / (double)(1L << l);
-        double* ins[4] = {L.L.u, L.L.u_a, L.L.u_b, L.L.u_a};
-        double* outs[4] = {L.L.u_a, L.L.u_b, L.L.u_a, L.L.u};
-        for (int st = 0; st < 4; ++st) {
-            BoxDev d = make_box(L.L.n, L.L.ng, L.L.bc, L.L.sf, L.L.dx, L.L.x0, dt);
-            d.u_in = ins[st];
-            d.u_n = L.L.u;
-            d.acc = L.L.acc;
-            d.u_out = outs[st];
-            d.shell = L.shell;
-            BoxSet& F = L.fused[st];
-            F = BoxSet{};
-            F.nbox = 1;
-            F.box[0] = d;
-            finalize_set(F, tab[ti].tile);
-            L.fill[st] = F;
-        }
+        hier_build_sets(H, l);
     }
     *hier = H;
+    return Z4C_OK;
+}
+
+// capture one coarse step on the private stream (every parent holds an
+// earlier level, so the schedule no longer changes from step to step)
+static int hier_capture(z4c_hier_s* H)
+{
+    hipError_t e;
+    if (!H->capture && (e = hipStreamCreateWithFlags(&H->capture, hipStreamNonBlocking)) != hipSuccess) {
+        H->capture = nullptr;
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    // captured on a private stream; the instantiated graph runs on the caller's
+    if ((e = hipStreamBeginCapture(H->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hier_level_step(H, 0, 0.0, H->capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(H->capture, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "hierarchy step launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    H->graph = g;
+    H->exec = x;
+    return Z4C_OK;
+}
+
+// After a coarse step: read the puncture back and shift every moving patch
+// whose centre is more than two of its cells away from it (per direction)
+// by two cells toward it; cells it covered before keep their values, new
+// ones are prolonged from the (already shifted) parent.  The captured step
+// is dropped when a patch moved (its geometry is baked into the graph).
+static int hier_regrid(z4c_hier_s* H, hipStream_t s)
+{
+    hipError_t e;
+    double st[10];
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if ((e = hipMemcpy(st, H->track, sizeof(st), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy (puncture)");
+    if (st[9] != 0.0) return fail(Z4C_EINVAL, "the puncture left the finest level");
+    const int nlev = (int)H->lv.size();
+    bool moved = false;
+    for (int l = H->lmove; l < nlev; ++l) {
+        HierLevel& L = H->lv[l];
+        int sh[3];
+        bool any = false;
+        for (int d = 0; d < 3; ++d) {
+            const double c = L.L.x0[d] + 0.5 * (L.L.n[d] - 1) * L.L.dx[d];
+            sh[d] = st[d] - c > 2.0 * L.L.dx[d] ? 1 : (st[d] - c < -2.0 * L.L.dx[d] ? -1 : 0);
+            any |= sh[d] != 0;
+        }
+        if (!any) continue;
+        z4c_level nl = L.L;
+        for (int d = 0; d < 3; ++d) {
+            nl.F[d] += sh[d];
+            nl.x0[d] += 2.0 * sh[d] * L.L.dx[d];
+        }
+        int rc;
+        const std::string tag = "regrid of level " + std::to_string(l) + ": ";
+        if ((rc = hier_check_level(nl, H->lv[l - 1].L, tag))) return rc;
+        if (l + 1 < nlev) {
+            z4c_level cl = H->lv[l + 1].L;
+            for (int d = 0; d < 3; ++d) cl.F[d] -= 2 * sh[d];
+            if ((rc = hier_check_level(cl, nl, tag + "child: "))) return rc;
+        }
+        const HierLevel& P = H->lv[l - 1];
+        ShiftArgs a{};
+        a.uc = L.L.u;
+        a.out = L.L.u_a;
+        a.sfc = L.L.sf;
+        a.ngc = L.L.ng;
+        a.up = P.L.u;
+        a.sfp = P.L.sf;
+        a.ngp = P.L.ng;
+        for (int d = 0; d < 3; ++d) {
+            a.Nc[d] = L.L.n[d] + 2 * L.L.ng;
+            a.nc[d] = L.L.n[d];
+            a.s[d] = sh[d];
+            a.Np[d] = P.L.n[d] + 2 * P.L.ng;
+            a.F[d] = nl.F[d];
+        }
+        if ((e = launch_shift(a, s)) != hipSuccess) return hip_fail(e, "patch shift launch");
+        if ((e = launch_copy(L.L.u, L.L.u_a, (long)NF * L.L.sf, s)) != hipSuccess) return hip_fail(e, "copy launch");
+        L.L = nl;
+        L.has_prev = false;
+        hier_build_sets(H, l);
+        if (l + 1 < nlev)
+            for (int d = 0; d < 3; ++d) H->lv[l + 1].L.F[d] -= 2 * sh[d];
+        moved = true;
+    }
+    if (moved) hier_drop_graph(H);
     return Z4C_OK;
 }
 
@@ -867,40 +1003,59 @@ int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream)
             if (!H->lv[l].has_prev) return false;
         return true;
     };
-    int done = 0;
-    // until every parent holds an earlier level the schedule changes from
-    // step to step: launch those steps directly
-    while (done < nsteps && (!use_graph || !primed())) {
-        if ((e = hier_level_step(H, 0, 0.0, s)) != hipSuccess) return hip_fail(e, "hierarchy step launch");
-        ++done;
+    for (int i = 0; i < nsteps; ++i) {
+        // until every parent holds an earlier level the schedule changes from
+        // step to step: those steps are launched directly
+        if (use_graph && primed()) {
+            int rc;
+            if (!H->exec && (rc = hier_capture(H))) return rc;
+            if ((e = hipGraphLaunch(H->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        } else if ((e = hier_level_step(H, 0, 0.0, s)) != hipSuccess) {
+            return hip_fail(e, "hierarchy step launch");
+        }
+        if (H->lmove > 0) {
+            int rc = hier_regrid(H, s);
+            if (rc) return rc;
+        }
     }
-    if (done == nsteps) return Z4C_OK;
-    if (!H->exec) {
-        if (!H->capture && (e = hipStreamCreateWithFlags(&H->capture, hipStreamNonBlocking)) != hipSuccess) {
-            H->capture = nullptr;
-            return hip_fail(e, "hipStreamCreateWithFlags");
-        }
-        // captured on a private stream; the instantiated graph runs on `s`
-        if ((e = hipStreamBeginCapture(H->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = hier_level_step(H, 0, 0.0, H->capture);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(H->capture, &g);
-        if (le != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(le, "hierarchy step launch during capture");
-        }
-        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-        hipGraphExec_t x = nullptr;
-        if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-        H->graph = g;
-        H->exec = x;
+    return Z4C_OK;
+}
+
+int z4c_hier_set_moving(void* hier, int lmove, const double* xp)
+{
+    if (!hier || !xp) return fail(Z4C_EINVAL, "hier and xp must be non-NULL");
+    z4c_hier_s* H = (z4c_hier_s*)hier;
+    const int nlev = (int)H->lv.size();
+    if (lmove < 1 || lmove >= nlev) return fail(Z4C_EINVAL, "moving levels must start at 1..nlev-1");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(xp[d])) return fail(Z4C_EINVAL, "non-finite puncture position");
+    hipError_t e;
+    if (!H->track && (e = hipMalloc((void**)&H->track, 10 * sizeof(double))) != hipSuccess) {
+        H->track = nullptr;
+        return fail(Z4C_ENOMEM, "puncture state allocation failed");
     }
-    for (; done < nsteps; ++done)
-        if ((e = hipGraphLaunch(H->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    const double st[10] = {xp[0], xp[1], xp[2], 0, 0, 0, xp[0], xp[1], xp[2], 0};
+    if ((e = hipMemcpy(H->track, st, sizeof(st), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy (puncture)");
+    H->lmove = lmove;
+    hier_drop_graph(H);
+    return Z4C_OK;
+}
+
+int z4c_hier_puncture(void* hier, double* xp, int* F, double* x0)
+{
+    if (!hier || !xp) return fail(Z4C_EINVAL, "hier and xp must be non-NULL");
+    z4c_hier_s* H = (z4c_hier_s*)hier;
+    if (!H->track) return fail(Z4C_EINVAL, "no moving levels (z4c_hier_set_moving)");
+    double st[10];
+    hipError_t e = hipMemcpy(st, H->track, sizeof(st), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (puncture)");
+    for (int d = 0; d < 3; ++d) xp[d] = st[d];
+    for (size_t l = 0; l < H->lv.size(); ++l)
+        for (int d = 0; d < 3; ++d) {
+            if (F) F[3 * l + d] = H->lv[l].L.F[d];
+            if (x0) x0[3 * l + d] = H->lv[l].L.x0[d];
+        }
     return Z4C_OK;
 }
 

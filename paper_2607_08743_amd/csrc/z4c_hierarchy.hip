@@ -107,6 +107,36 @@ __device__ __forceinline__ int prolong_cell(int a, int F, int& side)
     return F + half;
 }
 
+// Field f of the parent levels pa (time weights wt) interpolated at the child
+// point whose containing parent cell is (px, py, pz) (stored indices) and
+// whose sides are (sx, sy, sz).
+__device__ __forceinline__ double prolong_value(const double* const pa[3], const double wt[3], long sfp, long Nx,
+                                                long NxNy, int px, int py, int pz, int sx, int sy, int sz, int f)
+{
+    long ox[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) ox[m] = px + sx * kOff[m];
+    double s = 0.0;
+    for (int c = 0; c < 6; ++c) {
+        const long zc = (long)(pz + sz * kOff[c]) * NxNy;
+        double syy = 0.0;
+        for (int b = 0; b < 6; ++b) {
+            const long row = f * sfp + zc + (long)(py + sy * kOff[b]) * Nx;
+            double sxx = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                double v = 0.0;
+                for (int t = 0; t < 3; ++t)
+                    if (pa[t]) v += wt[t] * pa[t][row + ox[m]];
+                sxx += kProlong.w[m] * v;
+            }
+            syy += kProlong.w[b] * sxx;
+        }
+        s += kProlong.w[c] * syy;
+    }
+    return s;
+}
+
 __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
 {
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,29 +148,82 @@ __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
     const int py = prolong_cell(j - a.ngc, a.F[1], sy) + a.ngp;
     const int pz = prolong_cell(k - a.ngc, a.F[2], sz) + a.ngp;
     const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
-    long ox[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) ox[m] = px + sx * kOff[m];
-    for (int f = 0; f < NF; ++f) {
-        double s = 0.0;
-        for (int c = 0; c < 6; ++c) {
-            const long zc = (long)(pz + sz * kOff[c]) * NxNy;
-            double syy = 0.0;
-            for (int b = 0; b < 6; ++b) {
-                const long row = f * a.sfp + zc + (long)(py + sy * kOff[b]) * Nx;
-                double sxx = 0.0;
-#pragma unroll
-                for (int m = 0; m < 6; ++m) {
-                    double v = 0.0;
-                    for (int t = 0; t < 3; ++t)
-                        if (a.pa[t]) v += a.wt[t] * a.pa[t][row + ox[m]];
-                    sxx += kProlong.w[m] * v;
-                }
-                syy += kProlong.w[b] * sxx;
-            }
-            s += kProlong.w[c] * syy;
+    for (int f = 0; f < NF; ++f)
+        a.shell[f * a.nshell + q] = prolong_value(a.pa, a.wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f);
+}
+
+// A moving patch shifted by 2 s of its cells (s per direction in -1..1):
+// active cell a of the new patch is cell a + 2 s of the old one where that
+// exists, else prolonged from the parent (one time level, new face index F).
+__global__ void __launch_bounds__(256) shift_patch(ShiftArgs a)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n0 = a.nc[0], n1 = a.nc[1];
+    if (q >= n0 * n1 * a.nc[2]) return;
+    const int i = (int)(q % n0), j = (int)((q / n0) % n1), k = (int)(q / (n0 * n1));
+    const long Ncx = a.Nc[0], NcxNcy = (long)a.Nc[0] * a.Nc[1];
+    const long dst = (long)(k + a.ngc) * NcxNcy + (long)(j + a.ngc) * Ncx + (i + a.ngc);
+    const int si = i + 2 * a.s[0], sj = j + 2 * a.s[1], sk = k + 2 * a.s[2];
+    if (si >= 0 && si < a.nc[0] && sj >= 0 && sj < a.nc[1] && sk >= 0 && sk < a.nc[2]) {
+        const long src = (long)(sk + a.ngc) * NcxNcy + (long)(sj + a.ngc) * Ncx + (si + a.ngc);
+        for (int f = 0; f < NF; ++f) a.out[f * a.sfc + dst] = a.uc[f * a.sfc + src];
+        return;
+    }
+    int sx, sy, sz;
+    const int px = prolong_cell(i, a.F[0], sx) + a.ngp;
+    const int py = prolong_cell(j, a.F[1], sy) + a.ngp;
+    const int pz = prolong_cell(k, a.F[2], sz) + a.ngp;
+    const double* const pa[3] = {nullptr, a.up, nullptr};
+    const double wt[3] = {0.0, 1.0, 0.0};
+    const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
+    for (int f = 0; f < NF; ++f) a.out[f * a.sfc + dst] = prolong_value(pa, wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f);
+}
+
+// Puncture tracking, dx/dt = -beta, Heun's method on the finest level's
+// steps.  st = {x[3], b0[3], xs[3], err}.  mode 0 (before a step): b0 =
+// beta(x), xs = x - dt b0; mode 1 (after it): x -= dt/2 (b0 + beta(xs)).
+// beta by 4-point Lagrange interpolation in each direction (cell centres
+// i0-1 .. i0+2 around the point).  One thread: 64 terms per component.
+__global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
+{
+    if (threadIdx.x != 0) return;
+    double* st = a.state;
+    const double* x = a.mode == 0 ? st : st + 6;
+    double w[3][4];
+    int lo[3];
+    for (int d = 0; d < 3; ++d) {
+        const double sc = (x[d] - a.x0[d]) / a.h[d];
+        const int i0 = (int)floor(sc);
+        lo[d] = i0 - 1 + a.ng;
+        if (lo[d] < 0 || lo[d] + 3 >= a.N[d]) {  // outside the level: flag it, read nothing
+            st[9] = 1.0;
+            return;
         }
-        a.shell[f * a.nshell + q] = s;
+        const double t = sc - i0;
+        // nodes -1, 0, 1, 2
+        w[d][0] = (t - 0.0) * (t - 1.0) * (t - 2.0) / ((-1.0) * (-2.0) * (-3.0));
+        w[d][1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / ((1.0) * (-1.0) * (-2.0));
+        w[d][2] = (t + 1.0) * (t - 0.0) * (t - 2.0) / ((2.0) * (1.0) * (-1.0));
+        w[d][3] = (t + 1.0) * (t - 0.0) * (t - 1.0) / ((3.0) * (2.0) * (1.0));
+    }
+    const long Nx = a.N[0], NxNy = (long)a.N[0] * a.N[1];
+    double b[3];
+    for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i)
+                    s += w[2][k] * w[1][j] * w[0][i] *
+                         a.u[(F_BE + c) * a.sf + (lo[2] + k) * NxNy + (long)(lo[1] + j) * Nx + (lo[0] + i)];
+        b[c] = s;
+    }
+    if (a.mode == 0) {
+        for (int d = 0; d < 3; ++d) {
+            st[3 + d] = b[d];
+            st[6 + d] = st[d] - a.dt * b[d];
+        }
+    } else {
+        for (int d = 0; d < 3; ++d) st[d] = st[d] - 0.5 * a.dt * (st[3 + d] + b[d]);
     }
 }
 
@@ -196,6 +279,20 @@ hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s)
     const long n = (long)(a.nc[0] / 2) * (a.nc[1] / 2) * (a.nc[2] / 2);
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(restrict_cover, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift(const ShiftArgs& a, hipStream_t s)
+{
+    const long n = (long)a.nc[0] * a.nc[1] * a.nc[2];
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shift_patch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_track(const TrackArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(track_puncture, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -141,7 +141,33 @@ struct RestrictArgs {
     int ngp;
     int F[3];
 };
+struct ShiftArgs {
+    const double* uc;  // the patch before the shift
+    double* out;       // the patch after it (active cells written)
+    long sfc;
+    int Nc[3];
+    int ngc;
+    int nc[3];
+    int s[3];          // shift in parent cells (2 s own cells), each -1, 0 or 1
+    const double* up;  // parent state (same time)
+    long sfp;
+    int Np[3];
+    int ngp;
+    int F[3];          // parent active cell index of the shifted patch's lower faces
+};
+struct TrackArgs {
+    double* state;  // device: x[3], b0[3], xs[3], error flag
+    const double* u;  // level whose shift is interpolated
+    long sf;
+    int N[3];
+    int ng;
+    double x0[3], h[3];
+    double dt;
+    int mode;  // 0: predictor (before the step), 1: corrector (after it)
+};
 hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
+hipError_t launch_shift(const ShiftArgs& a, hipStream_t s);
+hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long n, hipStream_t s);
 

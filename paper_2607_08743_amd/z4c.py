@@ -88,6 +88,9 @@ def lib(path: str = LIB_PATH):
     L.z4c_hier_create.argtypes = [ctypes.POINTER(Level), i, pp, d, ctypes.POINTER(Tile), ctypes.POINTER(vp)]
     L.z4c_hier_advance.argtypes = [vp, i, i, vp]
     L.z4c_hier_destroy.argtypes = [vp]
+    L.z4c_hier_set_moving.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
+    L.z4c_hier_puncture.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.z4c_constraints_workspace.argtypes = [i, i, i]
     L.z4c_constraints_workspace.restype = l
     L.z4c_constraints.argtypes = [dp, dp, dp, dp, l, l, i, i, i, i, d, d, d, vp]
@@ -97,7 +100,7 @@ def lib(path: str = LIB_PATH):
     L.z4c_last_error.restype = ctypes.c_char_p
     for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
                  "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints",
-                 "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy"):
+                 "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy", "z4c_hier_set_moving", "z4c_hier_puncture"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -329,6 +332,21 @@ class Hierarchy:
 
     def advance(self, nsteps: int = 1, use_graph: bool = True, stream=None):
         check(lib().z4c_hier_advance(self._h, int(nsteps), int(bool(use_graph)), _stream(stream)), "z4c_hier_advance")
+
+    def set_moving(self, lmove: int, xp):
+        """Levels lmove.. follow the puncture that starts at xp."""
+        x = (ctypes.c_double * 3)(*[float(v) for v in xp])
+        check(lib().z4c_hier_set_moving(self._h, int(lmove), x), "z4c_hier_set_moving")
+
+    def puncture(self):
+        """(puncture position, [F per level], [x0 per level])."""
+        n = len(self.grids)
+        x = (ctypes.c_double * 3)()
+        F = (ctypes.c_int * (3 * n))()
+        x0 = (ctypes.c_double * (3 * n))()
+        check(lib().z4c_hier_puncture(self._h, x, F, x0), "z4c_hier_puncture")
+        return (list(x), [tuple(F[3 * l:3 * l + 3]) for l in range(n)],
+                [tuple(x0[3 * l:3 * l + 3]) for l in range(n)])
 
     def close(self):
         if getattr(self, "_h", None):

@@ -63,7 +63,7 @@ class OzLevel(ctypes.Structure):
     _fields_ = [("u", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("sf", ctypes.c_long),
                 ("n", ctypes.c_int * 3), ("ng", ctypes.c_int), ("h", ctypes.c_double * 3),
                 ("x0", ctypes.c_double * 3), ("F", ctypes.c_int * 3), ("bc", ctypes.c_int),
-                ("has_prev", ctypes.c_int)]
+                ("has_prev", ctypes.c_int), ("parent", ctypes.c_int), ("obj", ctypes.c_int)]
 
 
 class OzParams(ctypes.Structure):
@@ -114,10 +114,11 @@ def lib():
                                            ctypes.POINTER(OzParams), ctypes.c_double, ctypes.c_int, ctypes.c_int]
         L.oz_interp_beta.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp, dp, dp, dp]
         L.oz_regrid.argtypes = [ctypes.POINTER(OzLevel), ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+        L.oz_exchange.argtypes = [ctypes.POINTER(OzLevel), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.oz_mixed_2d.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         for name in ("oz_rhs", "oz_rhs_points", "oz_apply_ghosts", "oz_enforce", "oz_stage_points", "oz_rk4",
                      "oz_stencil_1d", "oz_mixed_2d", "oz_constraints", "oz_bo_advance", "oz_prolong", "oz_restrict",
-                     "oz_transfer_weights", "oz_bo_advance_moving", "oz_interp_beta", "oz_regrid"):
+                     "oz_transfer_weights", "oz_bo_advance_moving", "oz_interp_beta", "oz_regrid", "oz_exchange"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,21 +231,25 @@ def _ivec(v):
 
 
 class Level:
-    """One level of a box-in-box hierarchy for bo_advance: its grid, state u
-    (advanced in place), the earlier time level `prev` (allocated here) and
-    F, the parent active cell index of its lower faces (levels >= 1)."""
+    """One patch of a box-in-box hierarchy for bo_advance: its grid, state u
+    (advanced in place), the earlier time level `prev` (allocated here), F,
+    the parent active cell index of its lower faces (patches >= 1), the
+    index of its parent patch (None: the patch listed just before it) and
+    the tracked object it follows (-1: a fixed patch)."""
 
-    def __init__(self, grid, u, F=(0, 0, 0)):
+    def __init__(self, grid, u, F=(0, 0, 0), parent=None, obj=-1):
         self.grid = grid
         self.u = _state(u)
         self.prev = np.zeros_like(u)
         self.F = tuple(int(x) for x in F)
         self.has_prev = 0
+        self.parent = parent
+        self.obj = int(obj)
 
 
 def _level_array(levels):
     arr = (OzLevel * len(levels))()
-    for L, lv in zip(arr, levels):
+    for q, (L, lv) in enumerate(zip(arr, levels)):
         g = lv.grid
         L.u = lv.u.ctypes.data
         L.prev = lv.prev.ctypes.data
@@ -256,6 +261,8 @@ def _level_array(levels):
         L.F[:] = list(lv.F)
         L.bc = int(g.bc)
         L.has_prev = lv.has_prev
+        L.parent = int(lv.parent) if lv.parent is not None else q - 1
+        L.obj = lv.obj
     return arr
 
 
@@ -270,8 +277,8 @@ def _level_back(arr, levels):
 
 
 def bo_advance(levels, dt0, nsteps, p=None, nthreads=None) -> None:
-    """Berger-Oliger advance of the hierarchy by nsteps coarse steps of dt0
-    (level l takes 2^l steps of dt0 / 2^l each)."""
+    """Berger-Oliger advance of the hierarchy by nsteps root steps of dt0
+    (a patch at depth d takes 2^d steps of dt0 / 2^d each)."""
     p = p or params()
     arr = _level_array(levels)
     _check(lib().oz_bo_advance(arr, len(levels), ctypes.byref(p), float(dt0), int(nsteps),
@@ -279,27 +286,44 @@ def bo_advance(levels, dt0, nsteps, p=None, nthreads=None) -> None:
     _level_back(arr, levels)
 
 
-def bo_advance_moving(levels, lmove, xp, dt0, nsteps, p=None, nthreads=None) -> np.ndarray:
-    """As bo_advance, with levels lmove.. following the puncture that starts
-    at xp (tracked on the finest level, dx/dt = -beta); after every coarse
-    step each moving patch shifts by two of its cells toward the puncture
-    when its centre is more than two cells away.  Returns the final
-    puncture position; level grids and F are updated in place."""
+def _punctures(xp):
+    x = np.array(xp, dtype=np.float64)
+    single = x.ndim == 1
+    x = np.ascontiguousarray(x.reshape(-1, 3))
+    return x, single
+
+
+def bo_advance_moving(levels, xp, dt0, nsteps, p=None, nthreads=None) -> np.ndarray:
+    """As bo_advance, with the patches whose obj >= 0 following the
+    punctures xp (one row of 3 per object; a single row may be flat),
+    each tracked on its object's deepest patch (dx/dt = -beta).  After every
+    root step each moving patch shifts by two of its cells toward its
+    puncture when its centre is more than two cells away.  Returns the
+    final punctures in the shape of xp; grids and F are updated in place."""
     p = p or params()
-    x = np.ascontiguousarray(xp, dtype=np.float64).copy()
+    x, single = _punctures(xp)
     arr = _level_array(levels)
-    _check(lib().oz_bo_advance_moving(arr, len(levels), int(lmove), _dp(x), ctypes.byref(p), float(dt0),
+    _check(lib().oz_bo_advance_moving(arr, len(levels), len(x), _dp(x), ctypes.byref(p), float(dt0),
                                       int(nsteps), nthreads or threads_default()), "bo_advance_moving")
     _level_back(arr, levels)
-    return x
+    return x[0] if single else x
 
 
-def regrid(levels, lmove, xp, nthreads=None) -> None:
-    """One regrid of the moving levels toward xp, without a time step."""
-    x = np.ascontiguousarray(xp, dtype=np.float64)
+def regrid(levels, xp, nthreads=None) -> None:
+    """One regrid of the moving patches toward xp, without a time step."""
+    x, _ = _punctures(xp)
     arr = _level_array(levels)
-    _check(lib().oz_regrid(arr, len(levels), int(lmove), _dp(x), nthreads or threads_default()), "regrid")
+    _check(lib().oz_regrid(arr, len(levels), len(x), _dp(x), nthreads or threads_default()), "regrid")
     _level_back(arr, levels)
+
+
+def exchange(levels, depth, mode, nthreads=None) -> None:
+    """The exchange between the patches at one depth, in place: mode
+    "average" (overlapping active cells take their mean) or "ghosts" (ghost
+    points inside another patch's active region take its value)."""
+    arr = _level_array(levels)
+    m = {"average": 0, "ghosts": 1}[mode]
+    _check(lib().oz_exchange(arr, len(levels), int(depth), m, nthreads or threads_default()), "exchange")
 
 
 def interp_beta(u, g, x) -> np.ndarray:

@@ -905,33 +905,73 @@ int oz_mixed_2d(const double* f, int nx, int ny, double hx, double hy, double* o
 
 /* ------------------------------------------------------------------ */
 /* Box-in-box hierarchy with Berger-Oliger time subcycling (Sec.       */
-/* 2.2.1): successive levels refine 2:1 on cell-centred grids (child   */
-/* centres sit h_parent/4 from parent centres), every level takes two  */
-/* steps of half the size per parent step; the child's ghost zone is   */
-/* filled by 6th-order Lagrange interpolation in space of the parent,  */
-/* interpolated in time between the parent's time levels (2nd order,   */
-/* 1st order while the parent has no earlier level); after the child   */
-/* has caught up, every parent cell it covers is overwritten by a      */
-/* 4th-order Lagrange interpolation of the child data.                 */
+/* 2.2.1).  The hierarchy is a list of patches; patch 0 is the root    */
+/* (coarsest level, with its own boundary), every other patch names    */
+/* its parent, which refines it 2:1 on a cell-centred grid (child      */
+/* centres sit h_parent/4 from parent centres).  All patches at one    */
+/* depth share the depth's lattice and step together: two steps of     */
+/* half the size per parent step.  Fixed levels are single patches;    */
+/* moving levels hold one patch per tracked object.                    */
 /*                                                                     */
-/* Readings (also in the design notes): one box per level; the child's */
-/* lower faces coincide with parent cell faces (F = parent active cell */
-/* index of the face); the restriction stencil reaches one child ghost */
-/* layer, which is filled by prolongation at the new time first.       */
+/* Transfers between depths: a child's ghost zone is filled by 6th-     */
+/* order Lagrange interpolation in space of its parent, interpolated   */
+/* in time between the parent's time levels (2nd order, 1st order      */
+/* while the parent has no earlier level); after the children have     */
+/* caught up, every coarse cell covered by a child's active region is  */
+/* overwritten by a 4th-order Lagrange interpolation of the child data */
+/* (the average over the children covering it, where several do).     */
+/*                                                                     */
+/* Exchange between patches at one depth: where two active regions     */
+/* overlap, each takes the average of all of them; a ghost point that  */
+/* lies in another patch's active region takes that patch's value (the */
+/* first such patch in index order); ghost over ghost changes nothing. */
+/*                                                                     */
+/* Readings (also in the design notes): the child's lower faces        */
+/* coincide with parent cell faces (F = parent active cell index of    */
+/* the face); the restriction stencil reaches one child ghost layer,   */
+/* which is filled by prolongation and exchange at the new time first; */
+/* stage inputs get their ghosts (prolongation, then exchange) at the  */
+/* stage time; overlapping active cells are averaged once per step,    */
+/* after the last stage.                                               */
 /* ------------------------------------------------------------------ */
+
+#define OZ_MAXPATCH 32
 
 typedef struct {
     double* u;    /* state, advanced in place */
-    double* prev; /* this level one step earlier (kept for the time interpolation of its child) */
+    double* prev; /* this patch one step earlier (kept for the time interpolation of its children) */
     long sf;
     int n[3];
     int ng;
     double h[3];
     double x0[3];
-    int F[3];     /* levels >= 1: lower face in the parent's active cell index */
-    int bc;       /* level 0: its own boundary kind; levels >= 1: ignored (filled from the parent) */
+    int F[3];     /* patches >= 1: lower face in the parent's active cell index */
+    int bc;       /* root: its own boundary kind; other patches: ignored (filled from the parent) */
     int has_prev; /* in/out: prev holds a valid earlier time level */
+    int parent;   /* index of the parent patch, below the patch's own; -1 for the root (patch 0) */
+    int obj;      /* moving patches: the tracked object they follow; -1 for a fixed patch */
 } oz_level;
+
+/* the hierarchy during an advance: geometry derived from the patches and
+   the per-patch work arrays */
+typedef struct {
+    oz_level* lv;
+    int np;
+    int depth[OZ_MAXPATCH];
+    int off[OZ_MAXPATCH][3]; /* lattice index of the first active cell at the patch's depth */
+    int maxdepth;
+    grid g[OZ_MAXPATCH];
+    double* cur[OZ_MAXPATCH]; /* the patch at the start of its current step */
+    double* us[OZ_MAXPATCH];  /* stage input */
+    double* kk[OZ_MAXPATCH][4];
+    const oz_params* p;
+    double dt0;
+    int nt;
+    int nobj;
+    double* xp;              /* 3 per object, in/out */
+    int tp[OZ_MAXPATCH];     /* per object: the patch it is tracked on */
+    double b0[OZ_MAXPATCH][3], xs[OZ_MAXPATCH][3];
+} hierarchy;
 
 /* Lagrange weights of the m nodes at the point x */
 static void lagrange_weights(const double* nodes, int m, double x, double* w)
@@ -999,14 +1039,25 @@ static void prolong_ghosts(const grid* gp, const double* const pa[3], const doub
             }
 }
 
-/* Overwrite every parent active cell covered by the child's active region
-   with the 4th-order Lagrange interpolation of the child (nodes at -3/2,
-   -1/2, 1/2, 3/2 child cells from the parent centre). */
-static void restrict_to_parent(const grid* gc, const double* uc, const grid* gp, double* up, const int F[3], int nt)
+/* 4th-order Lagrange interpolation of field f of the child to the centre
+   of a parent cell: child cells (ci..ci+3) x (cj..) x (ck..) (stored
+   indices), nodes at -3/2, -1/2, 1/2, 3/2 child cells from that centre */
+static double restrict_value(const grid* gc, const double* uc, int f, int ci, int cj, int ck)
 {
     static const double nodes[4] = {-1.5, -0.5, 0.5, 1.5};
     double r[4];
     lagrange_weights(nodes, 4, 0.0, r);
+    double s = 0.0;
+    for (int z = 0; z < 4; ++z)
+        for (int y = 0; y < 4; ++y)
+            for (int x = 0; x < 4; ++x) s += r[z] * r[y] * r[x] * uc[f * gc->sf + lin(gc, ci + x, cj + y, ck + z)];
+    return s;
+}
+
+/* Overwrite every parent active cell covered by the child's active region
+   with the restriction of the child (probe of a single parent/child pair) */
+static void restrict_to_parent(const grid* gc, const double* uc, const grid* gp, double* up, const int F[3], int nt)
+{
     const int m0 = gc->n[0] / 2, m1 = gc->n[1] / 2, m2 = gc->n[2] / 2;
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (int c = 0; c < m2; ++c)
@@ -1015,14 +1066,7 @@ static void restrict_to_parent(const grid* gc, const double* uc, const grid* gp,
                 /* child active cells 2a-1 .. 2a+2 (and likewise in y, z) */
                 int ci = 2 * a - 1 + gc->ng, cj = 2 * b - 1 + gc->ng, ck = 2 * c - 1 + gc->ng;
                 long qp = lin(gp, F[0] + a + gp->ng, F[1] + b + gp->ng, F[2] + c + gp->ng);
-                for (int f = 0; f < NF; ++f) {
-                    double s = 0.0;
-                    for (int z = 0; z < 4; ++z)
-                        for (int y = 0; y < 4; ++y)
-                            for (int x = 0; x < 4; ++x)
-                                s += r[z] * r[y] * r[x] * uc[f * gc->sf + lin(gc, ci + x, cj + y, ck + z)];
-                    up[f * gp->sf + qp] = s;
-                }
+                for (int f = 0; f < NF; ++f) up[f * gp->sf + qp] = restrict_value(gc, uc, f, ci, cj, ck);
             }
 }
 
@@ -1040,160 +1084,333 @@ static void time_weights(double theta, int quadratic, double wt[3])
     }
 }
 
-typedef struct {
-    const grid* gp;
-    const double* pa[3];
-    int quadratic;
-    const int* F;
-} parent_ref;
+/* ---- hierarchy geometry ---- */
 
-static void fill_level_ghosts(double* u, const grid* g, const parent_ref* pr, double theta, int nt)
+/* depths, lattice offsets and grids of every patch; -1 if the patch list
+   is not a valid hierarchy */
+static int hier_geometry(hierarchy* H)
 {
-    if (!pr) {
-        ghosts(u, NULL, g);
-        return;
-    }
-    double wt[3];
-    time_weights(theta, pr->quadratic, wt);
-    const double* pa[3] = {pr->quadratic ? pr->pa[0] : NULL, pr->pa[1], pr->pa[2]};
-    prolong_ghosts(pr->gp, pa, wt, g, u, pr->F, nt);
-}
-
-static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt, int nt, const parent_ref* pr,
-                    double theta0, double* xp);
-static int interp_beta(const oz_level* L, const double x[3], double b[3]);
-
-/* one RK4 step of level l (the textbook form of oz_rk4), ghosts of every
-   stage input filled at that stage's time, then its children */
-static int bo_level(oz_level* lv, int nlev, int l, const oz_params* p, double dt, int nt, const parent_ref* pr,
-                    double theta0, double* xp)
-{
-    oz_level* L = &lv[l];
-    grid g;
-    make_level_grid(&g, L, l == 0 ? L->bc : BC_COPY);
-    const long sf = L->sf;
-    const size_t bytes = (size_t)NF * (size_t)sf * sizeof(double);
-    double* cur = malloc(bytes);
-    double* us = malloc(bytes);
-    double* kk[4];
-    for (int s = 0; s < 4; ++s) kk[s] = malloc(bytes);
-    int rc = 0;
-    if (!cur || !us || !kk[0] || !kk[1] || !kk[2] || !kk[3]) {
-        rc = -3;
-        goto done;
-    }
-    /* stage times in units of the parent step: theta0 + {0, 1/4, 1/4, 1/2} */
-    const double cstage[3] = {0.5, 0.5, 1.0};
-    fill_level_ghosts(L->u, &g, pr, theta0, nt);
-    memcpy(cur, L->u, bytes);
-    /* puncture tracking on the finest level: Heun's method for dx/dt = -beta,
-       beta at the start of the step at x, at its end at the predicted point */
-    const int track = xp && l == nlev - 1;
-    double b0[3], xs[3];
-    if (track) {
-        if (interp_beta(L, xp, b0)) {
-            rc = -2;
-            goto done;
-        }
-        for (int d = 0; d < 3; ++d) xs[d] = xp[d] - dt * b0[d];
-    }
-    for (int s = 0; s < 4; ++s) {
-        const double* src = s == 0 ? L->u : us;
-        rhs_all(src, kk[s], &g, p, nt);
-        if (s == 3) break;
-#pragma omp parallel for schedule(static) num_threads(nt)
-        for (int k = 0; k < g.N[2]; ++k)
-            for (int j = 0; j < g.N[1]; ++j)
-                for (int i = 0; i < g.N[0]; ++i) {
-                    long q = lin(&g, i, j, k);
-                    int ev = is_evolved(&g, i, j, k);
-                    for (int f = 0; f < NF; ++f)
-                        us[f * sf + q] = ev ? L->u[f * sf + q] + cstage[s] * dt * kk[s][f * sf + q] : L->u[f * sf + q];
-                    if (ev) enforce_point(us, sf, q);
-                }
-        fill_level_ghosts(us, &g, pr, theta0 + 0.5 * cstage[s], nt);
-    }
-#pragma omp parallel for schedule(static) num_threads(nt)
-    for (int k = 0; k < g.N[2]; ++k)
-        for (int j = 0; j < g.N[1]; ++j)
-            for (int i = 0; i < g.N[0]; ++i) {
-                long q = lin(&g, i, j, k);
-                if (!is_evolved(&g, i, j, k)) continue;
-                for (int f = 0; f < NF; ++f) {
-                    long o = f * sf + q;
-                    L->u[o] = L->u[o] + dt / 6.0 * (((kk[0][o] + 2.0 * kk[1][o]) + 2.0 * kk[2][o]) + kk[3][o]);
-                }
-                enforce_point(L->u, sf, q);
-            }
-    fill_level_ghosts(L->u, &g, pr, theta0 + 0.5, nt);
-    if (track) {
-        double b1[3];
-        if (interp_beta(L, xs, b1)) {
-            rc = -2;
-            goto done;
-        }
-        for (int d = 0; d < 3; ++d) xp[d] = xp[d] - 0.5 * dt * (b0[d] + b1[d]);
-    }
-    if (l + 1 < nlev) {
-        oz_level* C = &lv[l + 1];
-        parent_ref me = {&g, {L->has_prev ? L->prev : NULL, cur, L->u}, L->has_prev, C->F};
-        for (int m = 0; m < 2 && !rc; ++m) rc = bo_level(lv, nlev, l + 1, p, 0.5 * dt, nt, &me, 0.5 * m, xp);
-        if (!rc) {
-            grid gc;
-            make_level_grid(&gc, C, BC_COPY);
-            fill_level_ghosts(C->u, &gc, &me, 1.0, nt);
-            restrict_to_parent(&gc, C->u, &g, L->u, C->F, nt);
-            fill_level_ghosts(L->u, &g, pr, theta0 + 0.5, nt);
-        }
-    }
-    if (!rc) {
-        memcpy(L->prev, cur, bytes);
-        L->has_prev = 1;
-    }
-done:
-    free(cur);
-    free(us);
-    for (int s = 0; s < 4; ++s) free(kk[s]);
-    return rc;
-}
-
-static int check_levels(const oz_level* lv, int nlev)
-{
-    if (!lv || nlev < 1) return -1;
-    for (int l = 0; l < nlev; ++l) {
-        const oz_level* L = &lv[l];
-        grid g;
+    H->maxdepth = 0;
+    for (int q = 0; q < H->np; ++q) {
+        const oz_level* L = &H->lv[q];
         if (!L->u || !L->prev) return -1;
-        if (make_grid(&g, L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0], L->x0[1],
-                      L->x0[2], l == 0 ? L->bc : BC_COPY))
-            return -1;
-        if (l == 0) {
-            if (L->bc == BC_COPY) return -1; /* the coarsest level needs a boundary of its own */
+        if (q == 0) {
+            if (L->parent != -1 || L->bc == BC_COPY) return -1; /* the root needs a boundary of its own */
+            H->depth[0] = 0;
+            for (int d = 0; d < 3; ++d) H->off[0][d] = 0;
+            if (make_grid(&H->g[0], L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0],
+                          L->x0[1], L->x0[2], L->bc))
+                return -1;
             continue;
         }
-        const oz_level* P = &lv[l - 1];
+        if (L->parent < 0 || L->parent >= q) return -1;
+        const oz_level* P = &H->lv[L->parent];
+        H->depth[q] = H->depth[L->parent] + 1;
+        if (H->depth[q] > H->maxdepth) H->maxdepth = H->depth[q];
+        if (make_grid(&H->g[q], L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0],
+                      L->x0[1], L->x0[2], BC_COPY))
+            return -1;
         for (int d = 0; d < 3; ++d) {
             if (L->n[d] % 2 || L->h[d] != 0.5 * P->h[d]) return -1;
             /* prolongation stencil of every child ghost inside the parent's active cells */
             double w[6];
             int lo = prolong_1d(-L->ng, L->F[d], w), hi = prolong_1d(L->n[d] + L->ng - 1, L->F[d], w) + 5;
             if (lo < 0 || hi >= P->n[d]) return -1;
+            /* child active cell a sits at lattice index 2 (parent's first cell + F) + a */
+            H->off[q][d] = 2 * (H->off[L->parent][d] + L->F[d]);
         }
     }
     return 0;
 }
 
-/* Advance the hierarchy lv[0..nlev) by nsteps steps of the coarsest level
-   (size dt0; level l takes 2^l steps of dt0 / 2^l per coarse step). */
-int oz_bo_advance(oz_level* lv, int nlev, const oz_params* p, double dt0, int nsteps, int nthreads)
+static int in_active(const hierarchy* H, int q, const int G[3])
 {
-    if (!p || !(dt0 > 0) || nsteps < 0 || check_levels(lv, nlev)) return -1;
-    int nt = nthreads < 1 ? 1 : nthreads;
-    for (int s = 0; s < nsteps; ++s) {
-        int rc = bo_level(lv, nlev, 0, p, dt0, nt, NULL, 0.0, NULL);
-        if (rc) return rc;
+    for (int d = 0; d < 3; ++d) {
+        int a = G[d] - H->off[q][d];
+        if (a < 0 || a >= H->lv[q].n[d]) return 0;
+    }
+    return 1;
+}
+
+/* stored index of the lattice point G in patch q */
+static long lattice_lin(const hierarchy* H, int q, const int G[3])
+{
+    const int ng = H->lv[q].ng;
+    return lin(&H->g[q], G[0] - H->off[q][0] + ng, G[1] - H->off[q][1] + ng, G[2] - H->off[q][2] + ng);
+}
+
+/* Exchange at depth d, averaging: every lattice cell in the active regions
+   of several patches gets their mean in all of them.  The first patch (in
+   index order) that holds the cell does the work, so each cell is handled
+   once. */
+static void exchange_average(hierarchy* H, int d, double* const* arr)
+{
+    for (int a = 0; a < H->np; ++a) {
+        if (H->depth[a] != d) continue;
+        const oz_level* A = &H->lv[a];
+#pragma omp parallel for schedule(static) num_threads(H->nt)
+        for (int k = 0; k < A->n[2]; ++k)
+            for (int j = 0; j < A->n[1]; ++j)
+                for (int i = 0; i < A->n[0]; ++i) {
+                    const int G[3] = {H->off[a][0] + i, H->off[a][1] + j, H->off[a][2] + k};
+                    int first = -1, cnt = 0;
+                    for (int b = 0; b < H->np; ++b)
+                        if (H->depth[b] == d && in_active(H, b, G)) {
+                            if (first < 0) first = b;
+                            ++cnt;
+                        }
+                    if (first != a || cnt < 2) continue;
+                    for (int f = 0; f < NF; ++f) {
+                        double s = 0.0;
+                        for (int b = 0; b < H->np; ++b)
+                            if (H->depth[b] == d && in_active(H, b, G)) s += arr[b][f * H->lv[b].sf + lattice_lin(H, b, G)];
+                        const double v = s / cnt;
+                        for (int b = 0; b < H->np; ++b)
+                            if (H->depth[b] == d && in_active(H, b, G)) arr[b][f * H->lv[b].sf + lattice_lin(H, b, G)] = v;
+                    }
+                }
+    }
+}
+
+/* Exchange at depth d, ghosts: a ghost point of a patch that lies in the
+   active region of another patch of the depth takes its value (the first
+   such patch in index order). */
+static void exchange_ghosts(hierarchy* H, int d, double* const* arr)
+{
+    for (int b = 0; b < H->np; ++b) {
+        if (H->depth[b] != d) continue;
+        const grid* g = &H->g[b];
+#pragma omp parallel for schedule(static) num_threads(H->nt)
+        for (int k = 0; k < g->N[2]; ++k)
+            for (int j = 0; j < g->N[1]; ++j)
+                for (int i = 0; i < g->N[0]; ++i) {
+                    if (is_active(g, i, j, k)) continue;
+                    const int G[3] = {H->off[b][0] + i - g->ng, H->off[b][1] + j - g->ng, H->off[b][2] + k - g->ng};
+                    for (int a = 0; a < H->np; ++a) {
+                        if (a == b || H->depth[a] != d || !in_active(H, a, G)) continue;
+                        const long qa = lattice_lin(H, a, G), qb = lin(g, i, j, k);
+                        for (int f = 0; f < NF; ++f) arr[b][f * g->sf + qb] = arr[a][f * H->lv[a].sf + qa];
+                        break;
+                    }
+                }
+    }
+}
+
+/* ghosts of arr[q] for every patch q at depth d at the fraction theta of
+   the parent step (the root: its own boundary), then the exchange */
+static void fill_depth(hierarchy* H, int d, double* const* arr, double theta)
+{
+    for (int q = 0; q < H->np; ++q) {
+        if (H->depth[q] != d) continue;
+        if (q == 0) {
+            ghosts(arr[q], NULL, &H->g[q]);
+            continue;
+        }
+        const int P = H->lv[q].parent;
+        const oz_level* LP = &H->lv[P];
+        double wt[3];
+        time_weights(theta, LP->has_prev, wt);
+        const double* pa[3] = {LP->has_prev ? LP->prev : NULL, H->cur[P], LP->u};
+        prolong_ghosts(&H->g[P], pa, wt, &H->g[q], arr[q], H->lv[q].F, H->nt);
+    }
+    exchange_ghosts(H, d, arr);
+}
+
+/* Every active cell of a patch at depth d covered by the active region of
+   a patch at depth d+1 takes the restriction of that child (the mean over
+   the children that cover it). */
+static void restrict_depth(hierarchy* H, int d)
+{
+    for (int q = 0; q < H->np; ++q) {
+        if (H->depth[q] != d) continue;
+        const oz_level* P = &H->lv[q];
+#pragma omp parallel for schedule(static) num_threads(H->nt)
+        for (int k = 0; k < P->n[2]; ++k)
+            for (int j = 0; j < P->n[1]; ++j)
+                for (int i = 0; i < P->n[0]; ++i) {
+                    const int G[3] = {H->off[q][0] + i, H->off[q][1] + j, H->off[q][2] + k};
+                    double s[NF];
+                    int cnt = 0;
+                    for (int c = 0; c < H->np; ++c) {
+                        if (H->depth[c] != d + 1) continue;
+                        int ac[3], cov = 1;
+                        for (int e = 0; e < 3; ++e) {
+                            /* the parent cell spans child cells ac, ac+1 */
+                            ac[e] = 2 * G[e] - H->off[c][e];
+                            cov &= ac[e] >= 0 && ac[e] + 1 < H->lv[c].n[e];
+                        }
+                        if (!cov) continue;
+                        const grid* gc = &H->g[c];
+                        for (int f = 0; f < NF; ++f) {
+                            double v = restrict_value(gc, H->lv[c].u, f, ac[0] - 1 + gc->ng, ac[1] - 1 + gc->ng,
+                                                      ac[2] - 1 + gc->ng);
+                            s[f] = cnt ? s[f] + v : v;
+                        }
+                        ++cnt;
+                    }
+                    if (!cnt) continue;
+                    const long qp = lin(&H->g[q], i + P->ng, j + P->ng, k + P->ng);
+                    for (int f = 0; f < NF; ++f) P->u[f * P->sf + qp] = cnt == 1 ? s[f] : s[f] / cnt;
+                }
+    }
+}
+
+static int interp_beta(const oz_level* L, const double x[3], double b[3]);
+
+/* one RK4 step of every patch at depth d (the textbook form of oz_rk4),
+   ghosts of every stage input filled at that stage's time, then the two
+   steps of depth d+1 and the restriction */
+static int bo_depth(hierarchy* H, int d, double theta0)
+{
+    const double dt = H->dt0 / (double)(1L << d);
+    /* stage times in units of the parent step: theta0 + {0, 1/4, 1/4, 1/2} */
+    const double cstage[3] = {0.5, 0.5, 1.0};
+    double* uarr[OZ_MAXPATCH];
+    for (int q = 0; q < H->np; ++q) uarr[q] = H->lv[q].u;
+    fill_depth(H, d, uarr, theta0);
+    for (int q = 0; q < H->np; ++q)
+        if (H->depth[q] == d) memcpy(H->cur[q], H->lv[q].u, (size_t)NF * (size_t)H->lv[q].sf * sizeof(double));
+    /* puncture tracking on each object's finest patch: Heun's method for
+       dx/dt = -beta, beta at the start of the step at x, at its end at the
+       predicted point */
+    for (int o = 0; o < H->nobj; ++o) {
+        if (H->depth[H->tp[o]] != d) continue;
+        if (interp_beta(&H->lv[H->tp[o]], H->xp + 3 * o, H->b0[o])) return -2;
+        for (int e = 0; e < 3; ++e) H->xs[o][e] = H->xp[3 * o + e] - dt * H->b0[o][e];
+    }
+    for (int s = 0; s < 4; ++s) {
+        for (int q = 0; q < H->np; ++q)
+            if (H->depth[q] == d) rhs_all(s == 0 ? H->lv[q].u : H->us[q], H->kk[q][s], &H->g[q], H->p, H->nt);
+        if (s == 3) break;
+        for (int q = 0; q < H->np; ++q) {
+            if (H->depth[q] != d) continue;
+            const grid* g = &H->g[q];
+            const double* u = H->lv[q].u;
+            double* us = H->us[q];
+            const double* kq = H->kk[q][s];
+            const long sf = g->sf;
+#pragma omp parallel for schedule(static) num_threads(H->nt)
+            for (int k = 0; k < g->N[2]; ++k)
+                for (int j = 0; j < g->N[1]; ++j)
+                    for (int i = 0; i < g->N[0]; ++i) {
+                        long x = lin(g, i, j, k);
+                        int ev = is_evolved(g, i, j, k);
+                        for (int f = 0; f < NF; ++f)
+                            us[f * sf + x] = ev ? u[f * sf + x] + cstage[s] * dt * kq[f * sf + x] : u[f * sf + x];
+                        if (ev) enforce_point(us, sf, x);
+                    }
+        }
+        fill_depth(H, d, H->us, theta0 + 0.5 * cstage[s]);
+    }
+    for (int q = 0; q < H->np; ++q) {
+        if (H->depth[q] != d) continue;
+        const grid* g = &H->g[q];
+        double* u = H->lv[q].u;
+        double* const* kk = H->kk[q];
+        const long sf = g->sf;
+#pragma omp parallel for schedule(static) num_threads(H->nt)
+        for (int k = 0; k < g->N[2]; ++k)
+            for (int j = 0; j < g->N[1]; ++j)
+                for (int i = 0; i < g->N[0]; ++i) {
+                    long x = lin(g, i, j, k);
+                    if (!is_evolved(g, i, j, k)) continue;
+                    for (int f = 0; f < NF; ++f) {
+                        long o = f * sf + x;
+                        u[o] = u[o] + dt / 6.0 * (((kk[0][o] + 2.0 * kk[1][o]) + 2.0 * kk[2][o]) + kk[3][o]);
+                    }
+                    enforce_point(u, sf, x);
+                }
+    }
+    exchange_average(H, d, uarr);
+    fill_depth(H, d, uarr, theta0 + 0.5);
+    for (int o = 0; o < H->nobj; ++o) {
+        if (H->depth[H->tp[o]] != d) continue;
+        double b1[3];
+        if (interp_beta(&H->lv[H->tp[o]], H->xs[o], b1)) return -2;
+        for (int e = 0; e < 3; ++e) H->xp[3 * o + e] -= 0.5 * dt * (H->b0[o][e] + b1[e]);
+    }
+    if (d < H->maxdepth) {
+        int rc;
+        if ((rc = bo_depth(H, d + 1, 0.0)) || (rc = bo_depth(H, d + 1, 0.5))) return rc;
+        fill_depth(H, d + 1, uarr, 1.0);
+        restrict_depth(H, d);
+        fill_depth(H, d, uarr, theta0 + 0.5);
+    }
+    for (int q = 0; q < H->np; ++q) {
+        if (H->depth[q] != d) continue;
+        memcpy(H->lv[q].prev, H->cur[q], (size_t)NF * (size_t)H->lv[q].sf * sizeof(double));
+        H->lv[q].has_prev = 1;
     }
     return 0;
+}
+
+static void hier_release(hierarchy* H)
+{
+    for (int q = 0; q < OZ_MAXPATCH; ++q) {
+        free(H->cur[q]);
+        free(H->us[q]);
+        for (int s = 0; s < 4; ++s) free(H->kk[q][s]);
+    }
+}
+
+/* validate the patches and allocate the work arrays; objects 0..nobj-1
+   are tracked on their deepest patch (exactly one patch of each object at
+   its deepest depth) */
+static int hier_init(hierarchy* H, oz_level* lv, int np, const oz_params* p, double dt0, int nobj, double* xp,
+                     int nthreads)
+{
+    memset(H, 0, sizeof(*H));
+    if (!lv || np < 1 || np > OZ_MAXPATCH || nobj < 0 || nobj > OZ_MAXPATCH || (nobj && !xp)) return -1;
+    H->lv = lv;
+    H->np = np;
+    H->p = p;
+    H->dt0 = dt0;
+    H->nt = nthreads < 1 ? 1 : nthreads;
+    H->nobj = nobj;
+    H->xp = xp;
+    if (hier_geometry(H)) return -1;
+    for (int o = 0; o < nobj; ++o) {
+        H->tp[o] = -1;
+        int dmax = -1, count = 0;
+        for (int q = 0; q < np; ++q) {
+            if (lv[q].obj != o) continue;
+            if (H->depth[q] > dmax) {
+                dmax = H->depth[q];
+                H->tp[o] = q;
+                count = 1;
+            } else if (H->depth[q] == dmax) {
+                ++count;
+            }
+        }
+        if (H->tp[o] < 0 || count != 1) return -1;
+    }
+    for (int q = 0; q < np; ++q)
+        if (lv[q].obj >= nobj && nobj > 0) return -1;
+    for (int q = 0; q < np; ++q) {
+        const size_t bytes = (size_t)NF * (size_t)lv[q].sf * sizeof(double);
+        H->cur[q] = malloc(bytes);
+        H->us[q] = malloc(bytes);
+        int ok = H->cur[q] && H->us[q];
+        for (int s = 0; s < 4; ++s) ok &= (H->kk[q][s] = malloc(bytes)) != NULL;
+        if (!ok) {
+            hier_release(H);
+            return -3;
+        }
+    }
+    return 0;
+}
+
+/* Advance the hierarchy lv[0..np) by nsteps steps of the root (size dt0;
+   a patch at depth d takes 2^d steps of dt0 / 2^d per root step). */
+int oz_bo_advance(oz_level* lv, int np, const oz_params* p, double dt0, int nsteps, int nthreads)
+{
+    hierarchy H;
+    if (!p || !(dt0 > 0) || nsteps < 0) return -1;
+    int rc = hier_init(&H, lv, np, p, dt0, 0, NULL, nthreads);
+    if (rc) return rc;
+    for (int s = 0; s < nsteps && !rc; ++s) rc = bo_depth(&H, 0, 0.0);
+    hier_release(&H);
+    return rc;
 }
 
 /* Probes for the pins: prolongation of the parent (three time levels,
@@ -1240,23 +1457,46 @@ int oz_transfer_weights(double theta, int quadratic, double* wt3, double* prolon
     return 0;
 }
 
+/* probe: the exchange at depth d on the patches' states (mode 0 the
+   averaging of overlapping active cells, mode 1 the ghost copy) */
+int oz_exchange(oz_level* lv, int np, int depth, int mode, int nthreads)
+{
+    hierarchy H;
+    memset(&H, 0, sizeof(H));
+    if (!lv || np < 1 || np > OZ_MAXPATCH || (mode != 0 && mode != 1)) return -1;
+    H.lv = lv;
+    H.np = np;
+    H.nt = nthreads < 1 ? 1 : nthreads;
+    if (hier_geometry(&H)) return -1;
+    double* arr[OZ_MAXPATCH];
+    for (int q = 0; q < np; ++q) arr[q] = lv[q].u;
+    if (mode == 0)
+        exchange_average(&H, depth, arr);
+    else
+        exchange_ghosts(&H, depth, arr);
+    return 0;
+}
+
 
 /* ------------------------------------------------------------------ */
-/* Moving levels (Sec. 2.2.1): the finest level tracks the puncture    */
-/* with dx^i/dt = -beta^i (beta interpolated at the puncture); after   */
-/* each coarse step every moving patch whose centre is more than two   */
-/* of its cells from the puncture (per direction) shifts by two of its */
-/* cells -- one parent cell, so parent and child cell faces stay       */
-/* aligned -- toward it; its cells that were already covered keep      */
-/* their values, newly covered ones are prolonged from the parent.     */
-/* Readings: one patch per level tracking one puncture; Heun's method  */
-/* for the track with beta from the finest level by 4-point Lagrange   */
-/* interpolation in each direction; after a shift the level's earlier  */
-/* time level is dropped (its child interpolates linearly once).       */
+/* Moving levels (Sec. 2.2.1): each tracked object (a puncture) moves   */
+/* with dx^i/dt = -beta^i, beta interpolated at the puncture on the     */
+/* object's finest patch; after each root step every moving patch whose */
+/* centre is more than two of its cells from its object's puncture (per */
+/* direction) shifts by two of its cells -- one parent cell, so parent  */
+/* and child cell faces stay aligned -- toward it; its cells that were  */
+/* already covered keep their values, newly covered ones are prolonged  */
+/* from the parent.                                                     */
+/* Readings: Heun's method for the track with beta by 4-point Lagrange  */
+/* interpolation in each direction from active cells only; patches are  */
+/* shifted in index order (a parent before its children, so new cells   */
+/* are prolonged from the shifted parent); the children of a shifted    */
+/* patch keep their place in space; after a shift the patch's earlier   */
+/* time level is dropped (its children interpolate linearly once).      */
 /* ------------------------------------------------------------------ */
 
-/* 4-point Lagrange interpolation of beta at x from level L (nodes: the
-   cell centres i0-1 .. i0+2 around x in each direction) */
+/* 4-point Lagrange interpolation of beta at x from patch L (nodes: the
+   cell centres i0-1 .. i0+2 around x in each direction, all active) */
 static int interp_beta(const oz_level* L, const double x[3], double b[3])
 {
     static const double nodes[4] = {-1.0, 0.0, 1.0, 2.0};
@@ -1267,8 +1507,8 @@ static int interp_beta(const oz_level* L, const double x[3], double b[3])
     for (int d = 0; d < 3; ++d) {
         const double sc = (x[d] - L->x0[d]) / L->h[d]; /* active-index coordinate */
         const int i0 = (int)floor(sc);
+        if (!(sc > -2.0 && sc < L->n[d] + 1.0) || i0 - 1 < 0 || i0 + 2 >= L->n[d]) return -1;
         lo[d] = i0 - 1 + L->ng;
-        if (lo[d] < 0 || lo[d] + 3 >= g.N[d]) return -1;
         lagrange_weights(nodes, 4, sc - i0, w[d]);
     }
     for (int a = 0; a < 3; ++a) {
@@ -1282,7 +1522,7 @@ static int interp_beta(const oz_level* L, const double x[3], double b[3])
     return 0;
 }
 
-/* shift of level l toward the puncture xp: -1, 0 or +1 parent cells per direction */
+/* shift of patch L toward the puncture xp: -1, 0 or +1 parent cells per direction */
 static int patch_shift(const oz_level* L, const double xp[3], int sh[3])
 {
     int any = 0;
@@ -1294,13 +1534,15 @@ static int patch_shift(const oz_level* L, const double xp[3], int sh[3])
     return any;
 }
 
-static int regrid(oz_level* lv, int nlev, int lmove, const double xp[3], int nt)
+static int regrid(hierarchy* H)
 {
-    for (int l = lmove; l < nlev; ++l) {
-        oz_level* L = &lv[l];
-        const oz_level* P = &lv[l - 1];
+    oz_level* lv = H->lv;
+    for (int q = 1; q < H->np; ++q) {
+        oz_level* L = &lv[q];
+        if (L->obj < 0 || L->obj >= H->nobj) continue;
+        const oz_level* P = &lv[L->parent];
         int sh[3];
-        if (!patch_shift(L, xp, sh)) continue;
+        if (!patch_shift(L, H->xp + 3 * L->obj, sh)) continue;
         grid g, gp;
         make_level_grid(&g, L, BC_COPY);
         make_level_grid(&gp, P, BC_COPY);
@@ -1310,7 +1552,7 @@ static int regrid(oz_level* lv, int nlev, int lmove, const double xp[3], int nt)
         memcpy(nu, L->u, bytes);
         int F[3];
         for (int d = 0; d < 3; ++d) F[d] = L->F[d] + sh[d];
-#pragma omp parallel for schedule(static) num_threads(nt)
+#pragma omp parallel for schedule(static) num_threads(H->nt)
         for (int k = 0; k < L->n[2]; ++k)
             for (int j = 0; j < L->n[1]; ++j)
                 for (int i = 0; i < L->n[0]; ++i) {
@@ -1320,10 +1562,10 @@ static int regrid(oz_level* lv, int nlev, int lmove, const double xp[3], int nt)
                         src[d] = a[d] + 2 * sh[d];
                         inside &= src[d] >= 0 && src[d] < L->n[d];
                     }
-                    const long q = lin(&g, i + L->ng, j + L->ng, k + L->ng);
+                    const long x = lin(&g, i + L->ng, j + L->ng, k + L->ng);
                     if (inside) {
-                        const long qs = lin(&g, src[0] + L->ng, src[1] + L->ng, src[2] + L->ng);
-                        for (int f = 0; f < NF; ++f) nu[f * L->sf + q] = L->u[f * L->sf + qs];
+                        const long xs = lin(&g, src[0] + L->ng, src[1] + L->ng, src[2] + L->ng);
+                        for (int f = 0; f < NF; ++f) nu[f * L->sf + x] = L->u[f * L->sf + xs];
                         continue;
                     }
                     double wx[6], wy[6], wz[6];
@@ -1336,7 +1578,7 @@ static int regrid(oz_level* lv, int nlev, int lmove, const double xp[3], int nt)
                             for (int b = 0; b < 6; ++b)
                                 for (int m = 0; m < 6; ++m)
                                     s += wz[c] * wy[b] * wx[m] * P->u[f * P->sf + lin(&gp, lx + m, ly + b, lz + c)];
-                        nu[f * L->sf + q] = s;
+                        nu[f * L->sf + x] = s;
                     }
                 }
         memcpy(L->u, nu, bytes);
@@ -1344,30 +1586,36 @@ static int regrid(oz_level* lv, int nlev, int lmove, const double xp[3], int nt)
         for (int d = 0; d < 3; ++d) {
             L->F[d] = F[d];
             L->x0[d] += 2.0 * sh[d] * L->h[d];
-            if (l + 1 < nlev) lv[l + 1].F[d] -= 2 * sh[d];
         }
+        for (int c = q + 1; c < H->np; ++c)
+            if (lv[c].parent == q)
+                for (int d = 0; d < 3; ++d) lv[c].F[d] -= 2 * sh[d];
         L->has_prev = 0;
+        /* a shifted parent's new cells must be in place before its children use them */
+        if (hier_geometry(H)) return -4;
     }
-    return check_levels(lv, nlev) ? -4 : 0;
+    return hier_geometry(H) ? -4 : 0;
 }
 
-/* Advance a hierarchy whose levels lmove.. follow the puncture at xp (in/out):
-   per coarse step, the subcycled step with tracking, then the regrid. */
-int oz_bo_advance_moving(oz_level* lv, int nlev, int lmove, double* xp, const oz_params* p, double dt0, int nsteps,
+/* Advance a hierarchy whose patches with obj >= 0 follow the punctures xp
+   (3 per object, in/out): per root step, the subcycled step with tracking,
+   then the regrid. */
+int oz_bo_advance_moving(oz_level* lv, int np, int nobj, double* xp, const oz_params* p, double dt0, int nsteps,
                          int nthreads)
 {
-    if (!xp || lmove < 1 || lmove >= nlev) return -1;
-    if (!p || !(dt0 > 0) || nsteps < 0 || check_levels(lv, nlev)) return -1;
-    int nt = nthreads < 1 ? 1 : nthreads;
-    for (int s = 0; s < nsteps; ++s) {
-        int rc = bo_level(lv, nlev, 0, p, dt0, nt, NULL, 0.0, xp);
-        if (rc) return rc;
-        if ((rc = regrid(lv, nlev, lmove, xp, nt))) return rc;
+    hierarchy H;
+    if (!xp || nobj < 1 || !p || !(dt0 > 0) || nsteps < 0) return -1;
+    int rc = hier_init(&H, lv, np, p, dt0, nobj, xp, nthreads);
+    if (rc) return rc;
+    for (int s = 0; s < nsteps && !rc; ++s) {
+        rc = bo_depth(&H, 0, 0.0);
+        if (!rc) rc = regrid(&H);
     }
-    return 0;
+    hier_release(&H);
+    return rc;
 }
 
-/* probe: 4-point Lagrange interpolation of the shift of one level at x */
+/* probe: 4-point Lagrange interpolation of the shift of one patch at x */
 int oz_interp_beta(const double* u, long sf, const int* n, int ng, const double* h, const double* x0, const double* x,
                    double* b)
 {
@@ -1386,9 +1634,14 @@ int oz_interp_beta(const double* u, long sf, const int* n, int ng, const double*
     return interp_beta(&L, x, b);
 }
 
-/* probe: one regrid of the moving levels toward xp (no time step) */
-int oz_regrid(oz_level* lv, int nlev, int lmove, const double* xp, int nthreads)
+/* probe: one regrid of the moving patches toward xp (no time step) */
+int oz_regrid(oz_level* lv, int np, int nobj, double* xp, int nthreads)
 {
-    if (!xp || lmove < 1 || lmove >= nlev || check_levels(lv, nlev)) return -1;
-    return regrid(lv, nlev, lmove, xp, nthreads < 1 ? 1 : nthreads);
+    hierarchy H;
+    if (!xp || nobj < 1) return -1;
+    int rc = hier_init(&H, lv, np, NULL, 1.0, nobj, xp, nthreads);
+    if (rc) return rc;
+    rc = regrid(&H);
+    hier_release(&H);
+    return rc;
 }

@@ -282,6 +282,44 @@ def bo_level_grids(nlev=6, n=64, h0=4.0, bc0=BC_SOMMERFELD, ng=NG):
     return out
 
 
+def child_grid(gp: Grid, n, center, ng=NG):
+    """A patch of n cells per side (int or 3-tuple) refining gp 2:1, centred
+    on `center`, with its lower faces on parent cell faces.  Returns (grid,
+    F), F the parent active cell index of the lower faces."""
+    if np.isscalar(n):
+        n = (int(n),) * 3
+    hc = tuple(0.5 * float(h) for h in gp.h)
+    F, x0 = [], []
+    for d in range(3):
+        face = (center[d] - 0.5 * n[d] * hc[d] - (gp.x0[d] - 0.5 * gp.h[d])) / gp.h[d]
+        f = int(round(face))
+        if abs(face - f) > 1e-9:
+            raise ValueError("the patch's faces do not fall on parent cell faces")
+        F.append(f)
+        x0.append(gp.x0[d] + (f - 0.25) * gp.h[d])
+    return Grid(tuple(int(v) for v in n), hc, tuple(x0), BC_COPY, ng), tuple(F)
+
+
+def pair_hierarchy(root_n, h0, centers, moving, fixed=(), bc0=BC_PERIODIC, ng=NG):
+    """Patches of a hierarchy with moving levels (paper Sec. 2.2.1, Fig. 1):
+    a root of root_n^3 cells centred on the origin, fixed levels of sizes
+    `fixed` centred on the origin, then moving levels of sizes `moving`,
+    each with one patch per object centred on centers[o].  Returns
+    [(grid, F, parent, obj)] with parents listed before their children and
+    the patches of one depth in object order."""
+    out = [(centered_grid(root_n, h0, bc=bc0, ng=ng), (0, 0, 0), -1, -1)]
+    for n in fixed:
+        g, F = child_grid(out[-1][0], n, (0.0, 0.0, 0.0), ng)
+        out.append((g, F, len(out) - 1, -1))
+    last = {o: len(out) - 1 for o in range(len(centers))}
+    for n in moving:
+        for o, c in enumerate(centers):
+            g, F = child_grid(out[last[o]][0], n, c, ng)
+            out.append((g, F, last[o], o))
+            last[o] = len(out) - 1
+    return out
+
+
 def config_bo_hierarchy(nlev=6, n=64, h0=4.0):
     """Two-puncture Brill-Lindquist data on every level of bo_level_grids,
     pi-symmetrised; coarse step dt0 = 0.5 h0 (level l: 0.5 h0 / 2^l)."""

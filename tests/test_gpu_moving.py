@@ -54,12 +54,12 @@ def _moving_levels(beta, seed=12):
 
 def _oracle_moving(oz, levels, xp, dt0, nsteps, perturb=None):
     lv = []
-    for g, u, F in levels:
+    for l, (g, u, F) in enumerate(levels):
         v = u.copy()
         if perturb is not None:
             v = v + np.spacing(v) * perturb.choice([-1.0, 1.0], size=v.shape)
-        lv.append(oz.Level(g, v, F))
-    x = oz.bo_advance_moving(lv, 1, xp, dt0, nsteps)
+        lv.append(oz.Level(g, v, F, obj=0 if l >= 1 else -1))
+    x = oz.bo_advance_moving(lv, xp, dt0, nsteps)
     return lv, x
 
 

@@ -212,25 +212,36 @@ int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float*
 int z4c_plan_destroy(void* plan);
 
 /* ---------------------------------------------------------------------- */
-/* Box-in-box hierarchy with Berger-Oliger time subcycling (Sec. 2.2.1):  */
-/* level l advances with dt0 / 2^l, two steps per parent step; the        */
-/* child's ghost zone comes from the parent by 6th-order Lagrange         */
-/* prolongation, interpolated in time between the parent's time levels    */
-/* (2nd order; 1st order while the parent has no earlier level); after    */
-/* both child steps the parent cells the child covers are overwritten by  */
-/* the 4th-order Lagrange restriction of the child.                       */
+/* Box-in-box hierarchy with Berger-Oliger time subcycling (Sec. 2.2.1,   */
+/* Fig. 1): a list of patches; patch 0 is the root (the coarsest level,   */
+/* with its own boundary), every other patch names its parent, which it   */
+/* refines 2:1.  A patch at depth d advances with dt0 / 2^d, two steps    */
+/* per parent step, together with every patch of its depth (one launch    */
+/* per RK4 stage).  Fixed levels are single patches; a moving level holds */
+/* one patch per tracked object.  A patch's ghost zone comes from its     */
+/* parent by 6th-order Lagrange prolongation, interpolated in time        */
+/* between the parent's time levels (2nd order; 1st order while the       */
+/* parent has no earlier level).  Patches of one depth exchange data where */
+/* they meet: overlapping active cells take their mean after every step,  */
+/* and a ghost point inside another patch's active region takes that      */
+/* patch's value at every stage.  After the two steps of a depth every    */
+/* coarse cell covered by one of its patches is overwritten by the        */
+/* 4th-order Lagrange restriction (the mean where several cover it).      */
 /* ---------------------------------------------------------------------- */
 
-/* One level (one box).  Geometry as for z4c_box.  Level 0: bc is
- * Z4C_BC_PERIODIC, Z4C_BC_SOMMERFELD or Z4C_BC_EQUATORIAL.  Levels >= 1: bc
- * must be Z4C_BC_COPY (ghosts come from the parent), n even, dx half the
- * parent's, and the lower faces on parent cell faces: F[d] is the parent
- * active cell index of that face, x0[d] = parent x0[d] + (F[d] - 1/4) *
- * parent dx[d] (checked); the 6-point stencils of every ghost must fall in
- * the parent's active cells.  All six arrays are caller-owned device arrays
- * of 25 fields with stride sf: u the state (advanced in place), u_a, u_b,
- * acc the RK4 scratch, prev and cur the level's time levels kept for its
- * child (any contents on entry). */
+/* One patch.  Geometry as for z4c_box.  Patch 0 (the root): parent -1, bc
+ * Z4C_BC_PERIODIC, Z4C_BC_SOMMERFELD or Z4C_BC_EQUATORIAL, obj -1.  Patches
+ * >= 1: parent is the index of a patch listed before it; bc must be
+ * Z4C_BC_COPY (ghosts come from the parent), n even, dx half the parent's,
+ * and the lower faces on parent cell faces: F[d] is the parent active cell
+ * index of that face, x0[d] = parent x0[d] + (F[d] - 1/4) * parent dx[d]
+ * (checked); the 6-point stencils of every ghost must fall in the parent's
+ * active cells.  obj: -1 for a fixed patch, else the index of the tracked
+ * object the patch follows (z4c_hier_set_moving).  All six arrays are
+ * caller-owned device arrays of 25 fields with stride sf, distinct from
+ * every other patch's: u the state (advanced in place), u_a, u_b, acc the
+ * RK4 scratch, prev and cur the patch's time levels kept for its children
+ * (any contents on entry). */
 typedef struct z4c_level {
     int n[3];
     int ng;
@@ -245,37 +256,44 @@ typedef struct z4c_level {
     double* acc;
     double* prev;
     double* cur;
+    int parent;
+    int obj;
 } z4c_level;
 
-/* Create a hierarchy of nlev (1..16) levels advanced with coarse step dt0.
- * tile == NULL: the library default shape with a persistent launch.
- * Allocates one ghost-shell buffer per level >= 1 in device memory
- * (25 x (stored - active) doubles; Z4C_ENOMEM if that fails). */
+/* Create a hierarchy of nlev (1..32) patches, at most 16 per depth,
+ * advanced with root step dt0.  tile == NULL: the library default shape
+ * with a persistent launch.  Allocates one ghost-shell buffer per patch >= 1
+ * in device memory (25 x (stored - active) doubles; Z4C_ENOMEM if that
+ * fails). */
 int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, double dt0, const z4c_tile* tile,
                     void** hier);
 
-/* Advance every level by nsteps coarse steps on `stream`.  Ghosts of the
- * levels' states are not refreshed at the end (call apply_ghosts or read
- * the active cells).  use_graph: from the second coarse step on (every level
- * then holds an earlier time level) one coarse step is captured as a HIP
- * graph on first use and replayed. */
+/* Advance every patch by nsteps root steps on `stream`.  Ghosts of the
+ * patches' states are not refreshed at the end (call apply_ghosts or read
+ * the active cells).  use_graph: once every patch with children holds an
+ * earlier time level, one root step is captured as a HIP graph on first use
+ * and replayed (recaptured after a patch moved). */
 int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream);
 
-/* Moving levels (Sec. 2.2.1): levels lmove.. (1 <= lmove < nlev) follow the
- * puncture that starts at xp (3 doubles, host).  On the finest level it is
- * tracked with dx^i/dt = -beta^i (Heun's method per step, beta by 4-point
- * Lagrange interpolation in each direction).  After every coarse step
- * z4c_hier_advance reads it back (a stream synchronisation) and shifts each
- * moving patch whose centre is more than two of its cells from it, per
- * direction, by two cells toward it -- one parent cell, so F moves by one
- * and x0 by one parent dx; cells it covered before keep their values, newly
- * covered ones are prolonged from the parent.  A shift that would take a
- * patch's stencils out of its parent fails with Z4C_EINVAL.  Allocates 80
- * bytes of device memory. */
-int z4c_hier_set_moving(void* hier, int lmove, const double* xp);
+/* Moving patches (Sec. 2.2.1): the patches with obj >= 0 follow the nobj
+ * (1..16) punctures that start at xp (3 doubles per object, host).  Each
+ * puncture is tracked on its object's deepest patch (exactly one patch of
+ * the object at that depth) with dx^i/dt = -beta^i: Heun's method per step
+ * of that patch, beta by 4-point Lagrange interpolation in each direction
+ * from active cells.  After every root step z4c_hier_advance reads the
+ * punctures back (a stream synchronisation) and, in patch order, shifts each
+ * moving patch whose centre is more than two of its cells from its
+ * puncture, per direction, by two cells toward it -- one parent cell, so F
+ * moves by one and x0 by one parent dx; cells it covered before keep their
+ * values, newly covered ones are prolonged from the parent, its children
+ * keep their place in space (their F moves by -2).  A shift that would take
+ * a patch's stencils out of its parent, or a puncture whose stencil leaves
+ * its patch's active cells, fails with Z4C_EINVAL.  Allocates 80 bytes of
+ * device memory per object. */
+int z4c_hier_set_moving(void* hier, int nobj, const double* xp);
 
-/* Current puncture position (xp, 3 doubles) and, if not NULL, every level's
- * F and x0 (3 per level); synchronises with the device. */
+/* Current punctures (xp, 3 doubles per object; may be NULL) and, if not
+ * NULL, every patch's F and x0 (3 per patch); synchronises with the device. */
 int z4c_hier_puncture(void* hier, double* xp, int* F, double* x0);
 
 int z4c_hier_destroy(void* hier);

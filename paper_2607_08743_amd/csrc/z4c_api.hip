@@ -617,17 +617,28 @@ int z4c_plan_destroy(void* plan)
 // ---------------------------------------------------------------------------
 // Box-in-box hierarchy with Berger-Oliger subcycling
 // ---------------------------------------------------------------------------
-struct HierLevel {
+namespace {
+constexpr int MAXPATCH = 32;
+}
+
+struct HierPatch {
     z4c_level L;
-    double* shell;  // device: ghost shell filled by prolongation (levels >= 1)
+    double* shell;  // device: ghost shell filled by prolongation (patches >= 1)
     long nshell;
-    bool has_prev;  // prev holds this level one step earlier
+    bool has_prev;  // prev holds this patch one step earlier
+    int depth;
+    int off[3];     // lattice index of the first active cell at the patch's depth
+};
+
+struct HierDepth {
+    std::vector<int> q;  // its patches, in index order
     BoxSet fused[4];
-    BoxSet fill[4];  // ghost fill of the stage inputs u, a, b, a
+    BoxSet fill[4];      // ghost fill of the stage inputs u, a, b, a
 };
 
 struct z4c_hier_s {
-    std::vector<HierLevel> lv;
+    std::vector<HierPatch> pt;
+    std::vector<HierDepth> dp;
     ParamsDev prm;
     int precision;
     int tile_index;
@@ -636,11 +647,12 @@ struct z4c_hier_s {
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipStream_t capture;
-    int lmove;      // first moving level (0: none)
-    double* track;  // device: puncture x[3], b0[3], xs[3], error flag
+    int nobj;            // tracked objects (0: no moving patches)
+    int tp[MAXEX];       // per object: the patch it is tracked on
+    double* track;       // device: per object x[3], b0[3], xs[3], error flag
 };
 
-// Geometry of level x against its parent P: 2:1 spacing, lower faces on
+// Geometry of patch x against its parent P: 2:1 spacing, lower faces on
 // parent cell F, every ghost's prolongation stencil in P's active cells.
 static int hier_check_level(const z4c_level& x, const z4c_level& P, const std::string& tag)
 {
@@ -660,45 +672,156 @@ static int hier_check_level(const z4c_level& x, const z4c_level& P, const std::s
     return Z4C_OK;
 }
 
-// (Re)build the stage and ghost-fill sets of level l from its geometry.
-static void hier_build_sets(z4c_hier_s* H, int l)
+// depths, lattice offsets and the per-depth patch lists
+static void hier_geometry(z4c_hier_s* H)
+{
+    int maxd = 0;
+    for (size_t q = 0; q < H->pt.size(); ++q) {
+        HierPatch& P = H->pt[q];
+        if (q == 0) {
+            P.depth = 0;
+            for (int d = 0; d < 3; ++d) P.off[d] = 0;
+            continue;
+        }
+        const HierPatch& R = H->pt[P.L.parent];
+        P.depth = R.depth + 1;
+        maxd = std::max(maxd, P.depth);
+        // child active cell a sits at lattice index 2 (parent's first cell + F) + a
+        for (int d = 0; d < 3; ++d) P.off[d] = 2 * (R.off[d] + P.L.F[d]);
+    }
+    H->dp.resize(maxd + 1);
+    for (HierDepth& D : H->dp) D.q.clear();
+    for (size_t q = 0; q < H->pt.size(); ++q) H->dp[H->pt[q].depth].q.push_back((int)q);
+}
+
+// stage inputs and outputs of the four stages: u -> a -> b -> a -> u
+static double* stage_in(const z4c_level& L, int st)
+{
+    return st == 0 ? L.u : (st == 2 ? L.u_b : L.u_a);
+}
+static double* stage_out(const z4c_level& L, int st)
+{
+    return st == 0 ? L.u_a : (st == 1 ? L.u_b : (st == 2 ? L.u_a : L.u));
+}
+
+// (Re)build the stage and ghost-fill sets of depth d from its patches.
+static void hier_build_sets(z4c_hier_s* H, int d)
 {
     const TileEntry* tab = nullptr;
     tile_table(&tab);
-    HierLevel& L = H->lv[l];
-    const double dt = H->dt0 / (double)(1L << l);
-    double* ins[4] = {L.L.u, L.L.u_a, L.L.u_b, L.L.u_a};
-    double* outs[4] = {L.L.u_a, L.L.u_b, L.L.u_a, L.L.u};
+    HierDepth& D = H->dp[d];
+    const double dt = H->dt0 / (double)(1L << d);
     for (int st = 0; st < 4; ++st) {
-        BoxDev d = make_box(L.L.n, L.L.ng, L.L.bc, L.L.sf, L.L.dx, L.L.x0, dt);
-        d.u_in = ins[st];
-        d.u_n = L.L.u;
-        d.acc = L.L.acc;
-        d.u_out = outs[st];
-        d.shell = L.shell;
-        BoxSet& F = L.fused[st];
+        BoxSet& F = D.fused[st];
         F = BoxSet{};
-        F.nbox = 1;
-        F.box[0] = d;
+        F.nbox = (int)D.q.size();
+        for (int b = 0; b < F.nbox; ++b) {
+            const HierPatch& P = H->pt[D.q[b]];
+            BoxDev x = make_box(P.L.n, P.L.ng, P.L.bc, P.L.sf, P.L.dx, P.L.x0, dt);
+            x.u_in = stage_in(P.L, st);
+            x.u_n = P.L.u;
+            x.acc = P.L.acc;
+            x.u_out = stage_out(P.L, st);
+            x.shell = P.shell;
+            F.box[b] = x;
+        }
         finalize_set(F, tab[H->tile_index].tile);
-        L.fill[st] = F;
+        D.fill[st] = F;
     }
 }
 
-static hipError_t hier_track(z4c_hier_s* H, int l, int mode, hipStream_t s)
+static PatchRef patch_ref(const HierPatch& P, double* arr)
 {
-    const HierLevel& L = H->lv[l];
-    TrackArgs a{};
-    a.state = H->track;
-    a.u = L.L.u;
-    a.sf = L.L.sf;
+    PatchRef r{};
+    r.u = arr;
+    r.sf = P.L.sf;
+    r.ng = P.L.ng;
     for (int d = 0; d < 3; ++d) {
-        a.N[d] = L.L.n[d] + 2 * L.L.ng;
-        a.x0[d] = L.L.x0[d];
-        a.h[d] = L.L.dx[d];
+        r.N[d] = P.L.n[d] + 2 * P.L.ng;
+        r.n[d] = P.L.n[d];
+        r.off[d] = P.off[d];
     }
-    a.ng = L.L.ng;
-    a.dt = H->dt0 / (double)(1L << l);
+    return r;
+}
+
+// intersection of the lattice box [lo, lo + ext) with the bounding box of
+// the active regions of the depth's patches other than t; false if empty
+static bool others_box(const ExchArgs& a, int lo[3], int ext[3])
+{
+    int blo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, bhi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int b = 0; b < a.np; ++b) {
+        if (b == a.t) continue;
+        for (int d = 0; d < 3; ++d) {
+            blo[d] = std::min(blo[d], a.p[b].off[d]);
+            bhi[d] = std::max(bhi[d], a.p[b].off[d] + a.p[b].n[d]);
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        const int l = std::max(lo[d], blo[d]), h = std::min(lo[d] + ext[d], bhi[d]);
+        if (h <= l) return false;
+        lo[d] = l;
+        ext[d] = h - l;
+    }
+    return true;
+}
+
+// exchange at depth d on the stage-st input arrays: ghosts inside another
+// patch's active region take its values
+static hipError_t hier_exchange_ghosts(z4c_hier_s* H, int d, int st, hipStream_t s)
+{
+    const HierDepth& D = H->dp[d];
+    if (D.q.size() < 2) return hipSuccess;
+    ExchArgs a{};
+    a.np = (int)D.q.size();
+    for (int b = 0; b < a.np; ++b) a.p[b] = patch_ref(H->pt[D.q[b]], stage_in(H->pt[D.q[b]].L, st));
+    for (int t = 0; t < a.np; ++t) {
+        a.t = t;
+        for (int e = 0; e < 3; ++e) {
+            a.lo[e] = a.p[t].off[e] - a.p[t].ng;
+            a.ext[e] = a.p[t].N[e];
+        }
+        if (!others_box(a, a.lo, a.ext)) continue;
+        hipError_t e = launch_exchange_ghosts(a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// exchange at depth d on the states: overlapping active cells take their mean
+static hipError_t hier_exchange_average(z4c_hier_s* H, int d, hipStream_t s)
+{
+    const HierDepth& D = H->dp[d];
+    if (D.q.size() < 2) return hipSuccess;
+    ExchArgs a{};
+    a.np = (int)D.q.size();
+    for (int b = 0; b < a.np; ++b) a.p[b] = patch_ref(H->pt[D.q[b]], H->pt[D.q[b]].L.u);
+    for (int t = 0; t < a.np; ++t) {
+        a.t = t;
+        for (int e = 0; e < 3; ++e) {
+            a.lo[e] = a.p[t].off[e];
+            a.ext[e] = a.p[t].n[e];
+        }
+        if (!others_box(a, a.lo, a.ext)) continue;
+        hipError_t e = launch_exchange_average(a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t hier_track(z4c_hier_s* H, int o, int mode, hipStream_t s)
+{
+    const HierPatch& P = H->pt[H->tp[o]];
+    TrackArgs a{};
+    a.state = H->track + 10 * o;
+    a.u = P.L.u;
+    a.sf = P.L.sf;
+    for (int d = 0; d < 3; ++d) {
+        a.N[d] = P.L.n[d] + 2 * P.L.ng;
+        a.x0[d] = P.L.x0[d];
+        a.h[d] = P.L.dx[d];
+    }
+    a.ng = P.L.ng;
+    a.dt = H->dt0 / (double)(1L << P.depth);
     a.mode = mode;
     return launch_track(a, s);
 }
@@ -718,91 +841,118 @@ static void hier_time_weights(double theta, bool quadratic, double wt[3])
     }
 }
 
-static hipError_t hier_prolong(z4c_hier_s* H, int l, double theta, hipStream_t s)
+// the ghost shells of every patch at depth d at theta (fraction of the parent step)
+static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s)
 {
-    HierLevel& C = H->lv[l];
-    const HierLevel& P = H->lv[l - 1];
-    ProlongArgs a{};
-    hier_time_weights(theta, P.has_prev, a.wt);
-    a.pa[0] = P.has_prev ? P.L.prev : nullptr;
-    a.pa[1] = P.L.cur;
-    a.pa[2] = P.L.u;
-    a.sfp = P.L.sf;
-    for (int d = 0; d < 3; ++d) {
-        a.Np[d] = P.L.n[d] + 2 * P.L.ng;
-        a.nc[d] = C.L.n[d];
-        a.F[d] = C.L.F[d];
+    for (int q : H->dp[d].q) {
+        HierPatch& C = H->pt[q];
+        const HierPatch& P = H->pt[C.L.parent];
+        ProlongArgs a{};
+        hier_time_weights(theta, P.has_prev, a.wt);
+        a.pa[0] = P.has_prev ? P.L.prev : nullptr;
+        a.pa[1] = P.L.cur;
+        a.pa[2] = P.L.u;
+        a.sfp = P.L.sf;
+        for (int e = 0; e < 3; ++e) {
+            a.Np[e] = P.L.n[e] + 2 * P.L.ng;
+            a.nc[e] = C.L.n[e];
+            a.F[e] = C.L.F[e];
+        }
+        a.ngp = P.L.ng;
+        a.shell = C.shell;
+        a.nshell = C.nshell;
+        a.ngc = C.L.ng;
+        hipError_t e = launch_prolong(a, s);
+        if (e != hipSuccess) return e;
     }
-    a.ngp = P.L.ng;
-    a.shell = C.shell;
-    a.nshell = C.nshell;
-    a.ngc = C.L.ng;
-    return launch_prolong(a, s);
+    return hipSuccess;
 }
 
-static hipError_t hier_restrict(z4c_hier_s* H, int l, hipStream_t s)
+// every patch at depth d: the cells covered by the patches of depth d+1
+static hipError_t hier_restrict(z4c_hier_s* H, int d, hipStream_t s)
 {
-    const HierLevel& C = H->lv[l];
-    HierLevel& P = H->lv[l - 1];
+    const HierDepth& C = H->dp[d + 1];
     RestrictArgs a{};
-    a.uc = C.L.u;
-    a.sfc = C.L.sf;
-    a.ngc = C.L.ng;
-    a.up = P.L.u;
-    a.sfp = P.L.sf;
-    a.ngp = P.L.ng;
-    for (int d = 0; d < 3; ++d) {
-        a.Nc[d] = C.L.n[d] + 2 * C.L.ng;
-        a.nc[d] = C.L.n[d];
-        a.Np[d] = P.L.n[d] + 2 * P.L.ng;
-        a.F[d] = C.L.F[d];
+    a.nchild = (int)C.q.size();
+    int clo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, chi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int c = 0; c < a.nchild; ++c) {
+        a.child[c] = patch_ref(H->pt[C.q[c]], H->pt[C.q[c]].L.u);
+        for (int e = 0; e < 3; ++e) {  // covered lattice cells of depth d (off and n are even)
+            clo[e] = std::min(clo[e], a.child[c].off[e] / 2);
+            chi[e] = std::max(chi[e], (a.child[c].off[e] + a.child[c].n[e]) / 2);
+        }
     }
-    return launch_restrict(a, s);
+    for (int q : H->dp[d].q) {
+        const HierPatch& P = H->pt[q];
+        a.parent = patch_ref(P, P.L.u);
+        bool empty = false;
+        for (int e = 0; e < 3; ++e) {
+            const int l = std::max(0, clo[e] - P.off[e]), h = std::min(P.L.n[e], chi[e] - P.off[e]);
+            empty |= h <= l;
+            a.lo[e] = l;
+            a.ext[e] = h - l;
+        }
+        if (empty) continue;
+        hipError_t e = launch_restrict(a, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-// One RK4 step of level l starting at theta0 (fraction of the parent step),
-// then, if it has a child, the child's two steps, its ghost fill at the end
-// time and the restriction.  Stage inputs get their ghosts at the stage
-// times theta0 + {0, 1/4, 1/4, 1/2}.
-static hipError_t hier_level_step(z4c_hier_s* H, int l, double theta0, hipStream_t s)
+// One RK4 step of every patch at depth d starting at theta0 (fraction of
+// the parent step), then, if there is a finer depth, its two steps, its
+// ghost fill at the end time and the restriction.  Stage inputs get their
+// ghosts (prolongation, then the exchange) at the stage times theta0 + {0,
+// 1/4, 1/4, 1/2}; overlapping active cells are averaged after the last stage.
+static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream_t s)
 {
     const TileEntry* tab = nullptr;
     tile_table(&tab);
     const TileEntry& T = tab[H->tile_index];
-    HierLevel& L = H->lv[l];
-    const int nlev = (int)H->lv.size();
-    const bool outer = l == 0 && (L.L.bc == Z4C_BC_SOMMERFELD || L.L.bc == Z4C_BC_EQUATORIAL);
-    const long n = (long)NF * L.L.sf;
+    HierDepth& D = H->dp[d];
+    const int ndepth = (int)H->dp.size();
+    const z4c_level& R = H->pt[0].L;
+    const bool outer = d == 0 && (R.bc == Z4C_BC_SOMMERFELD || R.bc == Z4C_BC_EQUATORIAL);
     hipError_t e;
     auto fill = [&](int st) -> hipError_t {
-        if (l == 0 && L.L.bc == Z4C_BC_SOMMERFELD) return hipSuccess;
-        return launch_ghosts(L.fill[st], s);
-    };
-    auto stage = [&](int st) -> hipError_t {
-        hipError_t r = T.launch(L.fused[st], H->prm, MODE_STAGE, st + 1, H->persistent, s);
-        if (r == hipSuccess && outer) r = launch_sommerfeld(L.fused[st], H->prm, MODE_STAGE, st + 1, s);
+        hipError_t r = hipSuccess;
+        if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD)) r = launch_ghosts(D.fill[st], s);
+        if (r == hipSuccess) r = hier_exchange_ghosts(H, d, st, s);
         return r;
     };
-    if (l > 0 && theta0 == 0.0 && (e = hier_prolong(H, l, 0.0, s)) != hipSuccess) return e;
+    auto stage = [&](int st) -> hipError_t {
+        hipError_t r = T.launch(D.fused[st], H->prm, MODE_STAGE, st + 1, H->persistent, s);
+        if (r == hipSuccess && outer) r = launch_sommerfeld(D.fused[st], H->prm, MODE_STAGE, st + 1, s);
+        return r;
+    };
+    if (d > 0 && theta0 == 0.0 && (e = hier_prolong(H, d, 0.0, s)) != hipSuccess) return e;
     if ((e = fill(0)) != hipSuccess) return e;
-    if (l + 1 < nlev && (e = launch_copy(L.L.cur, L.L.u, n, s)) != hipSuccess) return e;
-    const bool track = H->lmove > 0 && l == nlev - 1;
-    if (track && (e = hier_track(H, l, 0, s)) != hipSuccess) return e;
+    if (d + 1 < ndepth)
+        for (int q : D.q)
+            if ((e = launch_copy(H->pt[q].L.cur, H->pt[q].L.u, (long)NF * H->pt[q].L.sf, s)) != hipSuccess) return e;
+    for (int o = 0; o < H->nobj; ++o)
+        if (H->pt[H->tp[o]].depth == d && (e = hier_track(H, o, 0, s)) != hipSuccess) return e;
     if ((e = stage(0)) != hipSuccess) return e;
-    if (l > 0 && (e = hier_prolong(H, l, theta0 + 0.25, s)) != hipSuccess) return e;
+    if (d > 0 && (e = hier_prolong(H, d, theta0 + 0.25, s)) != hipSuccess) return e;
     if ((e = fill(1)) != hipSuccess || (e = stage(1)) != hipSuccess) return e;
     if ((e = fill(2)) != hipSuccess || (e = stage(2)) != hipSuccess) return e;
-    if (l > 0 && (e = hier_prolong(H, l, theta0 + 0.5, s)) != hipSuccess) return e;
+    if (d > 0 && (e = hier_prolong(H, d, theta0 + 0.5, s)) != hipSuccess) return e;
     if ((e = fill(3)) != hipSuccess || (e = stage(3)) != hipSuccess) return e;
-    if (track && (e = hier_track(H, l, 1, s)) != hipSuccess) return e;
-    if (l + 1 < nlev) {
-        if ((e = hier_level_step(H, l + 1, 0.0, s)) != hipSuccess) return e;
-        if ((e = hier_level_step(H, l + 1, 0.5, s)) != hipSuccess) return e;
-        if ((e = hier_prolong(H, l + 1, 1.0, s)) != hipSuccess) return e;
-        if ((e = launch_ghosts(H->lv[l + 1].fill[0], s)) != hipSuccess) return e;
-        if ((e = hier_restrict(H, l + 1, s)) != hipSuccess) return e;
-        if ((e = launch_copy(L.L.prev, L.L.cur, n, s)) != hipSuccess) return e;
-        L.has_prev = true;
+    if ((e = hier_exchange_average(H, d, s)) != hipSuccess) return e;
+    for (int o = 0; o < H->nobj; ++o)
+        if (H->pt[H->tp[o]].depth == d && (e = hier_track(H, o, 1, s)) != hipSuccess) return e;
+    if (d + 1 < ndepth) {
+        if ((e = hier_depth_step(H, d + 1, 0.0, s)) != hipSuccess) return e;
+        if ((e = hier_depth_step(H, d + 1, 0.5, s)) != hipSuccess) return e;
+        if ((e = hier_prolong(H, d + 1, 1.0, s)) != hipSuccess) return e;
+        if ((e = launch_ghosts(H->dp[d + 1].fill[0], s)) != hipSuccess) return e;
+        if ((e = hier_exchange_ghosts(H, d + 1, 0, s)) != hipSuccess) return e;
+        if ((e = hier_restrict(H, d, s)) != hipSuccess) return e;
+        for (int q : D.q) {
+            HierPatch& P = H->pt[q];
+            if ((e = launch_copy(P.L.prev, P.L.cur, (long)NF * P.L.sf, s)) != hipSuccess) return e;
+            P.has_prev = true;
+        }
     }
     return hipSuccess;
 }
@@ -818,8 +968,8 @@ static void hier_drop_graph(z4c_hier_s* H)
 static void hier_free(z4c_hier_s* H)
 {
     hier_drop_graph(H);
-    for (HierLevel& L : H->lv)
-        if (L.shell) (void)hipFree(L.shell);
+    for (HierPatch& P : H->pt)
+        if (P.shell) (void)hipFree(P.shell);
     if (H->track) (void)hipFree(H->track);
     if (H->capture) (void)hipStreamDestroy(H->capture);
     delete H;
@@ -832,11 +982,12 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
     if (!hier) return fail(Z4C_EINVAL, "hier is NULL");
     *hier = nullptr;
     if ((rc = check_params(p))) return rc;
-    if (!levels || nlev < 1 || nlev > MAXBOX) return fail(Z4C_EINVAL, "need 1..16 levels");
+    if (!levels || nlev < 1 || nlev > MAXPATCH) return fail(Z4C_EINVAL, "need 1..32 patches");
     if (!finite_pos(dt0)) return fail(Z4C_EINVAL, "dt0 must be finite and > 0");
+    std::vector<int> depth(nlev, 0);
     for (int l = 0; l < nlev; ++l) {
         const z4c_level& x = levels[l];
-        const std::string tag = "level " + std::to_string(l) + ": ";
+        const std::string tag = "patch " + std::to_string(l) + ": ";
         long stored = 0;
         if ((rc = check_geom(x.sf, x.n[0], x.n[1], x.n[2], x.ng, x.bc, &stored)) ||
             (rc = check_spacing(x.dx[0], x.dx[1], x.dx[2], x.x0[0], x.x0[1], x.x0[2])))
@@ -846,14 +997,30 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
             if (!arr[i]) return fail(Z4C_EINVAL, tag + "all six state arrays are required");
             for (int j = 0; j < i; ++j)
                 if (overlap(arr[i], arr[j], x.sf)) return fail(Z4C_EINVAL, tag + "state arrays overlap");
+            for (int m = 0; m < l; ++m) {
+                const z4c_level& y = levels[m];
+                const double* brr[6] = {y.u, y.u_a, y.u_b, y.acc, y.prev, y.cur};
+                for (int j = 0; j < 6; ++j)
+                    if (overlap(arr[i], brr[j], std::max(x.sf, y.sf)))
+                        return fail(Z4C_EINVAL, tag + "state arrays overlap those of patch " + std::to_string(m));
+            }
         }
+        if (x.obj < -1) return fail(Z4C_EINVAL, tag + "obj must be -1 (fixed) or a tracked object index");
         if (l == 0) {
-            if (x.bc == Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "the coarsest level needs its own boundary");
+            if (x.parent != -1) return fail(Z4C_EINVAL, tag + "the root (patch 0) has parent -1");
+            if (x.bc == Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "the root needs its own boundary");
+            if (x.obj != -1) return fail(Z4C_EINVAL, tag + "the root cannot move");
             continue;
         }
-        if (x.bc != Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "levels >= 1 take Z4C_BC_COPY (filled from the parent)");
-        if ((rc = hier_check_level(x, levels[l - 1], tag))) return rc;
+        if (x.parent < 0 || x.parent >= l) return fail(Z4C_EINVAL, tag + "parent must be a patch listed before it");
+        if (x.bc != Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "patches >= 1 take Z4C_BC_COPY (filled from the parent)");
+        if ((rc = hier_check_level(x, levels[x.parent], tag))) return rc;
+        depth[l] = depth[x.parent] + 1;
+        if (depth[l] > 30) return fail(Z4C_EINVAL, tag + "deeper than 30 levels");
     }
+    for (int dd = 0; dd <= 30; ++dd)
+        if (std::count(depth.begin(), depth.end(), dd) > MAXEX)
+            return fail(Z4C_EINVAL, "more than 16 patches at depth " + std::to_string(dd));
     int pers = 1;
     int ti;
     if (tile) {
@@ -864,36 +1031,35 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         ti = default_tile_index(p->precision);
         if (ti < 0) return fail(Z4C_EUNSUPPORTED, "no tile compiled for this precision");
     }
-    const TileEntry* tab = nullptr;
-    tile_table(&tab);
     z4c_hier_s* H = new z4c_hier_s{};
     H->prm = to_dev(p);
     H->precision = p->precision;
     H->tile_index = ti;
     H->persistent = pers;
     H->dt0 = dt0;
-    H->lv.resize(nlev);
+    H->pt.resize(nlev);
     for (int l = 0; l < nlev; ++l) {
-        HierLevel& L = H->lv[l];
-        L.L = levels[l];
-        L.shell = nullptr;
-        L.has_prev = false;
-        L.nshell = l > 0 ? shell_size(L.L.n, L.L.ng) : 0;
+        HierPatch& P = H->pt[l];
+        P.L = levels[l];
+        P.shell = nullptr;
+        P.has_prev = false;
+        P.nshell = l > 0 ? shell_size(P.L.n, P.L.ng) : 0;
         if (l > 0) {
-            hipError_t e = hipMalloc((void**)&L.shell, (size_t)NF * L.nshell * sizeof(double));
+            hipError_t e = hipMalloc((void**)&P.shell, (size_t)NF * P.nshell * sizeof(double));
             if (e != hipSuccess) {
-                L.shell = nullptr;
+                P.shell = nullptr;
                 hier_free(H);
                 return fail(Z4C_ENOMEM, "ghost shell allocation failed");
             }
         }
-        hier_build_sets(H, l);
     }
+    hier_geometry(H);
+    for (int d = 0; d < (int)H->dp.size(); ++d) hier_build_sets(H, d);
     *hier = H;
     return Z4C_OK;
 }
 
-// capture one coarse step on the private stream (every parent holds an
+// capture one root step on the private stream (every parent holds an
 // earlier level, so the schedule no longer changes from step to step)
 static int hier_capture(z4c_hier_s* H)
 {
@@ -905,7 +1071,7 @@ static int hier_capture(z4c_hier_s* H)
     // captured on a private stream; the instantiated graph runs on the caller's
     if ((e = hipStreamBeginCapture(H->capture, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = hier_level_step(H, 0, 0.0, H->capture);
+    hipError_t le = hier_depth_step(H, 0, 0.0, H->capture);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(H->capture, &g);
     if (le != hipSuccess) {
@@ -923,70 +1089,82 @@ static int hier_capture(z4c_hier_s* H)
     return Z4C_OK;
 }
 
-// After a coarse step: read the puncture back and shift every moving patch
-// whose centre is more than two of its cells away from it (per direction)
-// by two cells toward it; cells it covered before keep their values, new
-// ones are prolonged from the (already shifted) parent.  The captured step
-// is dropped when a patch moved (its geometry is baked into the graph).
+// After a root step: read the punctures back and shift every moving patch
+// (in index order, so parents first) whose centre is more than two of its
+// cells away from its object's puncture (per direction) by two cells toward
+// it; cells it covered before keep their values, new ones are prolonged from
+// the (already shifted) parent, and its children keep their place in space.
+// The captured step is dropped when a patch moved (its geometry is baked
+// into the graph).
 static int hier_regrid(z4c_hier_s* H, hipStream_t s)
 {
     hipError_t e;
-    double st[10];
+    std::vector<double> st(10 * (size_t)H->nobj);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if ((e = hipMemcpy(st, H->track, sizeof(st), hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy (puncture)");
-    if (st[9] != 0.0) return fail(Z4C_EINVAL, "the puncture left the finest level");
-    const int nlev = (int)H->lv.size();
+    if ((e = hipMemcpy(st.data(), H->track, st.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy (punctures)");
+    for (int o = 0; o < H->nobj; ++o)
+        if (st[10 * o + 9] != 0.0)
+            return fail(Z4C_EINVAL, "puncture " + std::to_string(o) + " left the active cells of its finest patch");
+    const int np = (int)H->pt.size();
     bool moved = false;
-    for (int l = H->lmove; l < nlev; ++l) {
-        HierLevel& L = H->lv[l];
+    for (int q = 1; q < np; ++q) {
+        HierPatch& P = H->pt[q];
+        const int o = P.L.obj;
+        if (o < 0 || o >= H->nobj) continue;
         int sh[3];
         bool any = false;
         for (int d = 0; d < 3; ++d) {
-            const double c = L.L.x0[d] + 0.5 * (L.L.n[d] - 1) * L.L.dx[d];
-            sh[d] = st[d] - c > 2.0 * L.L.dx[d] ? 1 : (st[d] - c < -2.0 * L.L.dx[d] ? -1 : 0);
+            const double c = P.L.x0[d] + 0.5 * (P.L.n[d] - 1) * P.L.dx[d];
+            const double x = st[10 * o + d];
+            sh[d] = x - c > 2.0 * P.L.dx[d] ? 1 : (x - c < -2.0 * P.L.dx[d] ? -1 : 0);
             any |= sh[d] != 0;
         }
         if (!any) continue;
-        z4c_level nl = L.L;
+        z4c_level nl = P.L;
         for (int d = 0; d < 3; ++d) {
             nl.F[d] += sh[d];
-            nl.x0[d] += 2.0 * sh[d] * L.L.dx[d];
+            nl.x0[d] += 2.0 * sh[d] * P.L.dx[d];
         }
         int rc;
-        const std::string tag = "regrid of level " + std::to_string(l) + ": ";
-        if ((rc = hier_check_level(nl, H->lv[l - 1].L, tag))) return rc;
-        if (l + 1 < nlev) {
-            z4c_level cl = H->lv[l + 1].L;
+        const std::string tag = "regrid of patch " + std::to_string(q) + ": ";
+        const HierPatch& R = H->pt[P.L.parent];
+        if ((rc = hier_check_level(nl, R.L, tag))) return rc;
+        for (int c = q + 1; c < np; ++c) {
+            if (H->pt[c].L.parent != q) continue;
+            z4c_level cl = H->pt[c].L;
             for (int d = 0; d < 3; ++d) cl.F[d] -= 2 * sh[d];
-            if ((rc = hier_check_level(cl, nl, tag + "child: "))) return rc;
+            if ((rc = hier_check_level(cl, nl, tag + "child " + std::to_string(c) + ": "))) return rc;
         }
-        const HierLevel& P = H->lv[l - 1];
         ShiftArgs a{};
-        a.uc = L.L.u;
-        a.out = L.L.u_a;
-        a.sfc = L.L.sf;
-        a.ngc = L.L.ng;
-        a.up = P.L.u;
-        a.sfp = P.L.sf;
-        a.ngp = P.L.ng;
+        a.uc = P.L.u;
+        a.out = P.L.u_a;
+        a.sfc = P.L.sf;
+        a.ngc = P.L.ng;
+        a.up = R.L.u;
+        a.sfp = R.L.sf;
+        a.ngp = R.L.ng;
         for (int d = 0; d < 3; ++d) {
-            a.Nc[d] = L.L.n[d] + 2 * L.L.ng;
-            a.nc[d] = L.L.n[d];
+            a.Nc[d] = P.L.n[d] + 2 * P.L.ng;
+            a.nc[d] = P.L.n[d];
             a.s[d] = sh[d];
-            a.Np[d] = P.L.n[d] + 2 * P.L.ng;
+            a.Np[d] = R.L.n[d] + 2 * R.L.ng;
             a.F[d] = nl.F[d];
         }
         if ((e = launch_shift(a, s)) != hipSuccess) return hip_fail(e, "patch shift launch");
-        if ((e = launch_copy(L.L.u, L.L.u_a, (long)NF * L.L.sf, s)) != hipSuccess) return hip_fail(e, "copy launch");
-        L.L = nl;
-        L.has_prev = false;
-        hier_build_sets(H, l);
-        if (l + 1 < nlev)
-            for (int d = 0; d < 3; ++d) H->lv[l + 1].L.F[d] -= 2 * sh[d];
+        if ((e = launch_copy(P.L.u, P.L.u_a, (long)NF * P.L.sf, s)) != hipSuccess) return hip_fail(e, "copy launch");
+        P.L = nl;
+        P.has_prev = false;
+        for (int c = q + 1; c < np; ++c)
+            if (H->pt[c].L.parent == q)
+                for (int d = 0; d < 3; ++d) H->pt[c].L.F[d] -= 2 * sh[d];
+        hier_geometry(H);
         moved = true;
     }
-    if (moved) hier_drop_graph(H);
+    if (moved) {
+        for (int d = 0; d < (int)H->dp.size(); ++d) hier_build_sets(H, d);
+        hier_drop_graph(H);
+    }
     return Z4C_OK;
 }
 
@@ -999,8 +1177,9 @@ int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pending HIP error before z4c_hier_advance");
     auto primed = [&]() {
-        for (size_t l = 0; l + 1 < H->lv.size(); ++l)
-            if (!H->lv[l].has_prev) return false;
+        const int last = (int)H->dp.size() - 1;
+        for (const HierPatch& P : H->pt)
+            if (P.depth < last && !P.has_prev) return false;
         return true;
     };
     for (int i = 0; i < nsteps; ++i) {
@@ -1010,10 +1189,10 @@ int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream)
             int rc;
             if (!H->exec && (rc = hier_capture(H))) return rc;
             if ((e = hipGraphLaunch(H->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-        } else if ((e = hier_level_step(H, 0, 0.0, s)) != hipSuccess) {
+        } else if ((e = hier_depth_step(H, 0, 0.0, s)) != hipSuccess) {
             return hip_fail(e, "hierarchy step launch");
         }
-        if (H->lmove > 0) {
+        if (H->nobj > 0) {
             int rc = hier_regrid(H, s);
             if (rc) return rc;
         }
@@ -1021,40 +1200,68 @@ int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream)
     return Z4C_OK;
 }
 
-int z4c_hier_set_moving(void* hier, int lmove, const double* xp)
+int z4c_hier_set_moving(void* hier, int nobj, const double* xp)
 {
     if (!hier || !xp) return fail(Z4C_EINVAL, "hier and xp must be non-NULL");
     z4c_hier_s* H = (z4c_hier_s*)hier;
-    const int nlev = (int)H->lv.size();
-    if (lmove < 1 || lmove >= nlev) return fail(Z4C_EINVAL, "moving levels must start at 1..nlev-1");
-    for (int d = 0; d < 3; ++d)
-        if (!std::isfinite(xp[d])) return fail(Z4C_EINVAL, "non-finite puncture position");
-    hipError_t e;
-    if (!H->track && (e = hipMalloc((void**)&H->track, 10 * sizeof(double))) != hipSuccess) {
-        H->track = nullptr;
-        return fail(Z4C_ENOMEM, "puncture state allocation failed");
+    if (nobj < 1 || nobj > MAXEX) return fail(Z4C_EINVAL, "nobj must be 1..16");
+    for (int i = 0; i < 3 * nobj; ++i)
+        if (!std::isfinite(xp[i])) return fail(Z4C_EINVAL, "non-finite puncture position");
+    int tp[MAXEX];
+    for (int o = 0; o < nobj; ++o) {
+        int best = -1, count = 0;
+        for (int q = 0; q < (int)H->pt.size(); ++q) {
+            if (H->pt[q].L.obj != o) continue;
+            if (best < 0 || H->pt[q].depth > H->pt[best].depth) {
+                best = q;
+                count = 1;
+            } else if (H->pt[q].depth == H->pt[best].depth) {
+                ++count;
+            }
+        }
+        if (best < 0) return fail(Z4C_EINVAL, "object " + std::to_string(o) + " has no patch");
+        if (count != 1) return fail(Z4C_EINVAL, "object " + std::to_string(o) + " has several patches at its deepest depth");
+        tp[o] = best;
     }
-    const double st[10] = {xp[0], xp[1], xp[2], 0, 0, 0, xp[0], xp[1], xp[2], 0};
-    if ((e = hipMemcpy(H->track, st, sizeof(st), hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy (puncture)");
-    H->lmove = lmove;
+    for (const HierPatch& P : H->pt)
+        if (P.L.obj >= nobj) return fail(Z4C_EINVAL, "a patch follows an object index >= nobj");
+    hipError_t e;
+    if (nobj > H->nobj || !H->track) {
+        if (H->track) (void)hipFree(H->track);
+        H->track = nullptr;
+        if ((e = hipMalloc((void**)&H->track, 80 * (size_t)nobj)) != hipSuccess) {
+            H->track = nullptr;
+            H->nobj = 0;
+            return fail(Z4C_ENOMEM, "puncture state allocation failed");
+        }
+    }
+    std::vector<double> st(10 * (size_t)nobj, 0.0);
+    for (int o = 0; o < nobj; ++o)
+        for (int d = 0; d < 3; ++d) st[10 * o + d] = st[10 * o + 6 + d] = xp[3 * o + d];
+    if ((e = hipMemcpy(H->track, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy (punctures)");
+    H->nobj = nobj;
+    for (int o = 0; o < nobj; ++o) H->tp[o] = tp[o];
     hier_drop_graph(H);
     return Z4C_OK;
 }
 
 int z4c_hier_puncture(void* hier, double* xp, int* F, double* x0)
 {
-    if (!hier || !xp) return fail(Z4C_EINVAL, "hier and xp must be non-NULL");
+    if (!hier) return fail(Z4C_EINVAL, "hier is NULL");
     z4c_hier_s* H = (z4c_hier_s*)hier;
-    if (!H->track) return fail(Z4C_EINVAL, "no moving levels (z4c_hier_set_moving)");
-    double st[10];
-    hipError_t e = hipMemcpy(st, H->track, sizeof(st), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy (puncture)");
-    for (int d = 0; d < 3; ++d) xp[d] = st[d];
-    for (size_t l = 0; l < H->lv.size(); ++l)
+    if (xp) {
+        if (!H->track || H->nobj < 1) return fail(Z4C_EINVAL, "no moving patches (z4c_hier_set_moving)");
+        std::vector<double> st(10 * (size_t)H->nobj);
+        hipError_t e = hipMemcpy(st.data(), H->track, st.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy (punctures)");
+        for (int o = 0; o < H->nobj; ++o)
+            for (int d = 0; d < 3; ++d) xp[3 * o + d] = st[10 * o + d];
+    }
+    for (size_t q = 0; q < H->pt.size(); ++q)
         for (int d = 0; d < 3; ++d) {
-            if (F) F[3 * l + d] = H->lv[l].L.F[d];
-            if (x0) x0[3 * l + d] = H->lv[l].L.x0[d];
+            if (F) F[3 * q + d] = H->pt[q].L.F[d];
+            if (x0) x0[3 * q + d] = H->pt[q].L.x0[d];
         }
     return Z4C_OK;
 }

@@ -6,10 +6,13 @@
 //   prolongation: the child's ghost shell from the parent, 6th-order Lagrange
 //     interpolation in each direction (tensor product, 6x6x6 parent cells), of
 //     the parent time levels combined with the caller's time weights;
-//   restriction: every parent cell covered by the child's active region from
-//     the 4th-order Lagrange interpolation of the 4x4x4 child cells around
-//     its centre.
-// Both are HBM/L2 gather kernels, one thread per output point.
+//   restriction: every coarse cell covered by the active region of a finer
+//     patch from the 4th-order Lagrange interpolation of the 4x4x4 child
+//     cells around its centre (the mean where several patches cover it);
+//   exchange between the patches of one depth: overlapping active cells take
+//     their mean, a ghost inside another patch's active region its value;
+//   moving patches: puncture tracking and two-cell patch shifts.
+// All are HBM/L2 gather kernels, one thread per output point.
 #include <hip/hip_runtime.h>
 
 #include "z4c_internal.h"
@@ -183,7 +186,7 @@ __global__ void __launch_bounds__(256) shift_patch(ShiftArgs a)
 // steps.  st = {x[3], b0[3], xs[3], err}.  mode 0 (before a step): b0 =
 // beta(x), xs = x - dt b0; mode 1 (after it): x -= dt/2 (b0 + beta(xs)).
 // beta by 4-point Lagrange interpolation in each direction (cell centres
-// i0-1 .. i0+2 around the point).  One thread: 64 terms per component.
+// i0-1 .. i0+2 around the point, all active).  One thread: 64 terms per component.
 __global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
 {
     if (threadIdx.x != 0) return;
@@ -193,12 +196,18 @@ __global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
     int lo[3];
     for (int d = 0; d < 3; ++d) {
         const double sc = (x[d] - a.x0[d]) / a.h[d];
-        const int i0 = (int)floor(sc);
-        lo[d] = i0 - 1 + a.ng;
-        if (lo[d] < 0 || lo[d] + 3 >= a.N[d]) {  // outside the level: flag it, read nothing
+        const int n = a.N[d] - 2 * a.ng;
+        // stencil cells i0-1 .. i0+2 must be active: otherwise flag it, read nothing
+        if (!(sc > -2.0 && sc < n + 1.0)) {
             st[9] = 1.0;
             return;
         }
+        const int i0 = (int)floor(sc);
+        if (i0 - 1 < 0 || i0 + 2 >= n) {
+            st[9] = 1.0;
+            return;
+        }
+        lo[d] = i0 - 1 + a.ng;
         const double t = sc - i0;
         // nodes -1, 0, 1, 2
         w[d][0] = (t - 0.0) * (t - 1.0) * (t - 2.0) / ((-1.0) * (-2.0) * (-3.0));
@@ -233,29 +242,110 @@ __device__ __forceinline__ double rsum(double c0, double c1, double c2, double c
     return kR1 * (c1 + c2) + kR0 * (c0 + c3);
 }
 
+__device__ __forceinline__ bool in_active(const PatchRef& p, int g0, int g1, int g2)
+{
+    const int a0 = g0 - p.off[0], a1 = g1 - p.off[1], a2 = g2 - p.off[2];
+    return a0 >= 0 && a0 < p.n[0] && a1 >= 0 && a1 < p.n[1] && a2 >= 0 && a2 < p.n[2];
+}
+
+// stored index of lattice cell G in patch p
+__device__ __forceinline__ long lattice_index(const PatchRef& p, int g0, int g1, int g2)
+{
+    return ((long)(g2 - p.off[2] + p.ng) * p.N[1] + (g1 - p.off[1] + p.ng)) * p.N[0] + (g0 - p.off[0] + p.ng);
+}
+
+// Every parent active cell covered by the active region of a patch of the
+// finer depth takes that patch's restriction (the mean over the patches
+// that cover it, summed in patch order).
 __global__ void __launch_bounds__(256) restrict_cover(RestrictArgs a)
 {
-    const int m0 = a.nc[0] / 2, m1 = a.nc[1] / 2, m2 = a.nc[2] / 2;
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (long)m0 * m1 * m2) return;
-    const int x = (int)(q % m0), y = (int)((q / m0) % m1), z = (int)(q / ((long)m0 * m1));
-    const long Ncx = a.Nc[0], NcxNcy = (long)a.Nc[0] * a.Nc[1];
-    const long cb = (long)(2 * z - 1 + a.ngc) * NcxNcy + (long)(2 * y - 1 + a.ngc) * Ncx + (2 * x - 1 + a.ngc);
-    const long pq = ((long)(a.F[2] + z + a.ngp) * a.Np[1] + (a.F[1] + y + a.ngp)) * a.Np[0] + (a.F[0] + x + a.ngp);
-    for (int f = 0; f < NF; ++f) {
-        const double* u = a.uc + f * a.sfc + cb;
-        double pl[4];
+    if (q >= (long)a.ext[0] * a.ext[1] * a.ext[2]) return;
+    const PatchRef& P = a.parent;
+    const int x = a.lo[0] + (int)(q % a.ext[0]);
+    const int y = a.lo[1] + (int)((q / a.ext[0]) % a.ext[1]);
+    const int z = a.lo[2] + (int)(q / ((long)a.ext[0] * a.ext[1]));
+    const int G0 = P.off[0] + x, G1 = P.off[1] + y, G2 = P.off[2] + z;
+    double s[NF];
+    int cnt = 0;
+    for (int c = 0; c < a.nchild; ++c) {
+        const PatchRef& C = a.child[c];
+        // the parent cell spans child cells ac, ac + 1 in each direction
+        const int ac0 = 2 * G0 - C.off[0], ac1 = 2 * G1 - C.off[1], ac2 = 2 * G2 - C.off[2];
+        if (ac0 < 0 || ac0 + 1 >= C.n[0] || ac1 < 0 || ac1 + 1 >= C.n[1] || ac2 < 0 || ac2 + 1 >= C.n[2]) continue;
+        const long Ncx = C.N[0], NcxNcy = (long)C.N[0] * C.N[1];
+        const long cb = (long)(ac2 - 1 + C.ng) * NcxNcy + (long)(ac1 - 1 + C.ng) * Ncx + (ac0 - 1 + C.ng);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double rw[4];
+        for (int f = 0; f < NF; ++f) {
+            const double* u = C.u + f * C.sf + cb;
+            double pl[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const double* row = u + c * NcxNcy + b * Ncx;
-                rw[b] = rsum(row[0], row[1], row[2], row[3]);
+            for (int k = 0; k < 4; ++k) {
+                double rw[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double* row = u + k * NcxNcy + j * Ncx;
+                    rw[j] = rsum(row[0], row[1], row[2], row[3]);
+                }
+                pl[k] = rsum(rw[0], rw[1], rw[2], rw[3]);
             }
-            pl[c] = rsum(rw[0], rw[1], rw[2], rw[3]);
+            const double v = rsum(pl[0], pl[1], pl[2], pl[3]);
+            s[f] = cnt ? s[f] + v : v;
         }
-        a.up[f * a.sfp + pq] = rsum(pl[0], pl[1], pl[2], pl[3]);
+        ++cnt;
+    }
+    if (!cnt) return;
+    const long pq = ((long)(z + P.ng) * P.N[1] + (y + P.ng)) * P.N[0] + (x + P.ng);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) P.u[f * P.sf + pq] = cnt == 1 ? s[f] : s[f] / cnt;
+}
+
+// Exchange at one depth, averaging: a lattice cell in the active regions of
+// several patches takes their mean (summed in patch order) in all of them.
+// The first patch holding the cell writes it, so each cell is written by one
+// thread of one launch.
+__global__ void __launch_bounds__(256) exchange_average(ExchArgs a)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)a.ext[0] * a.ext[1] * a.ext[2]) return;
+    const int g0 = a.lo[0] + (int)(q % a.ext[0]);
+    const int g1 = a.lo[1] + (int)((q / a.ext[0]) % a.ext[1]);
+    const int g2 = a.lo[2] + (int)(q / ((long)a.ext[0] * a.ext[1]));
+    int first = -1, cnt = 0;
+    for (int b = 0; b < a.np; ++b)
+        if (in_active(a.p[b], g0, g1, g2)) {
+            if (first < 0) first = b;
+            ++cnt;
+        }
+    if (first != a.t || cnt < 2) return;
+    for (int f = 0; f < NF; ++f) {
+        double s = 0.0;
+        for (int b = 0; b < a.np; ++b)
+            if (in_active(a.p[b], g0, g1, g2)) s += a.p[b].u[f * a.p[b].sf + lattice_index(a.p[b], g0, g1, g2)];
+        const double v = s / cnt;
+        for (int b = 0; b < a.np; ++b)
+            if (in_active(a.p[b], g0, g1, g2)) a.p[b].u[f * a.p[b].sf + lattice_index(a.p[b], g0, g1, g2)] = v;
+    }
+}
+
+// Exchange at one depth, ghosts: a ghost point of patch t that lies in the
+// active region of another patch of the depth takes that patch's value (the
+// first such patch in index order).  Only ghosts are written, only active
+// cells are read.
+__global__ void __launch_bounds__(256) exchange_ghosts(ExchArgs a)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)a.ext[0] * a.ext[1] * a.ext[2]) return;
+    const int g0 = a.lo[0] + (int)(q % a.ext[0]);
+    const int g1 = a.lo[1] + (int)((q / a.ext[0]) % a.ext[1]);
+    const int g2 = a.lo[2] + (int)(q / ((long)a.ext[0] * a.ext[1]));
+    const PatchRef& T = a.p[a.t];
+    if (in_active(T, g0, g1, g2)) return;
+    for (int b = 0; b < a.np; ++b) {
+        if (b == a.t || !in_active(a.p[b], g0, g1, g2)) continue;
+        const long src = lattice_index(a.p[b], g0, g1, g2), dst = lattice_index(T, g0, g1, g2);
+        for (int f = 0; f < NF; ++f) T.u[f * T.sf + dst] = a.p[b].u[f * a.p[b].sf + src];
+        return;
     }
 }
 
@@ -276,9 +366,25 @@ hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s)
 
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s)
 {
-    const long n = (long)(a.nc[0] / 2) * (a.nc[1] / 2) * (a.nc[2] / 2);
-    if (n <= 0) return hipSuccess;
+    const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
+    if (n <= 0 || a.nchild <= 0) return hipSuccess;
     hipLaunchKernelGGL(restrict_cover, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange_average(const ExchArgs& a, hipStream_t s)
+{
+    const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
+    if (n <= 0 || a.np < 2) return hipSuccess;
+    hipLaunchKernelGGL(exchange_average, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s)
+{
+    const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
+    if (n <= 0 || a.np < 2) return hipSuccess;
+    hipLaunchKernelGGL(exchange_ghosts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

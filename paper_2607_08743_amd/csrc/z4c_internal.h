@@ -129,17 +129,29 @@ struct ProlongArgs {
     int ngc;
     int F[3];             // parent active cell index of the child's lower faces
 };
+// One patch of a hierarchy depth as the transfer kernels see it.  Lattice
+// index G of a cell at the patch's depth: active cell a of the patch sits at
+// G = off + a (all patches of one depth share the lattice).
+constexpr int MAXEX = 16;  // patches of one depth a transfer launch can take
+struct PatchRef {
+    double* u;
+    long sf;
+    int N[3];    // stored extents
+    int n[3];    // active extents
+    int ng;
+    int off[3];
+};
 struct RestrictArgs {
-    const double* uc;  // child state (active cells and one ghost layer read)
-    long sfc;
-    int Nc[3];
-    int ngc;
-    int nc[3];
-    double* up;  // parent state: covered active cells overwritten
-    long sfp;
-    int Np[3];
-    int ngp;
-    int F[3];
+    PatchRef child[MAXEX];  // every patch of the finer depth (active cells and one ghost layer read)
+    int nchild;
+    PatchRef parent;        // covered active cells overwritten
+    int lo[3], ext[3];      // parent active cells handled (parent active index)
+};
+struct ExchArgs {
+    PatchRef p[MAXEX];  // every patch of the depth, in index order
+    int np;
+    int t;              // the patch this launch works for
+    int lo[3], ext[3];  // lattice cells handled
 };
 struct ShiftArgs {
     const double* uc;  // the patch before the shift
@@ -169,6 +181,8 @@ hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
+hipError_t launch_exchange_average(const ExchArgs& a, hipStream_t s);
+hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long n, hipStream_t s);
 
 }  // namespace z4c

@@ -12,6 +12,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 from . import inputs as _inputs
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -55,7 +57,8 @@ class Level(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("ng", ctypes.c_int), ("bc", ctypes.c_int), ("sf", ctypes.c_long),
                 ("dx", ctypes.c_double * 3), ("x0", ctypes.c_double * 3), ("F", ctypes.c_int * 3),
                 ("u", ctypes.c_void_p), ("u_a", ctypes.c_void_p), ("u_b", ctypes.c_void_p),
-                ("acc", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("cur", ctypes.c_void_p)]
+                ("acc", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("cur", ctypes.c_void_p),
+                ("parent", ctypes.c_int), ("obj", ctypes.c_int)]
 
 
 _lib = None
@@ -300,17 +303,23 @@ class Plan:
 
 
 class Hierarchy:
-    """Box-in-box hierarchy with Berger-Oliger subcycling: levels[l] = (grid,
-    state, F) with F the parent active cell index of the level's lower faces
-    (ignored for level 0).  Owns the six device arrays of every level; u[l]
-    is level l's state."""
+    """Box-in-box hierarchy with Berger-Oliger subcycling: levels[q] = (grid,
+    state, F) or (grid, state, F, parent, obj) for patch q, with F the parent
+    active cell index of the patch's lower faces (ignored for the root),
+    parent the index of its parent patch (default: the patch before it) and
+    obj the tracked object it follows (default -1: fixed).  Owns the six
+    device arrays of every patch; u[q] is patch q's state."""
 
     def __init__(self, levels, dt0: float, params: Params = None, tile: Tile = None, device="cuda"):
         import torch
         self.params = params or default_params()
         self.grids = [lv[0] for lv in levels]
         self.u, self._keep, cl = [], [], []
-        for g, state, F in levels:
+        self.nobj = 0
+        for q, lv in enumerate(levels):
+            g, state, F = lv[:3]
+            parent = lv[3] if len(lv) > 3 and lv[3] is not None else q - 1
+            obj = lv[4] if len(lv) > 4 else -1
             u = torch.as_tensor(state, dtype=torch.float64, device=device).contiguous().clone()
             extra = [torch.zeros_like(u) for _ in range(5)]
             self.u.append(u)
@@ -323,6 +332,7 @@ class Hierarchy:
             c.F[:] = [int(v) for v in F]
             c.u = u.data_ptr()
             c.u_a, c.u_b, c.acc, c.prev, c.cur = [t.data_ptr() for t in extra]
+            c.parent, c.obj = int(parent), int(obj)
             cl.append(c)
         self._cl = (Level * len(cl))(*cl)
         h = ctypes.c_void_p()
@@ -333,20 +343,24 @@ class Hierarchy:
     def advance(self, nsteps: int = 1, use_graph: bool = True, stream=None):
         check(lib().z4c_hier_advance(self._h, int(nsteps), int(bool(use_graph)), _stream(stream)), "z4c_hier_advance")
 
-    def set_moving(self, lmove: int, xp):
-        """Levels lmove.. follow the puncture that starts at xp."""
-        x = (ctypes.c_double * 3)(*[float(v) for v in xp])
-        check(lib().z4c_hier_set_moving(self._h, int(lmove), x), "z4c_hier_set_moving")
+    def set_moving(self, xp):
+        """The patches with obj >= 0 follow the punctures xp (one row of 3 per
+        object; a single row may be flat)."""
+        x = np.ascontiguousarray(np.array(xp, dtype=np.float64).reshape(-1, 3))
+        self.nobj = len(x)
+        check(lib().z4c_hier_set_moving(self._h, self.nobj, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              "z4c_hier_set_moving")
 
     def puncture(self):
-        """(puncture position, [F per level], [x0 per level])."""
+        """(punctures (nobj, 3), [F per patch], [x0 per patch])."""
         n = len(self.grids)
-        x = (ctypes.c_double * 3)()
+        x = np.zeros((max(self.nobj, 1), 3))
         F = (ctypes.c_int * (3 * n))()
         x0 = (ctypes.c_double * (3 * n))()
-        check(lib().z4c_hier_puncture(self._h, x, F, x0), "z4c_hier_puncture")
-        return (list(x), [tuple(F[3 * l:3 * l + 3]) for l in range(n)],
-                [tuple(x0[3 * l:3 * l + 3]) for l in range(n)])
+        check(lib().z4c_hier_puncture(self._h, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if self.nobj else None,
+                                      F, x0), "z4c_hier_puncture")
+        return (x[:self.nobj], [tuple(F[3 * q:3 * q + 3]) for q in range(n)],
+                [tuple(x0[3 * q:3 * q + 3]) for q in range(n)])
 
     def close(self):
         if getattr(self, "_h", None):

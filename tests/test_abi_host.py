@@ -210,7 +210,7 @@ def test_equatorial_ghosts_reject_shell(L):
     assert "shell" in L.z4c_last_error().decode()
 
 
-def _level(n=16, dx=1.0, x0=None, F=(4, 4, 4), bc=2, base=0x100000):
+def _level(n=16, dx=1.0, x0=None, F=(4, 4, 4), bc=2, base=0x100000, parent=0, obj=-1):
     L = z4c.Level()
     L.n[:] = [n] * 3
     L.ng, L.bc = 3, bc
@@ -220,15 +220,24 @@ def _level(n=16, dx=1.0, x0=None, F=(4, 4, 4), bc=2, base=0x100000):
     L.F[:] = list(F)
     size = 25 * L.sf * 8
     L.u, L.u_a, L.u_b, L.acc, L.prev, L.cur = [base + k * size for k in range(6)]
+    L.parent, L.obj = parent, obj
     return L
 
 
-@pytest.mark.parametrize("case", ["dx", "x0", "stencil", "odd", "bc0", "bc1", "null"])
+HIER_CASES = {
+    "dx": "dx must be half", "x0": "x0 does not put", "stencil": "prolongation stencil", "odd": "even",
+    "bc0": "own boundary", "bc1": "Z4C_BC_COPY", "null": "six state arrays", "root_parent": "parent -1",
+    "parent_order": "listed before", "root_moves": "cannot move", "shared": "overlap those of patch",
+    "obj": "obj must be",
+}
+
+
+@pytest.mark.parametrize("case", sorted(HIER_CASES))
 def test_hierarchy_validation(L, case):
-    """z4c_hier_create rejects inconsistent level geometry before it would
-    touch the GPU."""
+    """z4c_hier_create rejects inconsistent patch geometry and links before
+    it would touch the GPU, each with its own message."""
     n = 16
-    parent = _level(n, 1.0, bc=z4c.BC_SOMMERFELD)
+    parent = _level(n, 1.0, bc=z4c.BC_SOMMERFELD, parent=-1)
     x0c = -0.5 * (n - 1) * 1.0 + (4 - 0.25) * 1.0
     child = _level(n, 0.5, x0=x0c, base=0x800000000)
     if case == "dx":
@@ -246,8 +255,19 @@ def test_hierarchy_validation(L, case):
         child.bc = z4c.BC_PERIODIC
     elif case == "null":
         child.cur = None
+    elif case == "root_parent":
+        parent.parent = 0
+    elif case == "parent_order":
+        child.parent = 1
+    elif case == "root_moves":
+        parent.obj = 0
+    elif case == "shared":
+        child.prev = parent.u
+    elif case == "obj":
+        child.obj = -2
     arr = (z4c.Level * 2)(parent, child)
     h = ctypes.c_void_p()
     p = z4c.default_params()
     assert L.z4c_hier_create(arr, 2, ctypes.byref(p), 0.5, None, ctypes.byref(h)) == z4c.EINVAL
+    assert HIER_CASES[case] in L.z4c_last_error().decode(), L.z4c_last_error().decode()
     assert not h.value

@@ -262,9 +262,10 @@ typedef struct z4c_level {
 
 /* Create a hierarchy of nlev (1..32) patches, at most 16 per depth,
  * advanced with root step dt0.  tile == NULL: the library default shape
- * with a persistent launch.  Allocates one ghost-shell buffer per patch >= 1
- * in device memory (25 x (stored - active) doubles; Z4C_ENOMEM if that
- * fails). */
+ * with a persistent launch.  Allocates four ghost-shell buffers per patch
+ * >= 1 in device memory, each 25 x (stored - active) doubles: the spatial
+ * prolongations of the parent's three time levels and their combination at
+ * the current stage time (Z4C_ENOMEM if that fails). */
 int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, double dt0, const z4c_tile* tile,
                     void** hier);
 

@@ -118,6 +118,15 @@ bool overlap(const void* a, const void* b, long sf)
     return pa < pb + len && pb < pa + len;
 }
 
+// two state arrays of different field strides
+bool overlap2(const void* a, long sfa, const void* b, long sfb)
+{
+    if (!a || !b) return false;
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    const uintptr_t la = (uintptr_t)sfa * NF * sizeof(double), lb = (uintptr_t)sfb * NF * sizeof(double);
+    return pa < pb + lb && pb < pa + la;
+}
+
 long bricks(const int n[3], const z4c_tile& t, int nb[3])
 {
     nb[0] = (n[0] + t.bx - 1) / t.bx;
@@ -623,7 +632,8 @@ constexpr int MAXPATCH = 32;
 
 struct HierPatch {
     z4c_level L;
-    double* shell;  // device: ghost shell filled by prolongation (patches >= 1)
+    double* shell;  // device: ghost shell at the current stage time (patches >= 1)
+    double* lev[3];  // device: spatial prolongations of the parent's time levels (prev, cur, new)
     long nshell;
     bool has_prev;  // prev holds this patch one step earlier
     int depth;
@@ -841,29 +851,41 @@ static void hier_time_weights(double theta, bool quadratic, double wt[3])
     }
 }
 
-// the ghost shells of every patch at depth d at theta (fraction of the parent step)
+// The ghost shells of every patch at depth d at theta (fraction of the
+// parent step).  Prolongation in space and interpolation in time are both
+// linear and commute: at the start of a parent step (theta 0) each parent
+// time level is prolonged once into its own shell, and the shell of every
+// stage time is then their weighted sum.
 static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s)
 {
     for (int q : H->dp[d].q) {
         HierPatch& C = H->pt[q];
         const HierPatch& P = H->pt[C.L.parent];
-        ProlongArgs a{};
-        hier_time_weights(theta, P.has_prev, a.wt);
-        a.pa[0] = P.has_prev ? P.L.prev : nullptr;
-        a.pa[1] = P.L.cur;
-        a.pa[2] = P.L.u;
-        a.sfp = P.L.sf;
-        for (int e = 0; e < 3; ++e) {
-            a.Np[e] = P.L.n[e] + 2 * P.L.ng;
-            a.nc[e] = C.L.n[e];
-            a.F[e] = C.L.F[e];
+        hipError_t e;
+        if (theta == 0.0) {
+            const double* lv[3] = {P.L.prev, P.L.cur, P.L.u};
+            for (int t = P.has_prev ? 0 : 1; t < 3; ++t) {
+                ProlongArgs a{};
+                a.wt[1] = 1.0;
+                a.pa[1] = lv[t];
+                a.sfp = P.L.sf;
+                for (int k = 0; k < 3; ++k) {
+                    a.Np[k] = P.L.n[k] + 2 * P.L.ng;
+                    a.nc[k] = C.L.n[k];
+                    a.F[k] = C.L.F[k];
+                }
+                a.ngp = P.L.ng;
+                a.shell = C.lev[t];
+                a.nshell = C.nshell;
+                a.ngc = C.L.ng;
+                if ((e = launch_prolong(a, s)) != hipSuccess) return e;
+            }
         }
-        a.ngp = P.L.ng;
-        a.shell = C.shell;
-        a.nshell = C.nshell;
-        a.ngc = C.L.ng;
-        hipError_t e = launch_prolong(a, s);
-        if (e != hipSuccess) return e;
+        double wt[3];
+        hier_time_weights(theta, P.has_prev, wt);
+        if ((e = launch_combine(C.shell, P.has_prev ? C.lev[0] : nullptr, C.lev[1], C.lev[2], wt, (long)NF * C.nshell,
+                                s)) != hipSuccess)
+            return e;
     }
     return hipSuccess;
 }
@@ -968,8 +990,11 @@ static void hier_drop_graph(z4c_hier_s* H)
 static void hier_free(z4c_hier_s* H)
 {
     hier_drop_graph(H);
-    for (HierPatch& P : H->pt)
+    for (HierPatch& P : H->pt) {
         if (P.shell) (void)hipFree(P.shell);
+        for (double* b : P.lev)
+            if (b) (void)hipFree(b);
+    }
     if (H->track) (void)hipFree(H->track);
     if (H->capture) (void)hipStreamDestroy(H->capture);
     delete H;
@@ -1001,7 +1026,7 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
                 const z4c_level& y = levels[m];
                 const double* brr[6] = {y.u, y.u_a, y.u_b, y.acc, y.prev, y.cur};
                 for (int j = 0; j < 6; ++j)
-                    if (overlap(arr[i], brr[j], std::max(x.sf, y.sf)))
+                    if (overlap2(arr[i], x.sf, brr[j], y.sf))
                         return fail(Z4C_EINVAL, tag + "state arrays overlap those of patch " + std::to_string(m));
             }
         }
@@ -1042,12 +1067,16 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         HierPatch& P = H->pt[l];
         P.L = levels[l];
         P.shell = nullptr;
+        P.lev[0] = P.lev[1] = P.lev[2] = nullptr;
         P.has_prev = false;
         P.nshell = l > 0 ? shell_size(P.L.n, P.L.ng) : 0;
-        if (l > 0) {
-            hipError_t e = hipMalloc((void**)&P.shell, (size_t)NF * P.nshell * sizeof(double));
-            if (e != hipSuccess) {
-                P.shell = nullptr;
+    }
+    for (int l = 1; l < nlev; ++l) {
+        HierPatch& P = H->pt[l];
+        double** bufs[4] = {&P.shell, &P.lev[0], &P.lev[1], &P.lev[2]};
+        for (double** b : bufs) {
+            if (hipMalloc((void**)b, (size_t)NF * P.nshell * sizeof(double)) != hipSuccess) {
+                *b = nullptr;
                 hier_free(H);
                 return fail(Z4C_ENOMEM, "ghost shell allocation failed");
             }

@@ -5,7 +5,8 @@
 //
 //   prolongation: the child's ghost shell from the parent, 6th-order Lagrange
 //     interpolation in each direction (tensor product, 6x6x6 parent cells), of
-//     the parent time levels combined with the caller's time weights;
+//     the parent time levels combined with the caller's time weights (or of
+//     one level, the shells of the levels then combined per stage time);
 //   restriction: every coarse cell covered by the active region of a finer
 //     patch from the 4th-order Lagrange interpolation of the 4x4x4 child
 //     cells around its centre (the mean where several patches cover it);
@@ -349,6 +350,20 @@ __global__ void __launch_bounds__(256) exchange_ghosts(ExchArgs a)
     }
 }
 
+// Ghost shell at one time of the parent step from the spatial prolongations
+// of the parent's time levels (prolongation and time interpolation are both
+// linear, so they commute); s0 may be NULL (weight 0).
+__global__ void __launch_bounds__(256) combine_shells(double* __restrict__ out, const double* __restrict__ s0,
+                                                      const double* __restrict__ s1, const double* __restrict__ s2,
+                                                      double w0, double w1, double w2, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = w1 * s1[i] + w2 * s2[i];
+    if (s0) v += w0 * s0[i];
+    out[i] = v;
+}
+
 __global__ void __launch_bounds__(256) copy_state(double* __restrict__ dst, const double* __restrict__ src, long n)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -399,6 +414,15 @@ hipError_t launch_shift(const ShiftArgs& a, hipStream_t s)
 hipError_t launch_track(const TrackArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(track_puncture, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(double* out, const double* s0, const double* s1, const double* s2, const double w[3], long n,
+                          hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_shells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, s0, s1, s2, w[0], w[1],
+                       w[2], n);
     return hipGetLastError();
 }
 

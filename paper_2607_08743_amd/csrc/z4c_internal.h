@@ -184,5 +184,8 @@ hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_exchange_average(const ExchArgs& a, hipStream_t s);
 hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long n, hipStream_t s);
+// out = w0 s0 + w1 s1 + w2 s2 over n doubles (s0 may be NULL)
+hipError_t launch_combine(double* out, const double* s0, const double* s1, const double* s2, const double w[3], long n,
+                          hipStream_t s);
 
 }  // namespace z4c

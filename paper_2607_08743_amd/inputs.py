@@ -320,6 +320,19 @@ def pair_hierarchy(root_n, h0, centers, moving, fixed=(), bc0=BC_PERIODIC, ng=NG
     return out
 
 
+def config_bbh_moving(root_n=128, h0=2.0, fixed=(128, 128, 128), moving=(64, 64, 64), sep=10.0):
+    """The binary-black-hole layout of Sec. 2.2.1 (Fig. 1): a Sommerfeld
+    root of root_n^3 cells (spacing h0) and fixed levels centred on the
+    origin, then moving levels with one patch per puncture, on two
+    Brill-Lindquist punctures (m = 0.5 each at x = +-sep/2), alpha = W.
+    Returns (patches [(grid, F, parent, obj)], states, root step dt0 = 0.5 h0,
+    puncture positions (2, 3))."""
+    centers = [(-0.5 * sep, 0.0, 0.0), (0.5 * sep, 0.0, 0.0)]
+    pt = pair_hierarchy(root_n, h0, centers, moving, fixed, bc0=BC_SOMMERFELD)
+    states = [brill_lindquist_state(g) for g, *_ in pt]
+    return pt, states, 0.5 * h0, np.array(centers)
+
+
 def config_bo_hierarchy(nlev=6, n=64, h0=4.0):
     """Two-puncture Brill-Lindquist data on every level of bo_level_grids,
     pi-symmetrised; coarse step dt0 = 0.5 h0 (level l: 0.5 h0 / 2^l)."""

@@ -232,6 +232,23 @@ HIER_CASES = {
 }
 
 
+def test_hierarchy_adjacent_patches_accepted(L):
+    """A small patch's arrays right before a larger patch's are not an
+    overlap (each array spans its own field stride), although they lie
+    within one large array's length of them."""
+    n = 16
+    base = 0x10000000
+    parent = _level(n, 1.0, bc=z4c.BC_SOMMERFELD, parent=-1, base=base)
+    x0c = -0.5 * (n - 1) * 1.0 + (4 - 0.25) * 1.0
+    small = (n - 8 + 6) ** 3
+    child = _level(n - 8, 0.5, x0=x0c, base=base - 6 * 25 * small * 8)
+    arr = (z4c.Level * 2)(parent, child)
+    h = ctypes.c_void_p()
+    p = z4c.default_params()
+    L.z4c_hier_create(arr, 2, ctypes.byref(p), 0.5, None, ctypes.byref(h))
+    assert "overlap" not in L.z4c_last_error().decode()
+
+
 @pytest.mark.parametrize("case", sorted(HIER_CASES))
 def test_hierarchy_validation(L, case):
     """z4c_hier_create rejects inconsistent patch geometry and links before
@@ -262,7 +279,7 @@ def test_hierarchy_validation(L, case):
     elif case == "root_moves":
         parent.obj = 0
     elif case == "shared":
-        child.prev = parent.u
+        child.prev = parent.u + 8  # inside the parent's state
     elif case == "obj":
         child.obj = -2
     arr = (z4c.Level * 2)(parent, child)

@@ -185,8 +185,9 @@ int z4c_tile_get(int precision, int index, z4c_tile* out);
 
 /* Choose the tile shape (and persistent flag) that rhs_z4c and rk4_substep
  * use for `precision` (process-wide, thread safe); tile == NULL restores the
- * default (first shape, not persistent).  Z4C_EUNSUPPORTED if that shape is
- * not compiled. */
+ * default (8x8x8 bricks with two waves per SIMD where compiled, else the
+ * first shape; not persistent).  Z4C_EUNSUPPORTED if that shape is not
+ * compiled. */
 int z4c_select_tile(int precision, const z4c_tile* tile);
 
 /* Create a plan over nbox boxes (1 <= nbox <= 16, largest first is best).

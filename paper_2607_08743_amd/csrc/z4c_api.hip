@@ -50,6 +50,12 @@ int default_tile_index(int precision, int* persistent = nullptr)
             return g_selected[precision];
         }
     }
+    // the shape measured fastest on large boxes (8x8x8 bricks, two waves per
+    // SIMD) when compiled, else the first of the precision
+    for (int i = 0; i < n; ++i)
+        if (t[i].precision == precision && t[i].tile.bx == 8 && t[i].tile.by == 8 && t[i].tile.bz == 8 &&
+            t[i].tile.waves == 2)
+            return i;
     for (int i = 0; i < n; ++i)
         if (t[i].precision == precision) return i;
     return -1;
@@ -634,6 +640,7 @@ struct HierPatch {
     z4c_level L;
     double* shell;  // device: ghost shell at the current stage time (patches >= 1)
     double* lev[3];  // device: spatial prolongations of the parent's time levels (prev, cur, new)
+    bool lev_cur;    // lev[1] holds the prolongation of the parent's cur of its previous step, at this geometry
     long nshell;
     bool has_prev;  // prev holds this patch one step earlier
     int depth;
@@ -863,8 +870,12 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
         const HierPatch& P = H->pt[C.L.parent];
         hipError_t e;
         if (theta == 0.0) {
+            // the parent's prev is its cur of the previous step: reuse that
+            // prolongation unless this patch moved since
             const double* lv[3] = {P.L.prev, P.L.cur, P.L.u};
-            for (int t = P.has_prev ? 0 : 1; t < 3; ++t) {
+            const bool reuse = P.has_prev && C.lev_cur;
+            if (reuse && (e = launch_copy(C.lev[0], C.lev[1], (long)NF * C.nshell, s)) != hipSuccess) return e;
+            for (int t = P.has_prev && !reuse ? 0 : 1; t < 3; ++t) {
                 ProlongArgs a{};
                 a.wt[1] = 1.0;
                 a.pa[1] = lv[t];
@@ -880,6 +891,7 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
                 a.ngc = C.L.ng;
                 if ((e = launch_prolong(a, s)) != hipSuccess) return e;
             }
+            C.lev_cur = true;
         }
         double wt[3];
         hier_time_weights(theta, P.has_prev, wt);
@@ -1068,6 +1080,7 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         P.L = levels[l];
         P.shell = nullptr;
         P.lev[0] = P.lev[1] = P.lev[2] = nullptr;
+        P.lev_cur = false;
         P.has_prev = false;
         P.nshell = l > 0 ? shell_size(P.L.n, P.L.ng) : 0;
     }
@@ -1184,9 +1197,12 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
         if ((e = launch_copy(P.L.u, P.L.u_a, (long)NF * P.L.sf, s)) != hipSuccess) return hip_fail(e, "copy launch");
         P.L = nl;
         P.has_prev = false;
+        P.lev_cur = false;  // its ghosts sit elsewhere now
         for (int c = q + 1; c < np; ++c)
-            if (H->pt[c].L.parent == q)
+            if (H->pt[c].L.parent == q) {
                 for (int d = 0; d < 3; ++d) H->pt[c].L.F[d] -= 2 * sh[d];
+                H->pt[c].lev_cur = false;
+            }
         hier_geometry(H);
         moved = true;
     }

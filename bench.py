@@ -216,6 +216,8 @@ def main():
     ap.add_argument("--tile", default="", help="bx,by,bz,waves,persistent (skip the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--only", choices=["bbh_moving"], default="",
+                    help="run only this extra measurement and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -232,6 +234,9 @@ def main():
     from paper_2607_08743_amd import z4c
 
     torch.cuda.set_device(0)
+    if args.only == "bbh_moving":
+        print(json.dumps({"bbh_moving": bbh_moving_rate(z4c, I, torch)}), flush=True)
+        return
     g, u0, dt = I.config_punctures(args.n)
     box = I.Box(g, u0, None, dt)
     params = z4c.default_params()

@@ -54,6 +54,10 @@ constexpr ProlongW make_prolong_w()
     return w;
 }
 __constant__ ProlongW kProlong = make_prolong_w();
+// the same offsets and weights as compile-time constants (immediates in the
+// unrolled single-level gather)
+constexpr int kOffC[6] = {0, 1, -1, 2, -2, 3};
+constexpr ProlongW kProlongC = make_prolong_w();
 
 // restriction: child centres at -3/2, -1/2, 1/2, 3/2 child cells from the
 // parent centre, weights (r0, r1, r1, r0), summed as r1 (c1 + c2) + r0 (c0 + c3)
@@ -141,6 +145,30 @@ __device__ __forceinline__ double prolong_value(const double* const pa[3], const
     return s;
 }
 
+// Field f of ONE parent level (no time combination) at a child point; the
+// same nearest-first order as prolong_value, with every loop unrolled so
+// that the 216 gathers issue back to back.
+__device__ __forceinline__ double prolong_one(const double* __restrict__ u, long Nx, long NxNy, int px, int py,
+                                              int pz, int sx, int sy, int sz)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const double* pl = u + (long)(pz + sz * kOffC[c]) * NxNy;
+        double syy = 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            const double* row = pl + (long)(py + sy * kOffC[b]) * Nx + px;
+            double sxx = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) sxx += kProlongC.w[m] * row[sx * kOffC[m]];
+            syy += kProlongC.w[b] * sxx;
+        }
+        s += kProlongC.w[c] * syy;
+    }
+    return s;
+}
+
 // one thread per (field, ghost point): 25 times the waves of one thread per
 // point, which the 216 gathered loads per value need to hide their latency
 __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
@@ -156,7 +184,11 @@ __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
     const int py = prolong_cell(j - a.ngc, a.F[1], sy) + a.ngp;
     const int pz = prolong_cell(k - a.ngc, a.F[2], sz) + a.ngp;
     const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
-    a.shell[f * a.nshell + q] = prolong_value(a.pa, a.wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f);
+    const int nlev = (a.pa[0] != nullptr) + (a.pa[1] != nullptr) + (a.pa[2] != nullptr);
+    if (nlev == 1 && a.pa[1] && a.wt[1] == 1.0)  // one level, weight 1: a plain spatial prolongation
+        a.shell[f * a.nshell + q] = prolong_one(a.pa[1] + f * a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz);
+    else
+        a.shell[f * a.nshell + q] = prolong_value(a.pa, a.wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f);
 }
 
 // A moving patch shifted by 2 s of its cells (s per direction in -1..1):

@@ -679,11 +679,19 @@ static int hier_check_level(const z4c_level& x, const z4c_level& P, const std::s
         const double want = P.x0[d] + (x.F[d] - 0.25) * P.dx[d];
         if (std::fabs(x.x0[d] - want) > 1e-9 * P.dx[d])
             return fail(Z4C_EINVAL, tag + "x0 does not put the lower faces on parent cell F");
-        // first / last parent cell read by the ghost stencils: floor(a/2) - 3 for
-        // a = -ng, and floor(a/2) + 3 for a = n + ng - 1
-        const int a_lo = -x.ng, a_hi = x.n[d] + x.ng - 1;
-        const int lo = x.F[d] + (a_lo >= 0 ? a_lo / 2 : -((1 - a_lo) / 2)) - 3;
-        const int hi = x.F[d] + a_hi / 2 + 3;
+        // first / last parent cell read by the ghost stencils: child cell a
+        // lies in parent cell F + floor(a/2), in its upper half for odd a
+        // (stencil -2..+3) and its lower half for even a (-3..+2)
+        auto span = [](int a, int& from, int& to) {
+            const int half = a >= 0 ? a / 2 : -((1 - a) / 2);
+            const bool odd = a - 2 * half != 0;
+            from = half + (odd ? -2 : -3);
+            to = half + (odd ? 3 : 2);
+        };
+        int lo_from, lo_to, hi_from, hi_to;
+        span(-x.ng, lo_from, lo_to);
+        span(x.n[d] + x.ng - 1, hi_from, hi_to);
+        const int lo = x.F[d] + lo_from, hi = x.F[d] + hi_to;
         if (lo < 0 || hi >= P.n[d]) return fail(Z4C_EINVAL, tag + "prolongation stencil leaves the parent's active cells");
     }
     return Z4C_OK;

@@ -95,3 +95,45 @@ def test_moving_parity_with_oracle(oz):
         print(f"level {l} oracle 1-ulp sensitivity:", " ".join(f"{v:.1e}" for v in sens))
         assert np.all(e <= np.maximum(TOL, 20 * sens)), (l, e)
         assert np.abs(got[l][:, m] - L.u[:, m]).max() <= TOL * np.abs(L.u[:, m]).max()
+
+
+def _edge_levels(F1, xp_off):
+    """Root 32^3 (h = 1, periodic) and one moving 24^3 child (h = 1/2) whose
+    lower faces sit on root cell F1; flat data with a small constant shift."""
+    root = I.centered_grid(32, 1.0, bc=I.BC_PERIODIC)
+    F = (F1, 10, 10)
+    x0 = tuple(root.x0[d] + (F[d] - 0.25) * root.h[d] for d in range(3))
+    child = I.Grid((24, 24, 24), (0.5,) * 3, x0, I.BC_COPY, 3)
+    lv = []
+    for g, Fl, par, obj in ((root, (0, 0, 0), -1, -1), (child, F, 0, 0)):
+        u = I.flat_state(g)
+        u[19] = 0.01
+        lv.append((g, u, Fl, par, obj))
+    centre = np.array([x0[d] + 0.5 * 23 * 0.5 for d in range(3)])
+    return lv, centre + np.asarray(xp_off)
+
+
+def test_moving_shift_out_of_parent_is_an_error():
+    """A patch already at the last root cell its stencils allow (F = 16 for a
+    24^3 child of a 32^3 root: its last ghost, child cell 26, reads root cells
+    up to F + 15) with its puncture three of its cells ahead: the regrid after
+    the first root step refuses the shift, as the oracle's does."""
+    print("case: moving patch shift out of its parent", flush=True)
+    lv, xp = _edge_levels(16, (1.5, 0.0, 0.0))
+    H = z4c.Hierarchy(lv, 0.5, params=z4c.default_params(eta=0.0))
+    H.set_moving(xp)
+    with pytest.raises(z4c.Z4cError, match="prolongation stencil leaves"):
+        H.advance(1)
+    H.close()
+
+
+def test_puncture_outside_active_cells_is_an_error():
+    """A puncture whose 4-point stencil would need a ghost of its patch: the
+    tracking kernel flags it and the advance reports it."""
+    print("case: puncture stencil outside the active cells", flush=True)
+    lv, xp = _edge_levels(10, (-5.8, 0.0, 0.0))  # 0.2 of a cell inside the first active cell
+    H = z4c.Hierarchy(lv, 0.5, params=z4c.default_params(eta=0.0))
+    H.set_moving(xp)
+    with pytest.raises(z4c.Z4cError, match="left the active cells"):
+        H.advance(1)
+    H.close()

@@ -106,7 +106,7 @@ def lib():
         L.oz_bo_advance.argtypes = [ctypes.POINTER(OzLevel), ctypes.c_int, ctypes.POINTER(OzParams), ctypes.c_double,
                                     ctypes.c_int, ctypes.c_int]
         L.oz_prolong.argtypes = [dp, dp, dp, dp, ctypes.c_long, ip, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_int,
-                                 ip, ctypes.c_int]
+                                 ip, ctypes.c_int, ctypes.c_int]
         L.oz_restrict.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp, ctypes.c_long, ip, ctypes.c_int, ip,
                                   ctypes.c_int]
         L.oz_transfer_weights.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
@@ -338,9 +338,11 @@ def interp_beta(u, g, x) -> np.ndarray:
     return b
 
 
-def prolong(parent_levels, wt, np_, ngp, uc, nc, ngc, F, nthreads=None) -> None:
+def prolong(parent_levels, wt, np_, ngp, uc, nc, ngc, F, refl=False, nthreads=None) -> None:
     """Fill every ghost of the child state uc from up to three parent time
-    levels (None allowed) combined with the time weights wt."""
+    levels (None allowed) combined with the time weights wt; refl: the
+    parent's lower z face is a symmetry plane (layers below it read as the
+    mirror images, with each field's z parity)."""
     pa = [None if a is None else _dp(_state(a)) for a in parent_levels]
     sfp = next(a for a in parent_levels if a is not None)[0].size
     wt = np.ascontiguousarray(wt, dtype=np.float64)
@@ -348,7 +350,7 @@ def prolong(parent_levels, wt, np_, ngp, uc, nc, ngc, F, nthreads=None) -> None:
     cn, _k2 = _ivec(nc)
     fF, _k3 = _ivec(F)
     _check(lib().oz_prolong(pa[0], pa[1], pa[2], _dp(wt), sfp, pn, int(ngp), _dp(_state(uc)), uc[0].size, cn, int(ngc),
-                            fF, nthreads or threads_default()), "prolong")
+                            fF, int(bool(refl)), nthreads or threads_default()), "prolong")
 
 
 def restrict(uc, nc, ngc, up, np_, ngp, F, nthreads=None) -> None:

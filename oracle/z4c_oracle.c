@@ -959,6 +959,7 @@ typedef struct {
     int np;
     int depth[OZ_MAXPATCH];
     int off[OZ_MAXPATCH][3]; /* lattice index of the first active cell at the patch's depth */
+    int plane[OZ_MAXPATCH];  /* the patch's lower z face is the symmetry plane of an equatorial root */
     int maxdepth;
     grid g[OZ_MAXPATCH];
     double* cur[OZ_MAXPATCH]; /* the patch at the start of its current step */
@@ -1012,7 +1013,7 @@ static void make_level_grid(grid* g, const oz_level* L, int bc)
 /* Fill every ghost point of the child from the parent time levels
    pa[0..3) combined with the time weights wt (a NULL level has weight 0). */
 static void prolong_ghosts(const grid* gp, const double* const pa[3], const double wt[3], const grid* gc,
-                           double* uc, const int F[3], int nt)
+                           double* uc, const int F[3], int refl, int nt)
 {
 #pragma omp parallel for schedule(static) num_threads(nt)
     for (int k = 0; k < gc->N[2]; ++k)
@@ -1025,15 +1026,23 @@ static void prolong_ghosts(const grid* gp, const double* const pa[3], const doub
                 int lz = prolong_1d(k - gc->ng, F[2], wz) + gp->ng;
                 for (int f = 0; f < NF; ++f) {
                     double s = 0.0;
-                    for (int c = 0; c < 6; ++c)
+                    for (int c = 0; c < 6; ++c) {
+                        /* refl: parent layers below the symmetry plane are the
+                           mirror images of those above it */
+                        int kz = lz + c, neg = 0;
+                        if (refl && kz < gp->ng) {
+                            kz = 2 * gp->ng - 1 - kz;
+                            neg = z_parity(f) < 0;
+                        }
                         for (int b = 0; b < 6; ++b)
                             for (int a = 0; a < 6; ++a) {
-                                long q = f * gp->sf + lin(gp, lx + a, ly + b, lz + c);
+                                long q = f * gp->sf + lin(gp, lx + a, ly + b, kz);
                                 double v = 0.0;
                                 for (int t = 0; t < 3; ++t)
                                     if (pa[t]) v += wt[t] * pa[t][q];
-                                s += wz[c] * wy[b] * wx[a] * v;
+                                s += wz[c] * wy[b] * wx[a] * (neg ? -v : v);
                             }
+                    }
                     uc[f * gc->sf + lin(gc, i, j, k)] = s;
                 }
             }
@@ -1097,6 +1106,7 @@ static int hier_geometry(hierarchy* H)
         if (q == 0) {
             if (L->parent != -1 || L->bc == BC_COPY) return -1; /* the root needs a boundary of its own */
             H->depth[0] = 0;
+            H->plane[0] = L->bc == BC_EQUATORIAL;
             for (int d = 0; d < 3; ++d) H->off[0][d] = 0;
             if (make_grid(&H->g[0], L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0],
                           L->x0[1], L->x0[2], L->bc))
@@ -1107,6 +1117,7 @@ static int hier_geometry(hierarchy* H)
         const oz_level* P = &H->lv[L->parent];
         H->depth[q] = H->depth[L->parent] + 1;
         if (H->depth[q] > H->maxdepth) H->maxdepth = H->depth[q];
+        H->plane[q] = H->plane[L->parent] && L->F[2] == 0;
         if (make_grid(&H->g[q], L->sf, L->n[0], L->n[1], L->n[2], L->ng, L->h[0], L->h[1], L->h[2], L->x0[0],
                       L->x0[1], L->x0[2], BC_COPY))
             return -1;
@@ -1115,7 +1126,8 @@ static int hier_geometry(hierarchy* H)
             /* prolongation stencil of every child ghost inside the parent's active cells */
             double w[6];
             int lo = prolong_1d(-L->ng, L->F[d], w), hi = prolong_1d(L->n[d] + L->ng - 1, L->F[d], w) + 5;
-            if (lo < 0 || hi >= P->n[d]) return -1;
+            if (d == 2 && H->plane[q]) lo = lo < 0 ? -1 - lo : lo; /* reflected across the plane */
+            if (lo < 0 || lo >= P->n[d] || hi >= P->n[d]) return -1;
             /* child active cell a sits at lattice index 2 (parent's first cell + F) + a */
             H->off[q][d] = 2 * (H->off[L->parent][d] + L->F[d]);
         }
@@ -1211,9 +1223,16 @@ static void fill_depth(hierarchy* H, int d, double* const* arr, double theta)
         double wt[3];
         time_weights(theta, LP->has_prev, wt);
         const double* pa[3] = {LP->has_prev ? LP->prev : NULL, H->cur[P], LP->u};
-        prolong_ghosts(&H->g[P], pa, wt, &H->g[q], arr[q], H->lv[q].F, H->nt);
+        prolong_ghosts(&H->g[P], pa, wt, &H->g[q], arr[q], H->lv[q].F, H->plane[q], H->nt);
     }
     exchange_ghosts(H, d, arr);
+    /* layers below the symmetry plane: mirror images of the patch's own */
+    for (int q = 1; q < H->np; ++q)
+        if (H->depth[q] == d && H->plane[q]) {
+            grid ge = H->g[q];
+            ge.bc = BC_EQUATORIAL;
+            ghosts(arr[q], NULL, &ge);
+        }
 }
 
 /* Every active cell of a patch at depth d covered by the active region of
@@ -1255,7 +1274,7 @@ static void restrict_depth(hierarchy* H, int d)
     }
 }
 
-static int interp_beta(const oz_level* L, const double x[3], double b[3]);
+static int interp_beta(const oz_level* L, const double x[3], int refl, double b[3]);
 
 /* one RK4 step of every patch at depth d (the textbook form of oz_rk4),
    ghosts of every stage input filled at that stage's time, then the two
@@ -1275,7 +1294,7 @@ static int bo_depth(hierarchy* H, int d, double theta0)
        predicted point */
     for (int o = 0; o < H->nobj; ++o) {
         if (H->depth[H->tp[o]] != d) continue;
-        if (interp_beta(&H->lv[H->tp[o]], H->xp + 3 * o, H->b0[o])) return -2;
+        if (interp_beta(&H->lv[H->tp[o]], H->xp + 3 * o, H->plane[H->tp[o]], H->b0[o])) return -2;
         for (int e = 0; e < 3; ++e) H->xs[o][e] = H->xp[3 * o + e] - dt * H->b0[o][e];
     }
     for (int s = 0; s < 4; ++s) {
@@ -1326,7 +1345,7 @@ static int bo_depth(hierarchy* H, int d, double theta0)
     for (int o = 0; o < H->nobj; ++o) {
         if (H->depth[H->tp[o]] != d) continue;
         double b1[3];
-        if (interp_beta(&H->lv[H->tp[o]], H->xs[o], b1)) return -2;
+        if (interp_beta(&H->lv[H->tp[o]], H->xs[o], H->plane[H->tp[o]], b1)) return -2;
         for (int e = 0; e < 3; ++e) H->xp[3 * o + e] -= 0.5 * dt * (H->b0[o][e] + b1[e]);
     }
     if (d < H->maxdepth) {
@@ -1416,7 +1435,7 @@ int oz_bo_advance(oz_level* lv, int np, const oz_params* p, double dt0, int nste
 /* Probes for the pins: prolongation of the parent (three time levels,
    pa[t] may be NULL) into every ghost of the child, and restriction. */
 int oz_prolong(const double* pa0, const double* pa1, const double* pa2, const double* wt, long sfp, const int* np,
-               int ngp, double* uc, long sfc, const int* nc, int ngc, const int* F, int nthreads)
+               int ngp, double* uc, long sfc, const int* nc, int ngc, const int* F, int refl, int nthreads)
 {
     grid gp, gc;
     if (!uc || !wt || !np || !nc || !F) return -1;
@@ -1425,10 +1444,11 @@ int oz_prolong(const double* pa0, const double* pa1, const double* pa2, const do
     for (int d = 0; d < 3; ++d) {
         double w[6];
         int lo = prolong_1d(-ngc, F[d], w) + ngp, hi = prolong_1d(nc[d] + ngc - 1, F[d], w) + 5 + ngp;
-        if (lo < 0 || hi >= gp.N[d]) return -1;
+        if (d == 2 && refl) lo = lo < ngp ? 2 * ngp - 1 - lo : lo; /* reflected across the plane */
+        if (lo < 0 || lo >= gp.N[d] || hi >= gp.N[d]) return -1;
     }
     const double* pa[3] = {pa0, pa1, pa2};
-    prolong_ghosts(&gp, pa, wt, &gc, uc, F, nthreads < 1 ? 1 : nthreads);
+    prolong_ghosts(&gp, pa, wt, &gc, uc, F, refl != 0, nthreads < 1 ? 1 : nthreads);
     return 0;
 }
 
@@ -1496,8 +1516,9 @@ int oz_exchange(oz_level* lv, int np, int depth, int mode, int nthreads)
 /* ------------------------------------------------------------------ */
 
 /* 4-point Lagrange interpolation of beta at x from patch L (nodes: the
-   cell centres i0-1 .. i0+2 around x in each direction, all active) */
-static int interp_beta(const oz_level* L, const double x[3], double b[3])
+   cell centres i0-1 .. i0+2 around x in each direction, all active; refl:
+   z layers below the symmetry plane are mirror images of those above) */
+static int interp_beta(const oz_level* L, const double x[3], int refl, double b[3])
 {
     static const double nodes[4] = {-1.0, 0.0, 1.0, 2.0};
     grid g;
@@ -1507,16 +1528,24 @@ static int interp_beta(const oz_level* L, const double x[3], double b[3])
     for (int d = 0; d < 3; ++d) {
         const double sc = (x[d] - L->x0[d]) / L->h[d]; /* active-index coordinate */
         const int i0 = (int)floor(sc);
-        if (!(sc > -2.0 && sc < L->n[d] + 1.0) || i0 - 1 < 0 || i0 + 2 >= L->n[d]) return -1;
+        const int reach = (d == 2 && refl) ? -L->n[d] : 0; /* lowest active index the stencil may use */
+        if (!(sc > -2.0 + reach && sc < L->n[d] + 1.0) || i0 - 1 < reach || i0 + 2 >= L->n[d]) return -1;
         lo[d] = i0 - 1 + L->ng;
         lagrange_weights(nodes, 4, sc - i0, w[d]);
     }
     for (int a = 0; a < 3; ++a) {
         double s = 0.0;
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 4; ++k) {
+            int kz = lo[2] + k;
+            double sg = 1.0;
+            if (kz < L->ng) { /* only with refl: mirrored layer */
+                kz = 2 * L->ng - 1 - kz;
+                sg = z_parity(IBE + a);
+            }
             for (int j = 0; j < 4; ++j)
                 for (int i = 0; i < 4; ++i)
-                    s += w[2][k] * w[1][j] * w[0][i] * L->u[(IBE + a) * L->sf + lin(&g, lo[0] + i, lo[1] + j, lo[2] + k)];
+                    s += w[2][k] * w[1][j] * w[0][i] * (sg * L->u[(IBE + a) * L->sf + lin(&g, lo[0] + i, lo[1] + j, kz)]);
+        }
         b[a] = s;
     }
     return 0;
@@ -1542,7 +1571,9 @@ static int regrid(hierarchy* H)
         if (L->obj < 0 || L->obj >= H->nobj) continue;
         const oz_level* P = &lv[L->parent];
         int sh[3];
-        if (!patch_shift(L, H->xp + 3 * L->obj, sh)) continue;
+        patch_shift(L, H->xp + 3 * L->obj, sh);
+        if (H->plane[q]) sh[2] = 0; /* a patch on the symmetry plane stays on it */
+        if (!sh[0] && !sh[1] && !sh[2]) continue;
         grid g, gp;
         make_level_grid(&g, L, BC_COPY);
         make_level_grid(&gp, P, BC_COPY);
@@ -1574,10 +1605,17 @@ static int regrid(hierarchy* H)
                     const int lz = prolong_1d(k, F[2], wz) + P->ng;
                     for (int f = 0; f < NF; ++f) {
                         double s = 0.0;
-                        for (int c = 0; c < 6; ++c)
+                        for (int c = 0; c < 6; ++c) {
+                            int kz = lz + c;
+                            double sg = 1.0;
+                            if (H->plane[q] && kz < P->ng) {
+                                kz = 2 * P->ng - 1 - kz;
+                                sg = z_parity(f);
+                            }
                             for (int b = 0; b < 6; ++b)
                                 for (int m = 0; m < 6; ++m)
-                                    s += wz[c] * wy[b] * wx[m] * P->u[f * P->sf + lin(&gp, lx + m, ly + b, lz + c)];
+                                    s += wz[c] * wy[b] * wx[m] * (sg * P->u[f * P->sf + lin(&gp, lx + m, ly + b, kz)]);
+                        }
                         nu[f * L->sf + x] = s;
                     }
                 }
@@ -1631,7 +1669,7 @@ int oz_interp_beta(const double* u, long sf, const int* n, int ng, const double*
         L.h[d] = h[d];
         L.x0[d] = x0[d];
     }
-    return interp_beta(&L, x, b);
+    return interp_beta(&L, x, 0, b);
 }
 
 /* probe: one regrid of the moving patches toward xp (no time step) */

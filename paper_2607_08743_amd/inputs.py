@@ -320,6 +320,21 @@ def pair_hierarchy(root_n, h0, centers, moving, fixed=(), bc0=BC_PERIODIC, ng=NG
     return out
 
 
+def upper_half_patches(patches, states):
+    """The upper half (z > 0) of a hierarchy whose patches are all centred on
+    z = 0 with z-symmetric data: the root becomes an equatorial box, every
+    other patch a patch whose lower z face is the symmetry plane (F_z = 0)."""
+    out_p, out_s = [], []
+    for (g, F, par, obj), u in zip(patches, states):
+        if g.n[2] % 2 or abs(g.x0[2] + 0.5 * (g.n[2] - 1) * g.h[2]) > 1e-12 * g.h[2]:
+            raise ValueError("every patch must be centred on z = 0 with an even z extent")
+        gh = Grid((g.n[0], g.n[1], g.n[2] // 2), g.h, (g.x0[0], g.x0[1], 0.5 * g.h[2]),
+                  BC_EQUATORIAL if par < 0 else g.bc, g.ng)
+        out_p.append((gh, (F[0], F[1], 0) if par >= 0 else tuple(F), par, obj))
+        out_s.append(upper_half(u, g.ng))
+    return out_p, out_s
+
+
 def config_bbh_moving(root_n=128, h0=2.0, fixed=(128, 128, 128), moving=(64, 64, 64), sep=10.0):
     """The binary-black-hole layout of Sec. 2.2.1 (Fig. 1): a Sommerfeld
     root of root_n^3 cells (spacing h0) and fixed levels centred on the

@@ -238,7 +238,12 @@ int z4c_plan_destroy(void* plan);
  * index of that face, x0[d] = parent x0[d] + (F[d] - 1/4) * parent dx[d]
  * (checked); the 6-point stencils of every ghost must fall in the parent's
  * active cells.  obj: -1 for a fixed patch, else the index of the tracked
- * object the patch follows (z4c_hier_set_moving).  All six arrays are
+ * object the patch follows (z4c_hier_set_moving).  Equatorial symmetry
+ * (Sec. 2.2.2, 2.4): with an equatorial root, a patch whose parent lies on
+ * the symmetry plane and whose F[2] is 0 lies on it too; its prolongation
+ * reads the parent's layers below the plane as mirror images (each field's z
+ * parity), its own layers below the plane are the mirror images of its
+ * active ones, and it never shifts in z.  All six arrays are
  * caller-owned device arrays of 25 fields with stride sf, distinct from
  * every other patch's: u the state (advanced in place), u_a, u_b, acc the
  * RK4 scratch, prev and cur the patch's time levels kept for its children

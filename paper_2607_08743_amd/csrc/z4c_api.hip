@@ -643,6 +643,7 @@ struct HierPatch {
     bool lev_cur;    // lev[1] holds the prolongation of the parent's cur of its previous step, at this geometry
     long nshell;
     bool has_prev;  // prev holds this patch one step earlier
+    bool plane;     // its lower z face is the symmetry plane of an equatorial root
     int depth;
     int off[3];     // lattice index of the first active cell at the patch's depth
 };
@@ -651,6 +652,7 @@ struct HierDepth {
     std::vector<int> q;  // its patches, in index order
     BoxSet fused[4];
     BoxSet fill[4];      // ghost fill of the stage inputs u, a, b, a
+    BoxSet mirror[4];    // the patches on the symmetry plane: their layers below it
 };
 
 struct z4c_hier_s {
@@ -671,7 +673,7 @@ struct z4c_hier_s {
 
 // Geometry of patch x against its parent P: 2:1 spacing, lower faces on
 // parent cell F, every ghost's prolongation stencil in P's active cells.
-static int hier_check_level(const z4c_level& x, const z4c_level& P, const std::string& tag)
+static int hier_check_level(const z4c_level& x, const z4c_level& P, bool plane, const std::string& tag)
 {
     for (int d = 0; d < 3; ++d) {
         if (x.n[d] % 2) return fail(Z4C_EINVAL, tag + "active extents must be even");
@@ -691,8 +693,11 @@ static int hier_check_level(const z4c_level& x, const z4c_level& P, const std::s
         int lo_from, lo_to, hi_from, hi_to;
         span(-x.ng, lo_from, lo_to);
         span(x.n[d] + x.ng - 1, hi_from, hi_to);
-        const int lo = x.F[d] + lo_from, hi = x.F[d] + hi_to;
-        if (lo < 0 || hi >= P.n[d]) return fail(Z4C_EINVAL, tag + "prolongation stencil leaves the parent's active cells");
+        int lo = x.F[d] + lo_from;
+        const int hi = x.F[d] + hi_to;
+        if (d == 2 && plane && lo < 0) lo = -1 - lo;  // layers below the symmetry plane read as mirror images
+        if (lo < 0 || lo >= P.n[d] || hi >= P.n[d])
+            return fail(Z4C_EINVAL, tag + "prolongation stencil leaves the parent's active cells");
     }
     return Z4C_OK;
 }
@@ -705,11 +710,13 @@ static void hier_geometry(z4c_hier_s* H)
         HierPatch& P = H->pt[q];
         if (q == 0) {
             P.depth = 0;
+            P.plane = P.L.bc == Z4C_BC_EQUATORIAL;
             for (int d = 0; d < 3; ++d) P.off[d] = 0;
             continue;
         }
         const HierPatch& R = H->pt[P.L.parent];
         P.depth = R.depth + 1;
+        P.plane = R.plane && P.L.F[2] == 0;
         maxd = std::max(maxd, P.depth);
         // child active cell a sits at lattice index 2 (parent's first cell + F) + a
         for (int d = 0; d < 3; ++d) P.off[d] = 2 * (R.off[d] + P.L.F[d]);
@@ -752,6 +759,15 @@ static void hier_build_sets(z4c_hier_s* H, int d)
         }
         finalize_set(F, tab[H->tile_index].tile);
         D.fill[st] = F;
+        BoxSet& M = D.mirror[st];
+        M = BoxSet{};
+        for (int b = 0; b < F.nbox; ++b)
+            if (D.q[b] > 0 && H->pt[D.q[b]].plane) {
+                M.box[M.nbox] = F.box[b];
+                M.box[M.nbox].bc = Z4C_BC_EQUATORIAL;
+                ++M.nbox;
+            }
+        finalize_set(M, tab[H->tile_index].tile);
     }
 }
 
@@ -848,6 +864,7 @@ static hipError_t hier_track(z4c_hier_s* H, int o, int mode, hipStream_t s)
     a.ng = P.L.ng;
     a.dt = H->dt0 / (double)(1L << P.depth);
     a.mode = mode;
+    a.refl = P.plane ? 1 : 0;
     return launch_track(a, s);
 }
 
@@ -897,6 +914,7 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
                 a.shell = C.lev[t];
                 a.nshell = C.nshell;
                 a.ngc = C.L.ng;
+                a.refl = C.plane ? 1 : 0;
                 if ((e = launch_prolong(a, s)) != hipSuccess) return e;
             }
             C.lev_cur = true;
@@ -960,6 +978,7 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
         hipError_t r = hipSuccess;
         if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD)) r = launch_ghosts(D.fill[st], s);
         if (r == hipSuccess) r = hier_exchange_ghosts(H, d, st, s);
+        if (r == hipSuccess && D.mirror[st].nbox) r = launch_ghosts(D.mirror[st], s);
         return r;
     };
     auto stage = [&](int st) -> hipError_t {
@@ -989,6 +1008,7 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
         if ((e = hier_prolong(H, d + 1, 1.0, s)) != hipSuccess) return e;
         if ((e = launch_ghosts(H->dp[d + 1].fill[0], s)) != hipSuccess) return e;
         if ((e = hier_exchange_ghosts(H, d + 1, 0, s)) != hipSuccess) return e;
+        if (H->dp[d + 1].mirror[0].nbox && (e = launch_ghosts(H->dp[d + 1].mirror[0], s)) != hipSuccess) return e;
         if ((e = hier_restrict(H, d, s)) != hipSuccess) return e;
         for (int q : D.q) {
             HierPatch& P = H->pt[q];
@@ -1030,6 +1050,7 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
     if (!levels || nlev < 1 || nlev > MAXPATCH) return fail(Z4C_EINVAL, "need 1..32 patches");
     if (!finite_pos(dt0)) return fail(Z4C_EINVAL, "dt0 must be finite and > 0");
     std::vector<int> depth(nlev, 0);
+    std::vector<char> plane(nlev, 0);
     for (int l = 0; l < nlev; ++l) {
         const z4c_level& x = levels[l];
         const std::string tag = "patch " + std::to_string(l) + ": ";
@@ -1055,11 +1076,13 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
             if (x.parent != -1) return fail(Z4C_EINVAL, tag + "the root (patch 0) has parent -1");
             if (x.bc == Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "the root needs its own boundary");
             if (x.obj != -1) return fail(Z4C_EINVAL, tag + "the root cannot move");
+            plane[0] = x.bc == Z4C_BC_EQUATORIAL;
             continue;
         }
         if (x.parent < 0 || x.parent >= l) return fail(Z4C_EINVAL, tag + "parent must be a patch listed before it");
         if (x.bc != Z4C_BC_COPY) return fail(Z4C_EINVAL, tag + "patches >= 1 take Z4C_BC_COPY (filled from the parent)");
-        if ((rc = hier_check_level(x, levels[x.parent], tag))) return rc;
+        plane[l] = plane[x.parent] && x.F[2] == 0;
+        if ((rc = hier_check_level(x, levels[x.parent], plane[l], tag))) return rc;
         depth[l] = depth[x.parent] + 1;
         if (depth[l] > 30) return fail(Z4C_EINVAL, tag + "deeper than 30 levels");
     }
@@ -1168,6 +1191,7 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
             const double c = P.L.x0[d] + 0.5 * (P.L.n[d] - 1) * P.L.dx[d];
             const double x = st[10 * o + d];
             sh[d] = x - c > 2.0 * P.L.dx[d] ? 1 : (x - c < -2.0 * P.L.dx[d] ? -1 : 0);
+            if (d == 2 && P.plane) sh[d] = 0;  // a patch on the symmetry plane stays on it
             any |= sh[d] != 0;
         }
         if (!any) continue;
@@ -1179,12 +1203,12 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
         int rc;
         const std::string tag = "regrid of patch " + std::to_string(q) + ": ";
         const HierPatch& R = H->pt[P.L.parent];
-        if ((rc = hier_check_level(nl, R.L, tag))) return rc;
+        if ((rc = hier_check_level(nl, R.L, P.plane, tag))) return rc;
         for (int c = q + 1; c < np; ++c) {
             if (H->pt[c].L.parent != q) continue;
             z4c_level cl = H->pt[c].L;
             for (int d = 0; d < 3; ++d) cl.F[d] -= 2 * sh[d];
-            if ((rc = hier_check_level(cl, nl, tag + "child " + std::to_string(c) + ": "))) return rc;
+            if ((rc = hier_check_level(cl, nl, H->pt[c].plane, tag + "child " + std::to_string(c) + ": "))) return rc;
         }
         ShiftArgs a{};
         a.uc = P.L.u;
@@ -1201,6 +1225,7 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
             a.Np[d] = R.L.n[d] + 2 * R.L.ng;
             a.F[d] = nl.F[d];
         }
+        a.refl = P.plane ? 1 : 0;
         if ((e = launch_shift(a, s)) != hipSuccess) return hip_fail(e, "patch shift launch");
         if ((e = launch_copy(P.L.u, P.L.u_a, (long)NF * P.L.sf, s)) != hipSuccess) return hip_fail(e, "copy launch");
         P.L = nl;

@@ -106,6 +106,23 @@ __device__ __forceinline__ void shell_index(long q, int nx, int ny, int nz, int 
     i = (int)(q % Nx);
 }
 
+// z parity of a field: -1 for the components with one z index
+__device__ __forceinline__ double zpar(int f)
+{
+    return (f == F_GT + 2 || f == F_GT + 4 || f == F_AT + 2 || f == F_AT + 4 || f == F_GAM + 2 || f == F_BE + 2 ||
+            f == F_BB + 2)
+               ? -1.0
+               : 1.0;
+}
+
+// stored z index of a parent layer, reflected across the symmetry plane
+// (the lower face of the active cells) when refl and it lies below it
+__device__ __forceinline__ int refl_layer(int kz, int ng, bool refl, bool& neg)
+{
+    neg = refl && kz < ng;
+    return neg ? 2 * ng - 1 - kz : kz;
+}
+
 // child active index a -> parent active index of the containing cell and the
 // side of it the child lies on (+1 upper half, -1 lower half)
 __device__ __forceinline__ int prolong_cell(int a, int F, int& side)
@@ -117,16 +134,21 @@ __device__ __forceinline__ int prolong_cell(int a, int F, int& side)
 
 // Field f of the parent levels pa (time weights wt) interpolated at the child
 // point whose containing parent cell is (px, py, pz) (stored indices) and
-// whose sides are (sx, sy, sz).
+// whose sides are (sx, sy, sz); refl: parent layers below the symmetry plane
+// (stored z < ngp) are read as the mirror images of those above it.
 __device__ __forceinline__ double prolong_value(const double* const pa[3], const double wt[3], long sfp, long Nx,
-                                                long NxNy, int px, int py, int pz, int sx, int sy, int sz, int f)
+                                                long NxNy, int px, int py, int pz, int sx, int sy, int sz, int f,
+                                                bool refl, int ngp)
 {
     long ox[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) ox[m] = px + sx * kOff[m];
+    const double par = zpar(f);
     double s = 0.0;
     for (int c = 0; c < 6; ++c) {
-        const long zc = (long)(pz + sz * kOff[c]) * NxNy;
+        bool neg;
+        const long zc = (long)refl_layer(pz + sz * kOff[c], ngp, refl, neg) * NxNy;
+        const double sg = neg ? par : 1.0;
         double syy = 0.0;
         for (int b = 0; b < 6; ++b) {
             const long row = f * sfp + zc + (long)(py + sy * kOff[b]) * Nx;
@@ -140,7 +162,7 @@ __device__ __forceinline__ double prolong_value(const double* const pa[3], const
             }
             syy += kProlong.w[b] * sxx;
         }
-        s += kProlong.w[c] * syy;
+        s += kProlong.w[c] * (sg * syy);
     }
     return s;
 }
@@ -149,12 +171,14 @@ __device__ __forceinline__ double prolong_value(const double* const pa[3], const
 // same nearest-first order as prolong_value, with every loop unrolled so
 // that the 216 gathers issue back to back.
 __device__ __forceinline__ double prolong_one(const double* __restrict__ u, long Nx, long NxNy, int px, int py,
-                                              int pz, int sx, int sy, int sz)
+                                              int pz, int sx, int sy, int sz, bool refl, int ngp, double par)
 {
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const double* pl = u + (long)(pz + sz * kOffC[c]) * NxNy;
+        bool neg;
+        const double* pl = u + (long)refl_layer(pz + sz * kOffC[c], ngp, refl, neg) * NxNy;
+        const double sg = neg ? par : 1.0;
         double syy = 0.0;
 #pragma unroll
         for (int b = 0; b < 6; ++b) {
@@ -164,7 +188,7 @@ __device__ __forceinline__ double prolong_one(const double* __restrict__ u, long
             for (int m = 0; m < 6; ++m) sxx += kProlongC.w[m] * row[sx * kOffC[m]];
             syy += kProlongC.w[b] * sxx;
         }
-        s += kProlongC.w[c] * syy;
+        s += kProlongC.w[c] * (sg * syy);
     }
     return s;
 }
@@ -186,9 +210,11 @@ __global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
     const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
     const int nlev = (a.pa[0] != nullptr) + (a.pa[1] != nullptr) + (a.pa[2] != nullptr);
     if (nlev == 1 && a.pa[1] && a.wt[1] == 1.0)  // one level, weight 1: a plain spatial prolongation
-        a.shell[f * a.nshell + q] = prolong_one(a.pa[1] + f * a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz);
+        a.shell[f * a.nshell + q] =
+            prolong_one(a.pa[1] + f * a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, a.refl != 0, a.ngp, zpar(f));
     else
-        a.shell[f * a.nshell + q] = prolong_value(a.pa, a.wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f);
+        a.shell[f * a.nshell + q] =
+            prolong_value(a.pa, a.wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f, a.refl != 0, a.ngp);
 }
 
 // A moving patch shifted by 2 s of its cells (s per direction in -1..1):
@@ -215,7 +241,8 @@ __global__ void __launch_bounds__(256) shift_patch(ShiftArgs a)
     const double* const pa[3] = {nullptr, a.up, nullptr};
     const double wt[3] = {0.0, 1.0, 0.0};
     const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
-    for (int f = 0; f < NF; ++f) a.out[f * a.sfc + dst] = prolong_value(pa, wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f);
+    for (int f = 0; f < NF; ++f)
+        a.out[f * a.sfc + dst] = prolong_value(pa, wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f, a.refl != 0, a.ngp);
 }
 
 // Puncture tracking, dx/dt = -beta, Heun's method on the finest level's
@@ -233,13 +260,16 @@ __global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
     for (int d = 0; d < 3; ++d) {
         const double sc = (x[d] - a.x0[d]) / a.h[d];
         const int n = a.N[d] - 2 * a.ng;
-        // stencil cells i0-1 .. i0+2 must be active: otherwise flag it, read nothing
-        if (!(sc > -2.0 && sc < n + 1.0)) {
+        // stencil cells i0-1 .. i0+2 must be active (with refl, z layers below
+        // the symmetry plane are the mirror images of active ones): otherwise
+        // flag it, read nothing
+        const int reach = (d == 2 && a.refl) ? -n : 0;
+        if (!(sc > -2.0 + reach && sc < n + 1.0)) {
             st[9] = 1.0;
             return;
         }
         const int i0 = (int)floor(sc);
-        if (i0 - 1 < 0 || i0 + 2 >= n) {
+        if (i0 - 1 < reach || i0 + 2 >= n) {
             st[9] = 1.0;
             return;
         }
@@ -255,11 +285,15 @@ __global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
     double b[3];
     for (int c = 0; c < 3; ++c) {
         double s = 0.0;
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < 4; ++k) {
+            bool neg;
+            const int kz = refl_layer(lo[2] + k, a.ng, a.refl != 0, neg);
+            const double sg = neg ? zpar(F_BE + c) : 1.0;
             for (int j = 0; j < 4; ++j)
                 for (int i = 0; i < 4; ++i)
                     s += w[2][k] * w[1][j] * w[0][i] *
-                         a.u[(F_BE + c) * a.sf + (lo[2] + k) * NxNy + (long)(lo[1] + j) * Nx + (lo[0] + i)];
+                         (sg * a.u[(F_BE + c) * a.sf + (long)kz * NxNy + (long)(lo[1] + j) * Nx + (lo[0] + i)]);
+        }
         b[c] = s;
     }
     if (a.mode == 0) {

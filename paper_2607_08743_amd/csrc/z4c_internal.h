@@ -128,6 +128,7 @@ struct ProlongArgs {
     int nc[3];            // child active extents
     int ngc;
     int F[3];             // parent active cell index of the child's lower faces
+    int refl;             // the child's lower z face is a symmetry plane: parent layers below it are mirror images
 };
 // One patch of a hierarchy depth as the transfer kernels see it.  Lattice
 // index G of a cell at the patch's depth: active cell a of the patch sits at
@@ -166,6 +167,7 @@ struct ShiftArgs {
     int Np[3];
     int ngp;
     int F[3];          // parent active cell index of the shifted patch's lower faces
+    int refl;          // as in ProlongArgs
 };
 struct TrackArgs {
     double* state;  // device: x[3], b0[3], xs[3], error flag
@@ -176,6 +178,7 @@ struct TrackArgs {
     double x0[3], h[3];
     double dt;
     int mode;  // 0: predictor (before the step), 1: corrector (after it)
+    int refl;  // the level's lower z face is a symmetry plane: layers below it are mirror images
 };
 hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, hipStream_t s);

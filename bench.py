@@ -158,13 +158,14 @@ def mixed_hierarchy_error(z4c, I, torch, boxes, steps=50):
             "reference": "float64 GPU path (oracle parity <= 1e-12)"}
 
 
-def bbh_moving_rate(z4c, I, torch, steps=3, warmup=1):
+def bbh_moving_rate(z4c, I, torch, steps=3, warmup=1, equatorial=False):
     """The full hierarchy method on the binary-black-hole layout: Berger-Oliger
     subcycling over fixed levels and moving patch pairs (exchange, tracking,
-    regrid), FP64.  Zone updates count every patch's active cells once per
+    regrid), FP64; equatorial: the upper half with every patch on the
+    symmetry plane.  Zone updates count every patch's active cells once per
     step of its depth (2^depth steps per root step)."""
     import time
-    pt, states, dt0, xp = I.config_bbh_moving()
+    pt, states, dt0, xp = I.config_bbh_moving(equatorial=equatorial)
     depth = []
     for g, F, par, obj in pt:
         depth.append(0 if par < 0 else depth[par] + 1)
@@ -181,7 +182,8 @@ def bbh_moving_rate(z4c, I, torch, steps=3, warmup=1):
     finite = all(bool(torch.isfinite(u).all()) for u in H.u)
     H.close()
     upd = sum(g.active * 2 ** d for (g, *_), d in zip(pt, depth))
-    return {"value": upd * steps / sec, "unit": "zone-cycles/s", "ms_per_root_step": 1e3 * sec / steps,
+    extra = {"full_domain_equivalent_value": 2 * upd * steps / sec} if equatorial else {}
+    return {"value": upd * steps / sec, **extra, "unit": "zone-cycles/s", "ms_per_root_step": 1e3 * sec / steps,
             "patches": len(pt), "depths": max(depth) + 1,
             "active_cells": sum(g.active for g, *_ in pt), "zone_updates_per_root_step": upd,
             "punctures_start": xp.tolist(), "punctures_end": x.tolist(),
@@ -216,7 +218,7 @@ def main():
     ap.add_argument("--tile", default="", help="bx,by,bz,waves,persistent (skip the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["bbh_moving"], default="",
+    ap.add_argument("--only", choices=["bbh_moving", "bbh_moving_equatorial"], default="",
                     help="run only this extra measurement and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -234,8 +236,9 @@ def main():
     from paper_2607_08743_amd import z4c
 
     torch.cuda.set_device(0)
-    if args.only == "bbh_moving":
-        print(json.dumps({"bbh_moving": bbh_moving_rate(z4c, I, torch)}), flush=True)
+    if args.only:
+        print(json.dumps({args.only: bbh_moving_rate(z4c, I, torch, equatorial=args.only.endswith("equatorial"))}),
+              flush=True)
         return
     g, u0, dt = I.config_punctures(args.n)
     box = I.Box(g, u0, None, dt)
@@ -306,6 +309,7 @@ def main():
         extras["hierarchy9"] = {"value": act_h * args.steps / sec_h, "ms_per_step": 1e3 * sec_h / args.steps,
                                 "active_cells": act_h, "tile": list(best_h.as_tuple()), "finite": fin_h}
         extras["bbh_moving"] = bbh_moving_rate(z4c, I, torch)
+        extras["bbh_moving_equatorial"] = bbh_moving_rate(z4c, I, torch, equatorial=True)
         sec_hm, best_hm, _, fin_hm = run(boxes, pm, None)
         extras["hierarchy9_mixed"] = {"value": act_h * args.steps / sec_hm, "ms_per_step": 1e3 * sec_hm / args.steps,
                                       "tile": list(best_hm.as_tuple()), "finite": fin_hm,

@@ -326,17 +326,20 @@ __device__ __forceinline__ long lattice_index(const PatchRef& p, int g0, int g1,
 
 // Every parent active cell covered by the active region of a patch of the
 // finer depth takes that patch's restriction (the mean over the patches
-// that cover it, summed in patch order).
+// that cover it, summed in patch order).  One thread per (field, cell).
 __global__ void __launch_bounds__(256) restrict_cover(RestrictArgs a)
 {
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (long)a.ext[0] * a.ext[1] * a.ext[2]) return;
+    const long cells = (long)a.ext[0] * a.ext[1] * a.ext[2];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long)NF * cells) return;
+    const int f = (int)(g / cells);
+    const long q = g - (long)f * cells;
     const PatchRef& P = a.parent;
     const int x = a.lo[0] + (int)(q % a.ext[0]);
     const int y = a.lo[1] + (int)((q / a.ext[0]) % a.ext[1]);
     const int z = a.lo[2] + (int)(q / ((long)a.ext[0] * a.ext[1]));
     const int G0 = P.off[0] + x, G1 = P.off[1] + y, G2 = P.off[2] + z;
-    double s[NF];
+    double s = 0.0;
     int cnt = 0;
     for (int c = 0; c < a.nchild; ++c) {
         const PatchRef& C = a.child[c];
@@ -344,30 +347,26 @@ __global__ void __launch_bounds__(256) restrict_cover(RestrictArgs a)
         const int ac0 = 2 * G0 - C.off[0], ac1 = 2 * G1 - C.off[1], ac2 = 2 * G2 - C.off[2];
         if (ac0 < 0 || ac0 + 1 >= C.n[0] || ac1 < 0 || ac1 + 1 >= C.n[1] || ac2 < 0 || ac2 + 1 >= C.n[2]) continue;
         const long Ncx = C.N[0], NcxNcy = (long)C.N[0] * C.N[1];
-        const long cb = (long)(ac2 - 1 + C.ng) * NcxNcy + (long)(ac1 - 1 + C.ng) * Ncx + (ac0 - 1 + C.ng);
+        const double* u =
+            C.u + f * C.sf + (long)(ac2 - 1 + C.ng) * NcxNcy + (long)(ac1 - 1 + C.ng) * Ncx + (ac0 - 1 + C.ng);
+        double pl[4];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const double* u = C.u + f * C.sf + cb;
-            double pl[4];
+        for (int k = 0; k < 4; ++k) {
+            double rw[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                double rw[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double* row = u + k * NcxNcy + j * Ncx;
-                    rw[j] = rsum(row[0], row[1], row[2], row[3]);
-                }
-                pl[k] = rsum(rw[0], rw[1], rw[2], rw[3]);
+            for (int j = 0; j < 4; ++j) {
+                const double* row = u + k * NcxNcy + j * Ncx;
+                rw[j] = rsum(row[0], row[1], row[2], row[3]);
             }
-            const double v = rsum(pl[0], pl[1], pl[2], pl[3]);
-            s[f] = cnt ? s[f] + v : v;
+            pl[k] = rsum(rw[0], rw[1], rw[2], rw[3]);
         }
+        const double v = rsum(pl[0], pl[1], pl[2], pl[3]);
+        s = cnt ? s + v : v;
         ++cnt;
     }
     if (!cnt) return;
     const long pq = ((long)(z + P.ng) * P.N[1] + (y + P.ng)) * P.N[0] + (x + P.ng);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) P.u[f * P.sf + pq] = cnt == 1 ? s[f] : s[f] / cnt;
+    P.u[f * P.sf + pq] = cnt == 1 ? s : s / cnt;
 }
 
 // Exchange at one depth, averaging: a lattice cell in the active regions of
@@ -451,7 +450,7 @@ hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s)
 
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s)
 {
-    const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
+    const long n = (long)NF * a.ext[0] * a.ext[1] * a.ext[2];
     if (n <= 0 || a.nchild <= 0) return hipSuccess;
     hipLaunchKernelGGL(restrict_cover, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -669,7 +669,39 @@ struct z4c_hier_s {
     int nobj;            // tracked objects (0: no moving patches)
     int tp[MAXEX];       // per object: the patch it is tracked on
     double* track;       // device: per object x[3], b0[3], xs[3], error flag
+    double* sepx;        // device scratch of the separable prolongation (x sums)
+    double* sepy;        // (y sums)
 };
+
+// Parent rows (active index, before reflection) read by the prolongation of
+// child cells a = a0 .. a1 - 1 along one direction with faces on parent cell F.
+static void prolong_rows(int F, int a0, int a1, int& lo, int& hi)
+{
+    lo = INT32_MAX;
+    hi = INT32_MIN;
+    for (int a = a0; a < a1; ++a) {
+        const int half = a >= 0 ? a / 2 : -((1 - a) / 2);
+        const bool odd = a - 2 * half != 0;
+        lo = std::min(lo, F + half + (odd ? -2 : -3));
+        hi = std::max(hi, F + half + (odd ? 3 : 2));
+    }
+}
+
+// the scratch window of patch P: parent y rows Y0 .. Y0+NY-1, z rows Z0 .. Z0+NZ-1
+static void sep_window(const z4c_level& L, bool plane, int& Y0, int& NY, int& Z0, int& NZ)
+{
+    int lo, hi;
+    prolong_rows(L.F[1], -L.ng, L.n[1] + L.ng, lo, hi);
+    Y0 = lo;
+    NY = hi - lo + 1;
+    prolong_rows(L.F[2], -L.ng, L.n[2] + L.ng, lo, hi);
+    if (plane && lo < 0) {  // rows below the symmetry plane are read reflected
+        hi = std::max(hi, -1 - lo);
+        lo = 0;
+    }
+    Z0 = lo;
+    NZ = hi - lo + 1;
+}
 
 // Geometry of patch x against its parent P: 2:1 spacing, lower faces on
 // parent cell F, every ghost's prolongation stencil in P's active cells.
@@ -901,9 +933,8 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
             const bool reuse = P.has_prev && C.lev_cur;
             if (reuse && (e = launch_copy(C.lev[0], C.lev[1], (long)NF * C.nshell, s)) != hipSuccess) return e;
             for (int t = P.has_prev && !reuse ? 0 : 1; t < 3; ++t) {
-                ProlongArgs a{};
-                a.wt[1] = 1.0;
-                a.pa[1] = lv[t];
+                SepArgs a{};
+                a.u = lv[t];
                 a.sfp = P.L.sf;
                 for (int k = 0; k < 3; ++k) {
                     a.Np[k] = P.L.n[k] + 2 * P.L.ng;
@@ -911,11 +942,14 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
                     a.F[k] = C.L.F[k];
                 }
                 a.ngp = P.L.ng;
+                a.ngc = C.L.ng;
+                sep_window(C.L, C.plane, a.Y0, a.NY, a.Z0, a.NZ);
+                a.X = H->sepx;
+                a.Y = H->sepy;
                 a.shell = C.lev[t];
                 a.nshell = C.nshell;
-                a.ngc = C.L.ng;
                 a.refl = C.plane ? 1 : 0;
-                if ((e = launch_prolong(a, s)) != hipSuccess) return e;
+                if ((e = launch_prolong_sep(a, s)) != hipSuccess) return e;
             }
             C.lev_cur = true;
         }
@@ -1036,6 +1070,8 @@ static void hier_free(z4c_hier_s* H)
             if (b) (void)hipFree(b);
     }
     if (H->track) (void)hipFree(H->track);
+    if (H->sepx) (void)hipFree(H->sepx);
+    if (H->sepy) (void)hipFree(H->sepy);
     if (H->capture) (void)hipStreamDestroy(H->capture);
     delete H;
 }
@@ -1127,6 +1163,25 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         }
     }
     hier_geometry(H);
+    // scratch of the separable prolongation, for the largest window (its
+    // extent does not depend on where the patch sits)
+    size_t nx = 0, ny = 0;
+    for (int l = 1; l < nlev; ++l) {
+        const HierPatch& P = H->pt[l];
+        int Y0, NY, Z0, NZ;
+        sep_window(P.L, P.plane, Y0, NY, Z0, NZ);
+        const size_t NCx = P.L.n[0] + 2 * P.L.ng, NCy = P.L.n[1] + 2 * P.L.ng;
+        nx = std::max(nx, (size_t)NF * NZ * NY * NCx);
+        ny = std::max(ny, (size_t)NF * NZ * NCy * NCx);
+    }
+    if (nx) {
+        if (hipMalloc((void**)&H->sepx, nx * sizeof(double)) != hipSuccess) H->sepx = nullptr;
+        if (H->sepx && hipMalloc((void**)&H->sepy, ny * sizeof(double)) != hipSuccess) H->sepy = nullptr;
+        if (!H->sepx || !H->sepy) {
+            hier_free(H);
+            return fail(Z4C_ENOMEM, "prolongation scratch allocation failed");
+        }
+    }
     for (int d = 0; d < (int)H->dp.size(); ++d) hier_build_sets(H, d);
     *hier = H;
     return Z4C_OK;

@@ -55,7 +55,7 @@ constexpr ProlongW make_prolong_w()
 }
 __constant__ ProlongW kProlong = make_prolong_w();
 // the same offsets and weights as compile-time constants (immediates in the
-// unrolled single-level gather)
+// separable passes)
 constexpr int kOffC[6] = {0, 1, -1, 2, -2, 3};
 constexpr ProlongW kProlongC = make_prolong_w();
 
@@ -167,54 +167,71 @@ __device__ __forceinline__ double prolong_value(const double* const pa[3], const
     return s;
 }
 
-// Field f of ONE parent level (no time combination) at a child point; the
-// same nearest-first order as prolong_value, with every loop unrolled so
-// that the 216 gathers issue back to back.
-__device__ __forceinline__ double prolong_one(const double* __restrict__ u, long Nx, long NxNy, int px, int py,
-                                              int pz, int sx, int sy, int sz, bool refl, int ngp, double par)
+// Separable single-level prolongation, pass 1: x sums for every child x
+// index and parent (y, z) row in the scratch window.
+__global__ void __launch_bounds__(256) sep_x(SepArgs a)
 {
-    double s = 0.0;
+    const long NCx = a.nc[0] + 2 * a.ngc;
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long)NF * a.NZ * a.NY * NCx) return;
+    const int i = (int)(g % NCx);
+    const int sy = (int)((g / NCx) % a.NY);
+    const int rz = (int)((g / (NCx * a.NY)) % a.NZ);
+    const int f = (int)(g / (NCx * a.NY * a.NZ));
+    int sx;
+    const int px = prolong_cell(i - a.ngc, a.F[0], sx) + a.ngp;
+    const double* row = a.u + f * a.sfp + ((long)(a.Z0 + rz + a.ngp) * a.Np[1] + (a.Y0 + sy + a.ngp)) * a.Np[0] + px;
+    double sxx = 0.0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        bool neg;
-        const double* pl = u + (long)refl_layer(pz + sz * kOffC[c], ngp, refl, neg) * NxNy;
-        const double sg = neg ? par : 1.0;
-        double syy = 0.0;
-#pragma unroll
-        for (int b = 0; b < 6; ++b) {
-            const double* row = pl + (long)(py + sy * kOffC[b]) * Nx + px;
-            double sxx = 0.0;
-#pragma unroll
-            for (int m = 0; m < 6; ++m) sxx += kProlongC.w[m] * row[sx * kOffC[m]];
-            syy += kProlongC.w[b] * sxx;
-        }
-        s += kProlongC.w[c] * (sg * syy);
-    }
-    return s;
+    for (int m = 0; m < 6; ++m) sxx += kProlongC.w[m] * row[sx * kOffC[m]];
+    a.X[g] = sxx;
 }
 
-// one thread per (field, ghost point): 25 times the waves of one thread per
-// point, which the 216 gathered loads per value need to hide their latency
-__global__ void __launch_bounds__(256) prolong_shell(ProlongArgs a)
+// pass 2: y sums for every child (x, y) and parent z row in the window
+__global__ void __launch_bounds__(256) sep_y(SepArgs a)
 {
+    const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long)NF * a.NZ * NCy * NCx) return;
+    const int i = (int)(g % NCx);
+    const int j = (int)((g / NCx) % NCy);
+    const long fr = g / (NCx * NCy);  // f * NZ + rz
+    int sy;
+    const int py = prolong_cell(j - a.ngc, a.F[1], sy) - a.Y0;
+    const double* col = a.X + fr * a.NY * NCx + i;
+    double syy = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) syy += kProlongC.w[b] * col[(long)(py + sy * kOffC[b]) * NCx];
+    a.Y[g] = syy;
+}
+
+// pass 3: z sums at the shell points (rows below the symmetry plane, with
+// refl, are the mirror images of rows above it)
+__global__ void __launch_bounds__(256) sep_z(SepArgs a)
+{
+    const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
     const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long)NF * a.nshell) return;
     const int f = (int)(g / a.nshell);
     const long q = g - (long)f * a.nshell;
     int i, j, k;
     shell_index(q, a.nc[0], a.nc[1], a.nc[2], a.ngc, i, j, k);
-    int sx, sy, sz;
-    const int px = prolong_cell(i - a.ngc, a.F[0], sx) + a.ngp;
-    const int py = prolong_cell(j - a.ngc, a.F[1], sy) + a.ngp;
-    const int pz = prolong_cell(k - a.ngc, a.F[2], sz) + a.ngp;
-    const long Nx = a.Np[0], NxNy = (long)a.Np[0] * a.Np[1];
-    const int nlev = (a.pa[0] != nullptr) + (a.pa[1] != nullptr) + (a.pa[2] != nullptr);
-    if (nlev == 1 && a.pa[1] && a.wt[1] == 1.0)  // one level, weight 1: a plain spatial prolongation
-        a.shell[f * a.nshell + q] =
-            prolong_one(a.pa[1] + f * a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, a.refl != 0, a.ngp, zpar(f));
-    else
-        a.shell[f * a.nshell + q] =
-            prolong_value(a.pa, a.wt, a.sfp, Nx, NxNy, px, py, pz, sx, sy, sz, f, a.refl != 0, a.ngp);
+    int sz;
+    const int pz = prolong_cell(k - a.ngc, a.F[2], sz);
+    const double par = zpar(f);
+    const double* base = a.Y + (long)f * a.NZ * NCy * NCx + (long)j * NCx + i;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        int r = pz + sz * kOffC[c];
+        double sg = 1.0;
+        if (a.refl && r < 0) {
+            r = -1 - r;
+            sg = par;
+        }
+        s += kProlongC.w[c] * (sg * base[(long)(r - a.Z0) * NCy * NCx]);
+    }
+    a.shell[f * a.nshell + q] = s;
 }
 
 // A moving patch shifted by 2 s of its cells (s per direction in -1..1):
@@ -440,14 +457,6 @@ __global__ void __launch_bounds__(256) copy_state(double* __restrict__ dst, cons
 
 }  // namespace
 
-hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s)
-{
-    if (a.nshell <= 0) return hipSuccess;
-    const long n = (long)NF * a.nshell;
-    hipLaunchKernelGGL(prolong_shell, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s)
 {
     const long n = (long)NF * a.ext[0] * a.ext[1] * a.ext[2];
@@ -469,6 +478,17 @@ hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s)
     const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
     if (n <= 0 || a.np < 2) return hipSuccess;
     hipLaunchKernelGGL(exchange_ghosts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_sep(const SepArgs& a, hipStream_t s)
+{
+    if (a.nshell <= 0) return hipSuccess;
+    const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
+    const long nx = (long)NF * a.NZ * a.NY * NCx, ny = (long)NF * a.NZ * NCy * NCx, nz = (long)NF * a.nshell;
+    hipLaunchKernelGGL(sep_x, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sep_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sep_z, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

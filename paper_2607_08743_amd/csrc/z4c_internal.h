@@ -117,19 +117,6 @@ __device__ __forceinline__ void bar()
 }
 
 // Inter-level transfers of the Berger-Oliger hierarchy.
-struct ProlongArgs {
-    const double* pa[3];  // parent time levels (earlier, start, end of the parent step); NULL = weight 0
-    double wt[3];         // their time weights
-    long sfp;
-    int Np[3];            // parent stored extents
-    int ngp;
-    double* shell;        // child ghost shell (25 x nshell, canonical order)
-    long nshell;
-    int nc[3];            // child active extents
-    int ngc;
-    int F[3];             // parent active cell index of the child's lower faces
-    int refl;             // the child's lower z face is a symmetry plane: parent layers below it are mirror images
-};
 // One patch of a hierarchy depth as the transfer kernels see it.  Lattice
 // index G of a cell at the patch's depth: active cell a of the patch sits at
 // G = off + a (all patches of one depth share the lattice).
@@ -141,6 +128,27 @@ struct PatchRef {
     int n[3];    // active extents
     int ng;
     int off[3];
+};
+// Spatial prolongation of one parent level into a child's ghost shell,
+// evaluated in three separable passes through scratch (6-point sums nearest
+// node first, x innermost, then y, then z): X holds the x sums for every child x
+// index and every parent (y, z) row used, Y the y sums for every child
+// (x, y) and parent z row, the last pass the z sums at the shell points.
+struct SepArgs {
+    const double* u;  // parent level
+    long sfp;
+    int Np[3];        // parent stored extents
+    int ngp;
+    int nc[3];        // child active extents
+    int ngc;
+    int F[3];
+    int Y0, NY;       // parent active y rows Y0 .. Y0+NY-1 held in X
+    int Z0, NZ;       // parent active z rows Z0 .. Z0+NZ-1 held in X and Y
+    double* X;        // 25 x NZ x NY x (nc[0]+2ngc)
+    double* Y;        // 25 x NZ x (nc[1]+2ngc) x (nc[0]+2ngc)
+    double* shell;
+    long nshell;
+    int refl;         // the child's lower z face is a symmetry plane: parent rows below it are mirror images
 };
 struct RestrictArgs {
     PatchRef child[MAXEX];  // every patch of the finer depth (active cells and one ghost layer read)
@@ -167,7 +175,7 @@ struct ShiftArgs {
     int Np[3];
     int ngp;
     int F[3];          // parent active cell index of the shifted patch's lower faces
-    int refl;          // as in ProlongArgs
+    int refl;          // the patch lies on the symmetry plane: parent rows below it are mirror images
 };
 struct TrackArgs {
     double* state;  // device: x[3], b0[3], xs[3], error flag
@@ -180,7 +188,7 @@ struct TrackArgs {
     int mode;  // 0: predictor (before the step), 1: corrector (after it)
     int refl;  // the level's lower z face is a symmetry plane: layers below it are mirror images
 };
-hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
+hipError_t launch_prolong_sep(const SepArgs& a, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, hipStream_t s);
 hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);

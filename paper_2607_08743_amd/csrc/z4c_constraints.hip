@@ -23,7 +23,7 @@ namespace z4c {
 
 namespace {
 
-constexpr int CX = 8, CY = 8, CZ = 4;  // brick of one block (one point per thread)
+constexpr int CX = 8, CY = 8, CZ = 8;  // brick of one block (one point per thread)
 constexpr int CNT = CX * CY * CZ;
 
 // Tile geometry: halo 3 on the DMA path (tile rows then start on even

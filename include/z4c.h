@@ -295,8 +295,10 @@ int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream);
  * values, newly covered ones are prolonged from the parent, its children
  * keep their place in space (their F moves by -2).  A shift that would take
  * a patch's stencils out of its parent, or a puncture whose stencil leaves
- * its patch's active cells, fails with Z4C_EINVAL.  Allocates 80 bytes of
- * device memory per object. */
+ * its patch's active cells, fails with Z4C_EINVAL after that root step;
+ * the patches the same regrid shifted before the refused one stay shifted
+ * (and consistent), the refused one and those after it stay in place.
+ * Allocates 80 bytes of device memory per object. */
 int z4c_hier_set_moving(void* hier, int nobj, const double* xp);
 
 /* Current punctures (xp, 3 doubles per object; may be NULL) and, if not

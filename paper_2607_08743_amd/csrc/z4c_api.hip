@@ -1155,10 +1155,11 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         HierPatch& P = H->pt[l];
         double** bufs[4] = {&P.shell, &P.lev[0], &P.lev[1], &P.lev[2]};
         for (double** b : bufs) {
-            if (hipMalloc((void**)b, (size_t)NF * P.nshell * sizeof(double)) != hipSuccess) {
+            const hipError_t e = hipMalloc((void**)b, (size_t)NF * P.nshell * sizeof(double));
+            if (e != hipSuccess) {
                 *b = nullptr;
                 hier_free(H);
-                return fail(Z4C_ENOMEM, "ghost shell allocation failed");
+                return fail(Z4C_ENOMEM, std::string("ghost shell allocation failed: ") + hipGetErrorString(e));
             }
         }
     }
@@ -1175,11 +1176,12 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         ny = std::max(ny, (size_t)NF * NZ * NCy * NCx);
     }
     if (nx) {
-        if (hipMalloc((void**)&H->sepx, nx * sizeof(double)) != hipSuccess) H->sepx = nullptr;
-        if (H->sepx && hipMalloc((void**)&H->sepy, ny * sizeof(double)) != hipSuccess) H->sepy = nullptr;
+        hipError_t e = hipMalloc((void**)&H->sepx, nx * sizeof(double));
+        if (e != hipSuccess) H->sepx = nullptr;
+        if (H->sepx && (e = hipMalloc((void**)&H->sepy, ny * sizeof(double))) != hipSuccess) H->sepy = nullptr;
         if (!H->sepx || !H->sepy) {
             hier_free(H);
-            return fail(Z4C_ENOMEM, "prolongation scratch allocation failed");
+            return fail(Z4C_ENOMEM, std::string("prolongation scratch allocation failed: ") + hipGetErrorString(e));
         }
     }
     for (int d = 0; d < (int)H->dp.size(); ++d) hier_build_sets(H, d);
@@ -1236,6 +1238,15 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
             return fail(Z4C_EINVAL, "puncture " + std::to_string(o) + " left the active cells of its finest patch");
     const int np = (int)H->pt.size();
     bool moved = false;
+    // whatever happens below, patches that did move must not run on launch
+    // sets and a captured graph of their old geometry
+    auto finish = [&](int rc) {
+        if (moved) {
+            for (int d = 0; d < (int)H->dp.size(); ++d) hier_build_sets(H, d);
+            hier_drop_graph(H);
+        }
+        return rc;
+    };
     for (int q = 1; q < np; ++q) {
         HierPatch& P = H->pt[q];
         const int o = P.L.obj;
@@ -1258,12 +1269,13 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
         int rc;
         const std::string tag = "regrid of patch " + std::to_string(q) + ": ";
         const HierPatch& R = H->pt[P.L.parent];
-        if ((rc = hier_check_level(nl, R.L, P.plane, tag))) return rc;
+        if ((rc = hier_check_level(nl, R.L, P.plane, tag))) return finish(rc);
         for (int c = q + 1; c < np; ++c) {
             if (H->pt[c].L.parent != q) continue;
             z4c_level cl = H->pt[c].L;
             for (int d = 0; d < 3; ++d) cl.F[d] -= 2 * sh[d];
-            if ((rc = hier_check_level(cl, nl, H->pt[c].plane, tag + "child " + std::to_string(c) + ": "))) return rc;
+            if ((rc = hier_check_level(cl, nl, H->pt[c].plane, tag + "child " + std::to_string(c) + ": ")))
+                return finish(rc);
         }
         ShiftArgs a{};
         a.uc = P.L.u;
@@ -1281,8 +1293,9 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
             a.F[d] = nl.F[d];
         }
         a.refl = P.plane ? 1 : 0;
-        if ((e = launch_shift(a, s)) != hipSuccess) return hip_fail(e, "patch shift launch");
-        if ((e = launch_copy(P.L.u, P.L.u_a, (long)NF * P.L.sf, s)) != hipSuccess) return hip_fail(e, "copy launch");
+        if ((e = launch_shift(a, s)) != hipSuccess) return finish(hip_fail(e, "patch shift launch"));
+        if ((e = launch_copy(P.L.u, P.L.u_a, (long)NF * P.L.sf, s)) != hipSuccess)
+            return finish(hip_fail(e, "copy launch"));
         P.L = nl;
         P.has_prev = false;
         P.lev_cur = false;  // its ghosts sit elsewhere now
@@ -1294,11 +1307,7 @@ static int hier_regrid(z4c_hier_s* H, hipStream_t s)
         hier_geometry(H);
         moved = true;
     }
-    if (moved) {
-        for (int d = 0; d < (int)H->dp.size(); ++d) hier_build_sets(H, d);
-        hier_drop_graph(H);
-    }
-    return Z4C_OK;
+    return finish(Z4C_OK);
 }
 
 int z4c_hier_advance(void* hier, int nsteps, int use_graph, void* stream)
@@ -1365,7 +1374,7 @@ int z4c_hier_set_moving(void* hier, int nobj, const double* xp)
         if ((e = hipMalloc((void**)&H->track, 80 * (size_t)nobj)) != hipSuccess) {
             H->track = nullptr;
             H->nobj = 0;
-            return fail(Z4C_ENOMEM, "puncture state allocation failed");
+            return fail(Z4C_ENOMEM, std::string("puncture state allocation failed: ") + hipGetErrorString(e));
         }
     }
     std::vector<double> st(10 * (size_t)nobj, 0.0);

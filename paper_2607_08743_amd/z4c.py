@@ -72,6 +72,12 @@ def lib(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libz4c.so is not built ({path}); run __graft_entry__.build() "
                            "or python -m paper_2607_08743_amd.build")
+    # The library must run on the HIP runtime that owns torch's device memory
+    # and streams.  torch ships its own libamdhip64; once it is loaded, the
+    # library's dependency resolves to it by soname.  Loaded first, the
+    # library would pull in a second, separate HIP runtime, in which torch's
+    # stream handles are invalid (and which may not see the device at all).
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, dp, i, l, d = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_double
     pp = ctypes.POINTER(Params)

@@ -162,10 +162,30 @@ def test_product_path_has_no_oracle_dependency():
                 assert "import oracle" not in text and "from oracle" not in text and "oz_" not in text, f
 
 
+def test_library_shares_torch_hip_runtime():
+    """Loading the library first (default_params before any torch import)
+    still leaves one HIP runtime in the process: torch's, which owns the
+    device memory and the streams handed to the library."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2607_08743_amd import z4c\n"
+            "assert 'torch' not in sys.modules\n"
+            "z4c.default_params()\n"
+            "import torch, os\n"
+            "libs = {os.path.realpath(l.split()[-1]) for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "tl = os.path.realpath(os.path.join(os.path.dirname(torch.__file__), 'lib'))\n"
+            "print(len(libs), all(l.startswith(tl) for l in libs))\n") % root
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[-2:] == ["1", "True"], out.stdout
+
+
 def test_constraints_workspace_size(L):
-    # one partial per 8x8x4 brick of the active box, four constraints each
-    assert L.z4c_constraints_workspace(256, 256, 256) == 4 * 32 * 32 * 64
-    assert L.z4c_constraints_workspace(9, 8, 5) == 4 * 2 * 1 * 2
+    # one partial per 8x8x8 brick of the active box, four constraints each
+    assert L.z4c_constraints_workspace(256, 256, 256) == 4 * 32 * 32 * 32
+    assert L.z4c_constraints_workspace(9, 8, 9) == 4 * 2 * 1 * 2
     assert L.z4c_constraints_workspace(0, 8, 8) == 0
 
 

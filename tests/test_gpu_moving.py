@@ -137,3 +137,44 @@ def test_puncture_outside_active_cells_is_an_error():
     with pytest.raises(z4c.Z4cError, match="left the active cells"):
         H.advance(1)
     H.close()
+
+
+def test_failed_regrid_keeps_moved_patches_consistent():
+    """Two moving 24^3 patches of a 32^3 root; patch 2 already at the last
+    root cell its stencils allow.  Both punctures drift +x (constant shift)
+    and cross the shift threshold in the regrid after the second root step:
+    patch 1 moves, then patch 2's move is refused.  Patch 1 has moved all the
+    same, so the next step must use its new position: that step (which fails
+    the same way in its regrid) gives bitwise the same states from the
+    captured-graph path (whose graph, captured at the second step, holds
+    patch 1's old position and must be rebuilt) as from direct launches."""
+    print("case: regrid error after another patch moved, graph vs direct", flush=True)
+    root = I.centered_grid(32, 1.0, bc=I.BC_PERIODIC)
+    lv, xp = [], []
+    for q, F in enumerate(((0, 0, 0), (4, 10, 10), (16, 10, 10))):
+        g = root
+        if q:
+            x0 = tuple(root.x0[d] + (F[d] - 0.25) * root.h[d] for d in range(3))
+            g = I.Grid((24, 24, 24), (0.5,) * 3, x0, I.BC_COPY, 3)
+            xp.append([x0[d] + 0.5 * 23 * 0.5 + (0.85 if d == 0 else 0.0) for d in range(3)])
+        u = I.flat_state(g) + 1e-3 * (I.random_strong_field_state(g, seed=80 + q) - I.flat_state(g))
+        u[19] -= 0.2  # beta^x = -0.2: the punctures move by +0.1 per root step
+        lv.append((g, u, F, 0 if q else -1, q - 1))
+    xp = np.array(xp)
+    out = []
+    for use_graph in (True, False):
+        H = z4c.Hierarchy(lv, 0.5)
+        H.set_moving(xp)
+        H.advance(1, use_graph=use_graph)
+        assert H.puncture()[1][1:] == [(4, 10, 10), (16, 10, 10)]  # under the threshold
+        with pytest.raises(z4c.Z4cError, match="regrid of patch 2"):
+            H.advance(1, use_graph=use_graph)
+        assert H.puncture()[1][1:] == [(5, 10, 10), (16, 10, 10)]
+        with pytest.raises(z4c.Z4cError, match="regrid of patch 2"):
+            H.advance(1, use_graph=use_graph)
+        out.append(([to_host(u) for u in H.u], H.puncture()))
+        H.close()
+    (a, (xa, Fa, _)), (b, (xb, Fb, _)) = out
+    assert Fa == Fb and np.array_equal(xa, xb)
+    for q in range(3):
+        assert np.array_equal(a[q], b[q]), q

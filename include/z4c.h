@@ -247,7 +247,8 @@ int z4c_plan_destroy(void* plan);
  * caller-owned device arrays of 25 fields with stride sf, distinct from
  * every other patch's: u the state (advanced in place), u_a, u_b, acc the
  * RK4 scratch, prev and cur the patch's time levels kept for its children
- * (any contents on entry). */
+ * (any contents on entry; only the cells its children's prolongations read,
+ * one cell wider for children that move, are written there). */
 typedef struct z4c_level {
     int n[3];
     int ng;
@@ -268,10 +269,10 @@ typedef struct z4c_level {
 
 /* Create a hierarchy of nlev (1..32) patches, at most 16 per depth,
  * advanced with root step dt0.  tile == NULL: the library default shape
- * with a persistent launch.  Allocates four ghost-shell buffers per patch
+ * with a persistent launch.  Allocates three ghost-shell buffers per patch
  * >= 1 in device memory, each 25 x (stored - active) doubles: the spatial
- * prolongations of the parent's three time levels and their combination at
- * the current stage time (Z4C_ENOMEM if that fails). */
+ * prolongations of the parent's three time levels, which the ghost fill
+ * weights per stage time (Z4C_ENOMEM if that fails). */
 int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, double dt0, const z4c_tile* tile,
                     void** hier);
 

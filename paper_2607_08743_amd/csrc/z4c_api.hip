@@ -638,8 +638,9 @@ constexpr int MAXPATCH = 32;
 
 struct HierPatch {
     z4c_level L;
-    double* shell;  // device: ghost shell at the current stage time (patches >= 1)
     double* lev[3];  // device: spatial prolongations of the parent's time levels (prev, cur, new)
+    double wt[3];    // their weights at the current stage time (wt[0] unused without prev)
+    bool quad;       // the parent holds prev: quadratic in time
     bool lev_cur;    // lev[1] holds the prolongation of the parent's cur of its previous step, at this geometry
     long nshell;
     bool has_prev;  // prev holds this patch one step earlier
@@ -786,7 +787,6 @@ static void hier_build_sets(z4c_hier_s* H, int d)
             x.u_n = P.L.u;
             x.acc = P.L.acc;
             x.u_out = stage_out(P.L, st);
-            x.shell = P.shell;
             F.box[b] = x;
         }
         finalize_set(F, tab[H->tile_index].tile);
@@ -918,8 +918,9 @@ static void hier_time_weights(double theta, bool quadratic, double wt[3])
 // The ghost shells of every patch at depth d at theta (fraction of the
 // parent step).  Prolongation in space and interpolation in time are both
 // linear and commute: at the start of a parent step (theta 0) each parent
-// time level is prolonged once into its own shell, and the shell of every
-// stage time is then their weighted sum.
+// time level is prolonged once into its own shell; the shell of every stage
+// time is their weighted sum, formed by the ghost fill with the weights set
+// here.
 static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s)
 {
     for (int q : H->dp[d].q) {
@@ -953,11 +954,77 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
             }
             C.lev_cur = true;
         }
-        double wt[3];
-        hier_time_weights(theta, P.has_prev, wt);
-        if ((e = launch_combine(C.shell, P.has_prev ? C.lev[0] : nullptr, C.lev[1], C.lev[2], wt, (long)NF * C.nshell,
-                                s)) != hipSuccess)
-            return e;
+        C.quad = P.has_prev;
+        hier_time_weights(theta, C.quad, C.wt);
+    }
+    return hipSuccess;
+}
+
+// the ghost fill of stage input st at depth d: copy boxes take the weighted
+// sum of their parent's time levels at the stage time of their last
+// hier_prolong (the weights are kernel arguments, so a captured graph keeps
+// each launch's own)
+static BoxSet hier_fill_set(const z4c_hier_s* H, int d, int st)
+{
+    BoxSet F = H->dp[d].fill[st];
+    for (int b = 0; b < F.nbox; ++b) {
+        const HierPatch& C = H->pt[H->dp[d].q[b]];
+        if (H->dp[d].q[b] == 0) continue;
+        // theta 0 and 1 fall on the parent's cur and new levels: a copy
+        const int only = C.wt[0] == 0.0 && C.wt[1] == 1.0 && C.wt[2] == 0.0   ? 1
+                         : C.wt[0] == 0.0 && C.wt[1] == 0.0 && C.wt[2] == 1.0 ? 2
+                                                                              : -1;
+        if (only > 0) {
+            F.box[b].lv[1] = C.lev[only];
+            continue;
+        }
+        F.box[b].lv[0] = C.quad ? C.lev[0] : nullptr;
+        F.box[b].lv[1] = C.lev[1];
+        F.box[b].lv[2] = C.lev[2];
+        for (int t = 0; t < 3; ++t) F.box[b].lw[t] = C.wt[t];
+    }
+    return F;
+}
+
+// The parent cells (stored coordinates of P) that the prolongation of its
+// child C reads, one cell wider where C may shift (by one parent cell at
+// most, at a root-step boundary) before a level kept now is read again.
+static void child_window(const HierPatch& P, const HierPatch& C, int lo[3], int ext[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        int l, h;
+        prolong_rows(C.L.F[d], -C.L.ng, C.L.n[d] + C.L.ng, l, h);
+        if (d == 2 && C.plane && l < 0) {  // rows below the symmetry plane are read reflected
+            h = std::max(h, -1 - l);
+            l = 0;
+        }
+        if (C.L.obj >= 0 && !(d == 2 && C.plane)) {
+            --l;
+            ++h;
+        }
+        l = std::max(l + P.L.ng, 0);
+        h = std::min(h + P.L.ng, P.L.n[d] + 2 * P.L.ng - 1);
+        lo[d] = l;
+        ext[d] = h - l + 1;
+    }
+}
+
+// keep a time level of patch q (src -> dst): only the cells its children's
+// prolongations read
+static hipError_t hier_keep_level(z4c_hier_s* H, int q, double* dst, const double* src, hipStream_t s)
+{
+    const HierPatch& P = H->pt[q];
+    const int d = P.depth;
+    for (int c : H->dp[d + 1].q) {
+        if (H->pt[c].L.parent != q) continue;
+        CopyBoxArgs a{};
+        a.dst = dst;
+        a.src = src;
+        a.sf = P.L.sf;
+        for (int e = 0; e < 3; ++e) a.N[e] = P.L.n[e] + 2 * P.L.ng;
+        child_window(P, H->pt[c], a.lo, a.ext);
+        const hipError_t e = launch_copy_box(a, s);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -1010,7 +1077,7 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
     hipError_t e;
     auto fill = [&](int st) -> hipError_t {
         hipError_t r = hipSuccess;
-        if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD)) r = launch_ghosts(D.fill[st], s);
+        if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD)) r = launch_ghosts(hier_fill_set(H, d, st), s);
         if (r == hipSuccess) r = hier_exchange_ghosts(H, d, st, s);
         if (r == hipSuccess && D.mirror[st].nbox) r = launch_ghosts(D.mirror[st], s);
         return r;
@@ -1024,7 +1091,7 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
     if ((e = fill(0)) != hipSuccess) return e;
     if (d + 1 < ndepth)
         for (int q : D.q)
-            if ((e = launch_copy(H->pt[q].L.cur, H->pt[q].L.u, (long)NF * H->pt[q].L.sf, s)) != hipSuccess) return e;
+            if ((e = hier_keep_level(H, q, H->pt[q].L.cur, H->pt[q].L.u, s)) != hipSuccess) return e;
     for (int o = 0; o < H->nobj; ++o)
         if (H->pt[H->tp[o]].depth == d && (e = hier_track(H, o, 0, s)) != hipSuccess) return e;
     if ((e = stage(0)) != hipSuccess) return e;
@@ -1040,13 +1107,13 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
         if ((e = hier_depth_step(H, d + 1, 0.0, s)) != hipSuccess) return e;
         if ((e = hier_depth_step(H, d + 1, 0.5, s)) != hipSuccess) return e;
         if ((e = hier_prolong(H, d + 1, 1.0, s)) != hipSuccess) return e;
-        if ((e = launch_ghosts(H->dp[d + 1].fill[0], s)) != hipSuccess) return e;
+        if ((e = launch_ghosts(hier_fill_set(H, d + 1, 0), s)) != hipSuccess) return e;
         if ((e = hier_exchange_ghosts(H, d + 1, 0, s)) != hipSuccess) return e;
         if (H->dp[d + 1].mirror[0].nbox && (e = launch_ghosts(H->dp[d + 1].mirror[0], s)) != hipSuccess) return e;
         if ((e = hier_restrict(H, d, s)) != hipSuccess) return e;
         for (int q : D.q) {
             HierPatch& P = H->pt[q];
-            if ((e = launch_copy(P.L.prev, P.L.cur, (long)NF * P.L.sf, s)) != hipSuccess) return e;
+            if ((e = hier_keep_level(H, q, P.L.prev, P.L.cur, s)) != hipSuccess) return e;
             P.has_prev = true;
         }
     }
@@ -1065,7 +1132,6 @@ static void hier_free(z4c_hier_s* H)
 {
     hier_drop_graph(H);
     for (HierPatch& P : H->pt) {
-        if (P.shell) (void)hipFree(P.shell);
         for (double* b : P.lev)
             if (b) (void)hipFree(b);
     }
@@ -1145,15 +1211,16 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
     for (int l = 0; l < nlev; ++l) {
         HierPatch& P = H->pt[l];
         P.L = levels[l];
-        P.shell = nullptr;
         P.lev[0] = P.lev[1] = P.lev[2] = nullptr;
+        P.wt[0] = P.wt[1] = P.wt[2] = 0.0;
+        P.quad = false;
         P.lev_cur = false;
         P.has_prev = false;
         P.nshell = l > 0 ? shell_size(P.L.n, P.L.ng) : 0;
     }
     for (int l = 1; l < nlev; ++l) {
         HierPatch& P = H->pt[l];
-        double** bufs[4] = {&P.shell, &P.lev[0], &P.lev[1], &P.lev[2]};
+        double** bufs[3] = {&P.lev[0], &P.lev[1], &P.lev[2]};
         for (double** b : bufs) {
             const hipError_t e = hipMalloc((void**)b, (size_t)NF * P.nshell * sizeof(double));
             if (e != hipSuccess) {

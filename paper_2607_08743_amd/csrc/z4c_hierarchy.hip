@@ -3,10 +3,10 @@
 // refine 2:1 on cell-centred grids, so every child cell centre sits a quarter
 // parent cell from the centre of the parent cell that contains it.
 //
-//   prolongation: the child's ghost shell from the parent, 6th-order Lagrange
-//     interpolation in each direction (tensor product, 6x6x6 parent cells), of
-//     the parent time levels combined with the caller's time weights (or of
-//     one level, the shells of the levels then combined per stage time);
+//   prolongation: the child's ghost shell from one parent time level,
+//     6th-order Lagrange interpolation in each direction (tensor product,
+//     6x6x6 parent cells, in three separable passes); the ghost fill weights
+//     the levels' shells per stage time;
 //   restriction: every coarse cell covered by the active region of a finer
 //     patch from the 4th-order Lagrange interpolation of the 4x4x4 child
 //     cells around its centre (the mean where several patches cover it);
@@ -435,18 +435,18 @@ __global__ void __launch_bounds__(256) exchange_ghosts(ExchArgs a)
     }
 }
 
-// Ghost shell at one time of the parent step from the spatial prolongations
-// of the parent's time levels (prolongation and time interpolation are both
-// linear, so they commute); s0 may be NULL (weight 0).
-__global__ void __launch_bounds__(256) combine_shells(double* __restrict__ out, const double* __restrict__ s0,
-                                                      const double* __restrict__ s1, const double* __restrict__ s2,
-                                                      double w0, double w1, double w2, long n)
+__global__ void __launch_bounds__(256) copy_box(CopyBoxArgs a)
 {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = w1 * s1[i] + w2 * s2[i];
-    if (s0) v += w0 * s0[i];
-    out[i] = v;
+    const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (long)NF * n) return;
+    const int f = (int)(g / n);
+    const long r = g - (long)f * n;
+    const int i = (int)(r % a.ext[0]);
+    const int j = (int)((r / a.ext[0]) % a.ext[1]);
+    const int k = (int)(r / ((long)a.ext[0] * a.ext[1]));
+    const long p = f * a.sf + ((long)(a.lo[2] + k) * a.N[1] + (a.lo[1] + j)) * a.N[0] + (a.lo[0] + i);
+    a.dst[p] = a.src[p];
 }
 
 __global__ void __launch_bounds__(256) copy_state(double* __restrict__ dst, const double* __restrict__ src, long n)
@@ -506,12 +506,11 @@ hipError_t launch_track(const TrackArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_combine(double* out, const double* s0, const double* s1, const double* s2, const double w[3], long n,
-                          hipStream_t s)
+hipError_t launch_copy_box(const CopyBoxArgs& a, hipStream_t s)
 {
+    const long n = (long)NF * a.ext[0] * a.ext[1] * a.ext[2];
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(combine_shells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, s0, s1, s2, w[0], w[1],
-                       w[2], n);
+    hipLaunchKernelGGL(copy_box, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -31,6 +31,12 @@ struct BoxDev {
     double* acc;          // RK4 accumulator
     double* u_out;        // stage output, or the right-hand side in RHS mode
     const double* shell;  // ghost shell (copy boxes)
+    // Copy boxes of a patch hierarchy instead read the parent's time levels
+    // prolonged in space and fill each ghost with their weighted sum
+    // lw[1] lv[1] + lw[2] lv[2] (+ lw[0] lv[0] where lv[0] is set); with
+    // lv[2] NULL, lv[1] alone is the shell (a stage time that is a level).
+    const double* lv[3];
+    double lw[3];
     long sf;              // stride between fields
     int n[3];             // active cells
     int ng;               // ghost width
@@ -49,6 +55,7 @@ struct BoxSet {
     long shell_begin[MAXBOX + 1];
     BoxDev box[MAXBOX];
 };
+static_assert(sizeof(BoxSet) + 256 <= 4096, "a BoxSet and the scalars beside it must fit the kernel arguments");
 
 struct ParamsDev {
     double kappa1, kappa2, kappa3, eta, shift_coeff, ko_sigma, w_floor;
@@ -194,9 +201,18 @@ hipError_t launch_track(const TrackArgs& a, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_exchange_average(const ExchArgs& a, hipStream_t s);
 hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s);
+// Copy of the stored-coordinate box [lo, lo + ext) of all 25 fields
+// between two arrays of one patch's layout (stored extents N, field stride sf).
+struct CopyBoxArgs {
+    double* dst;
+    const double* src;
+    long sf;
+    int N[3];
+    int lo[3];
+    int ext[3];
+};
+hipError_t launch_copy_box(const CopyBoxArgs& a, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long n, hipStream_t s);
 // out = w0 s0 + w1 s1 + w2 s2 over n doubles (s0 may be NULL)
-hipError_t launch_combine(double* out, const double* s0, const double* s1, const double* s2, const double w[3], long n,
-                          hipStream_t s);
 
 }  // namespace z4c

@@ -1028,6 +1028,9 @@ __device__ __forceinline__ double z_sign(int f)
                : 1.0;
 }
 
+// One thread per ghost point, all 25 fields.  Every load of a point is
+// issued before its first store, so a thread keeps them all in flight (the
+// stores may alias the sources as far as the compiler knows).
 __global__ void __launch_bounds__(256) ghost_fill(BoxSet set)
 {
     const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1044,20 +1047,35 @@ __global__ void __launch_bounds__(256) ghost_fill(BoxSet set)
     const size_t p = ((size_t)k * Ny + j) * Nx + i;
     double* u = const_cast<double*>(B.u_in);
     const size_t sf = (size_t)B.sf;
+    double v[NF];
     if (B.bc == Z4C_BC_EQUATORIAL) {
         // layer ng-1-m below the symmetry plane mirrors layer ng+m above it
         const size_t src = ((size_t)(2 * B.ng - 1 - k) * Ny + j) * Nx + i;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) u[f * sf + p] = z_sign(f) * u[f * sf + src];
+        for (int f = 0; f < NF; ++f) v[f] = z_sign(f) * u[f * sf + src];
     } else if (B.bc == Z4C_BC_PERIODIC) {
         const size_t src = ((size_t)wrap(k, B.ng, B.n[2]) * Ny + wrap(j, B.ng, B.n[1])) * Nx + wrap(i, B.ng, B.n[0]);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) u[f * sf + p] = u[f * sf + src];
+        for (int f = 0; f < NF; ++f) v[f] = u[f * sf + src];
     } else {
         const size_t ns = (size_t)(set.shell_begin[bi + 1] - set.shell_begin[bi]);
+        if (B.lv[2]) {
+            // the shell at this stage time: weighted sum of the parent's time
+            // levels, each prolonged in space (both steps are linear and commute)
 #pragma unroll
-        for (int f = 0; f < NF; ++f) u[f * sf + p] = B.shell[f * ns + q];
+            for (int f = 0; f < NF; ++f) v[f] = B.lw[1] * B.lv[1][f * ns + q] + B.lw[2] * B.lv[2][f * ns + q];
+            if (B.lv[0]) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) v[f] += B.lw[0] * B.lv[0][f * ns + q];
+            }
+        } else {
+            const double* sh = B.lv[1] ? B.lv[1] : B.shell;  // a stage time that is a time level
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[f] = sh[f * ns + q];
+        }
     }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u[f * sf + p] = v[f];
 }
 
 // 2nd-order derivative for the Sommerfeld condition: centred where both

@@ -293,6 +293,12 @@ def main():
     extras = {}
     extras["constraints"] = constraint_monitor_rate(z4c, torch, g, u0, args.n)
     if not args.no_extras:
+        # the same puncture data on the 128^3 box (dx = 0.25), same tile
+        g2, u2, dt2 = I.config_punctures(128)
+        sec2, _, _, fin2 = run([I.Box(g2, u2, None, dt2)], params, best)
+        extras["box128"] = {"value": g2.active * args.steps / sec2, "ms_per_step": 1e3 * sec2 / args.steps,
+                            "tile": list(best.as_tuple()), "finite": fin2}
+        del u2
         pm = z4c.default_params(precision=z4c.MIXED)
         sec_m, best_m, _, fin_m = run([box], pm, None)
         extras["mixed"] = {"value": active * args.steps / sec_m, "ms_per_step": 1e3 * sec_m / args.steps,

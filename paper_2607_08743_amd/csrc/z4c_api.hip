@@ -672,6 +672,7 @@ struct z4c_hier_s {
     double* track;       // device: per object x[3], b0[3], xs[3], error flag
     double* sepx;        // device scratch of the separable prolongation (x sums)
     double* sepy;        // (y sums)
+    size_t sepx_cap, sepy_cap;  // their lengths (doubles)
 };
 
 // Parent rows (active index, before reflection) read by the prolongation of
@@ -881,23 +882,29 @@ static hipError_t hier_exchange_average(z4c_hier_s* H, int d, hipStream_t s)
     return hipSuccess;
 }
 
-static hipError_t hier_track(z4c_hier_s* H, int o, int mode, hipStream_t s)
+// the puncture update (mode 0: predictor, 1: corrector) of every object
+// whose deepest patch is at depth d, in one launch
+static hipError_t hier_track(z4c_hier_s* H, int d, int mode, hipStream_t s)
 {
-    const HierPatch& P = H->pt[H->tp[o]];
-    TrackArgs a{};
-    a.state = H->track + 10 * o;
-    a.u = P.L.u;
-    a.sf = P.L.sf;
-    for (int d = 0; d < 3; ++d) {
-        a.N[d] = P.L.n[d] + 2 * P.L.ng;
-        a.x0[d] = P.L.x0[d];
-        a.h[d] = P.L.dx[d];
+    TrackBatch b{};
+    for (int o = 0; o < H->nobj; ++o) {
+        const HierPatch& P = H->pt[H->tp[o]];
+        if (P.depth != d) continue;
+        TrackArgs& a = b.a[b.n++];
+        a.state = H->track + 10 * o;
+        a.u = P.L.u;
+        a.sf = P.L.sf;
+        for (int e = 0; e < 3; ++e) {
+            a.N[e] = P.L.n[e] + 2 * P.L.ng;
+            a.x0[e] = P.L.x0[e];
+            a.h[e] = P.L.dx[e];
+        }
+        a.ng = P.L.ng;
+        a.dt = H->dt0 / (double)(1L << P.depth);
+        a.mode = mode;
+        a.refl = P.plane ? 1 : 0;
     }
-    a.ng = P.L.ng;
-    a.dt = H->dt0 / (double)(1L << P.depth);
-    a.mode = mode;
-    a.refl = P.plane ? 1 : 0;
-    return launch_track(a, s);
+    return launch_track(b, s);
 }
 
 // Lagrange weights of the parent time levels (nodes -1, 0, 1 in units of
@@ -923,17 +930,33 @@ static void hier_time_weights(double theta, bool quadratic, double wt[3])
 // here.
 static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s)
 {
-    for (int q : H->dp[d].q) {
-        HierPatch& C = H->pt[q];
-        const HierPatch& P = H->pt[C.L.parent];
-        hipError_t e;
-        if (theta == 0.0) {
-            // the parent's prev is its cur of the previous step: reuse that
-            // prolongation unless this patch moved since
+    hipError_t e;
+    if (theta == 0.0) {
+        // the parent's prev is its cur of the previous step: reuse that
+        // prolongation unless the patch moved since (copied before lev[1]
+        // is overwritten below)
+        CopyList reuse{};
+        for (int q : H->dp[d].q) {
+            const HierPatch& C = H->pt[q];
+            if (!(H->pt[C.L.parent].has_prev && C.lev_cur)) continue;
+            reuse.dst[reuse.n] = C.lev[0];
+            reuse.src[reuse.n] = C.lev[1];
+            reuse.len[reuse.n] = (long)NF * C.nshell;
+            reuse.begin[reuse.n + 1] = batch_add(reuse.begin[reuse.n], reuse.len[reuse.n]);
+            ++reuse.n;
+        }
+        if ((e = launch_copy_list(reuse, s)) != hipSuccess) return e;
+        // every other level of every patch: the separable passes in batches
+        // that share the scratch (a batch's passes are done before the next
+        // batch's first pass, on the same stream)
+        SepBatch b{};
+        size_t ox = 0, oy = 0;
+        for (int q : H->dp[d].q) {
+            HierPatch& C = H->pt[q];
+            const HierPatch& P = H->pt[C.L.parent];
             const double* lv[3] = {P.L.prev, P.L.cur, P.L.u};
-            const bool reuse = P.has_prev && C.lev_cur;
-            if (reuse && (e = launch_copy(C.lev[0], C.lev[1], (long)NF * C.nshell, s)) != hipSuccess) return e;
-            for (int t = P.has_prev && !reuse ? 0 : 1; t < 3; ++t) {
+            const bool reused = P.has_prev && C.lev_cur;
+            for (int t = P.has_prev && !reused ? 0 : 1; t < 3; ++t) {
                 SepArgs a{};
                 a.u = lv[t];
                 a.sfp = P.L.sf;
@@ -945,16 +968,33 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
                 a.ngp = P.L.ng;
                 a.ngc = C.L.ng;
                 sep_window(C.L, C.plane, a.Y0, a.NY, a.Z0, a.NZ);
-                a.X = H->sepx;
-                a.Y = H->sepy;
                 a.shell = C.lev[t];
                 a.nshell = C.nshell;
                 a.refl = C.plane ? 1 : 0;
-                if ((e = launch_prolong_sep(a, s)) != hipSuccess) return e;
+                long nx, ny, nz;
+                sep_counts(a, nx, ny, nz);
+                if (b.n == MAXSEP || ox + (size_t)nx > H->sepx_cap || oy + (size_t)ny > H->sepy_cap) {
+                    if ((e = launch_prolong_sep(b, s)) != hipSuccess) return e;
+                    b = SepBatch{};
+                    ox = oy = 0;
+                }
+                a.X = H->sepx + ox;
+                a.Y = H->sepy + oy;
+                ox += (size_t)nx;
+                oy += (size_t)ny;
+                b.e[b.n] = a;
+                b.bx[b.n + 1] = batch_add(b.bx[b.n], nx);
+                b.by[b.n + 1] = batch_add(b.by[b.n], ny);
+                b.bz[b.n + 1] = batch_add(b.bz[b.n], nz);
+                ++b.n;
             }
             C.lev_cur = true;
         }
-        C.quad = P.has_prev;
+        if ((e = launch_prolong_sep(b, s)) != hipSuccess) return e;
+    }
+    for (int q : H->dp[d].q) {
+        HierPatch& C = H->pt[q];
+        C.quad = H->pt[C.L.parent].has_prev;
         hier_time_weights(theta, C.quad, C.wt);
     }
     return hipSuccess;
@@ -1009,24 +1049,24 @@ static void child_window(const HierPatch& P, const HierPatch& C, int lo[3], int 
     }
 }
 
-// keep a time level of patch q (src -> dst): only the cells its children's
-// prolongations read
-static hipError_t hier_keep_level(z4c_hier_s* H, int q, double* dst, const double* src, hipStream_t s)
+// keep a time level of every patch at depth d (prev: prev <- cur, else
+// cur <- u), over the cells their children's prolongations read, in one launch
+static hipError_t hier_keep_levels(z4c_hier_s* H, int d, bool prev, hipStream_t s)
 {
-    const HierPatch& P = H->pt[q];
-    const int d = P.depth;
+    CopyBoxBatch b{};
     for (int c : H->dp[d + 1].q) {
-        if (H->pt[c].L.parent != q) continue;
-        CopyBoxArgs a{};
-        a.dst = dst;
-        a.src = src;
+        const HierPatch& C = H->pt[c];
+        const HierPatch& P = H->pt[C.L.parent];
+        CopyBoxArgs& a = b.e[b.n];
+        a.dst = prev ? P.L.prev : P.L.cur;
+        a.src = prev ? P.L.cur : P.L.u;
         a.sf = P.L.sf;
         for (int e = 0; e < 3; ++e) a.N[e] = P.L.n[e] + 2 * P.L.ng;
-        child_window(P, H->pt[c], a.lo, a.ext);
-        const hipError_t e = launch_copy_box(a, s);
-        if (e != hipSuccess) return e;
+        child_window(P, C, a.lo, a.ext);
+        b.begin[b.n + 1] = batch_add(b.begin[b.n], (long)NF * a.ext[0] * a.ext[1] * a.ext[2]);
+        ++b.n;
     }
-    return hipSuccess;
+    return launch_copy_box(b, s);
 }
 
 // every patch at depth d: the cells covered by the patches of depth d+1
@@ -1089,11 +1129,8 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
     };
     if (d > 0 && theta0 == 0.0 && (e = hier_prolong(H, d, 0.0, s)) != hipSuccess) return e;
     if ((e = fill(0)) != hipSuccess) return e;
-    if (d + 1 < ndepth)
-        for (int q : D.q)
-            if ((e = hier_keep_level(H, q, H->pt[q].L.cur, H->pt[q].L.u, s)) != hipSuccess) return e;
-    for (int o = 0; o < H->nobj; ++o)
-        if (H->pt[H->tp[o]].depth == d && (e = hier_track(H, o, 0, s)) != hipSuccess) return e;
+    if (d + 1 < ndepth && (e = hier_keep_levels(H, d, false, s)) != hipSuccess) return e;
+    if ((e = hier_track(H, d, 0, s)) != hipSuccess) return e;
     if ((e = stage(0)) != hipSuccess) return e;
     if (d > 0 && (e = hier_prolong(H, d, theta0 + 0.25, s)) != hipSuccess) return e;
     if ((e = fill(1)) != hipSuccess || (e = stage(1)) != hipSuccess) return e;
@@ -1101,8 +1138,7 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
     if (d > 0 && (e = hier_prolong(H, d, theta0 + 0.5, s)) != hipSuccess) return e;
     if ((e = fill(3)) != hipSuccess || (e = stage(3)) != hipSuccess) return e;
     if ((e = hier_exchange_average(H, d, s)) != hipSuccess) return e;
-    for (int o = 0; o < H->nobj; ++o)
-        if (H->pt[H->tp[o]].depth == d && (e = hier_track(H, o, 1, s)) != hipSuccess) return e;
+    if ((e = hier_track(H, d, 1, s)) != hipSuccess) return e;
     if (d + 1 < ndepth) {
         if ((e = hier_depth_step(H, d + 1, 0.0, s)) != hipSuccess) return e;
         if ((e = hier_depth_step(H, d + 1, 0.5, s)) != hipSuccess) return e;
@@ -1111,11 +1147,8 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
         if ((e = hier_exchange_ghosts(H, d + 1, 0, s)) != hipSuccess) return e;
         if (H->dp[d + 1].mirror[0].nbox && (e = launch_ghosts(H->dp[d + 1].mirror[0], s)) != hipSuccess) return e;
         if ((e = hier_restrict(H, d, s)) != hipSuccess) return e;
-        for (int q : D.q) {
-            HierPatch& P = H->pt[q];
-            if ((e = hier_keep_level(H, q, P.L.prev, P.L.cur, s)) != hipSuccess) return e;
-            P.has_prev = true;
-        }
+        if ((e = hier_keep_levels(H, d, true, s)) != hipSuccess) return e;
+        for (int q : D.q) H->pt[q].has_prev = true;
     }
     return hipSuccess;
 }
@@ -1231,17 +1264,25 @@ int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, doub
         }
     }
     hier_geometry(H);
-    // scratch of the separable prolongation, for the largest window (its
-    // extent does not depend on where the patch sits)
+    // scratch of the separable prolongation: two levels of every patch of
+    // the depth that needs most (a window's extent does not depend on where
+    // the patch sits); a third level after a move goes into a later batch
     size_t nx = 0, ny = 0;
-    for (int l = 1; l < nlev; ++l) {
-        const HierPatch& P = H->pt[l];
-        int Y0, NY, Z0, NZ;
-        sep_window(P.L, P.plane, Y0, NY, Z0, NZ);
-        const size_t NCx = P.L.n[0] + 2 * P.L.ng, NCy = P.L.n[1] + 2 * P.L.ng;
-        nx = std::max(nx, (size_t)NF * NZ * NY * NCx);
-        ny = std::max(ny, (size_t)NF * NZ * NCy * NCx);
+    for (int d = 1; d < (int)H->dp.size(); ++d) {
+        size_t sx = 0, sy = 0;
+        for (int l : H->dp[d].q) {
+            const HierPatch& P = H->pt[l];
+            int Y0, NY, Z0, NZ;
+            sep_window(P.L, P.plane, Y0, NY, Z0, NZ);
+            const size_t NCx = P.L.n[0] + 2 * P.L.ng, NCy = P.L.n[1] + 2 * P.L.ng;
+            sx += 2 * (size_t)NF * NZ * NY * NCx;
+            sy += 2 * (size_t)NF * NZ * NCy * NCx;
+        }
+        nx = std::max(nx, sx);
+        ny = std::max(ny, sy);
     }
+    H->sepx_cap = nx;
+    H->sepy_cap = ny;
     if (nx) {
         hipError_t e = hipMalloc((void**)&H->sepx, nx * sizeof(double));
         if (e != hipSuccess) H->sepx = nullptr;

@@ -169,10 +169,24 @@ __device__ __forceinline__ double prolong_value(const double* const pa[3], const
 
 // Separable single-level prolongation, pass 1: x sums for every child x
 // index and parent (y, z) row in the scratch window.
-__global__ void __launch_bounds__(256) sep_x(SepArgs a)
+// Entry of a batch that the current block works on.  Entries start on
+// block boundaries (begin: exclusive prefix sums of the entries' thread
+// counts, each rounded up to whole blocks), so the entry is the same for the
+// whole block and its fields are read with scalar loads.
+__device__ __forceinline__ int block_entry(const long* begin, int n)
 {
+    const long g0 = (long)blockIdx.x * blockDim.x;
+    int e = 0;
+    while (e + 1 < n && g0 >= begin[e + 1]) ++e;
+    return __builtin_amdgcn_readfirstlane(e);
+}
+
+__global__ void __launch_bounds__(256) sep_x(SepBatch b)
+{
+    const int ei = block_entry(b.bx, b.n);
+    const SepArgs& a = b.e[ei];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.bx[ei];
     const long NCx = a.nc[0] + 2 * a.ngc;
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long)NF * a.NZ * a.NY * NCx) return;
     const int i = (int)(g % NCx);
     const int sy = (int)((g / NCx) % a.NY);
@@ -188,10 +202,12 @@ __global__ void __launch_bounds__(256) sep_x(SepArgs a)
 }
 
 // pass 2: y sums for every child (x, y) and parent z row in the window
-__global__ void __launch_bounds__(256) sep_y(SepArgs a)
+__global__ void __launch_bounds__(256) sep_y(SepBatch b)
 {
+    const int ei = block_entry(b.by, b.n);
+    const SepArgs& a = b.e[ei];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.by[ei];
     const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long)NF * a.NZ * NCy * NCx) return;
     const int i = (int)(g % NCx);
     const int j = (int)((g / NCx) % NCy);
@@ -201,16 +217,18 @@ __global__ void __launch_bounds__(256) sep_y(SepArgs a)
     const double* col = a.X + fr * a.NY * NCx + i;
     double syy = 0.0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b) syy += kProlongC.w[b] * col[(long)(py + sy * kOffC[b]) * NCx];
+    for (int m = 0; m < 6; ++m) syy += kProlongC.w[m] * col[(long)(py + sy * kOffC[m]) * NCx];
     a.Y[g] = syy;
 }
 
 // pass 3: z sums at the shell points (rows below the symmetry plane, with
 // refl, are the mirror images of rows above it)
-__global__ void __launch_bounds__(256) sep_z(SepArgs a)
+__global__ void __launch_bounds__(256) sep_z(SepBatch b)
 {
+    const int ei = block_entry(b.bz, b.n);
+    const SepArgs& a = b.e[ei];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.bz[ei];
     const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long)NF * a.nshell) return;
     const int f = (int)(g / a.nshell);
     const long q = g - (long)f * a.nshell;
@@ -267,13 +285,18 @@ __global__ void __launch_bounds__(256) shift_patch(ShiftArgs a)
 // beta(x), xs = x - dt b0; mode 1 (after it): x -= dt/2 (b0 + beta(xs)).
 // beta by 4-point Lagrange interpolation in each direction (cell centres
 // i0-1 .. i0+2 around the point, all active).  One thread: 64 terms per component.
-__global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
+__global__ void __launch_bounds__(64) track_puncture(TrackBatch batch)
 {
-    if (threadIdx.x != 0) return;
+    const TrackArgs& a = batch.a[blockIdx.x];
+    // lane t loads stencil point (t & 3, (t >> 2) & 3, t >> 4) of the three
+    // shift components (one round trip); lane 0 then sums them in index order
+    __shared__ double val[3][64];
+    const int t = threadIdx.x;
     double* st = a.state;
     const double* x = a.mode == 0 ? st : st + 6;
     double w[3][4];
     int lo[3];
+    // every lane derives the same stencil from the same position
     for (int d = 0; d < 3; ++d) {
         const double sc = (x[d] - a.x0[d]) / a.h[d];
         const int n = a.N[d] - 2 * a.ng;
@@ -282,35 +305,38 @@ __global__ void __launch_bounds__(64) track_puncture(TrackArgs a)
         // flag it, read nothing
         const int reach = (d == 2 && a.refl) ? -n : 0;
         if (!(sc > -2.0 + reach && sc < n + 1.0)) {
-            st[9] = 1.0;
+            if (t == 0) st[9] = 1.0;
             return;
         }
         const int i0 = (int)floor(sc);
         if (i0 - 1 < reach || i0 + 2 >= n) {
-            st[9] = 1.0;
+            if (t == 0) st[9] = 1.0;
             return;
         }
         lo[d] = i0 - 1 + a.ng;
-        const double t = sc - i0;
+        const double r = sc - i0;
         // nodes -1, 0, 1, 2
-        w[d][0] = (t - 0.0) * (t - 1.0) * (t - 2.0) / ((-1.0) * (-2.0) * (-3.0));
-        w[d][1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / ((1.0) * (-1.0) * (-2.0));
-        w[d][2] = (t + 1.0) * (t - 0.0) * (t - 2.0) / ((2.0) * (1.0) * (-1.0));
-        w[d][3] = (t + 1.0) * (t - 0.0) * (t - 1.0) / ((3.0) * (2.0) * (1.0));
+        w[d][0] = (r - 0.0) * (r - 1.0) * (r - 2.0) / ((-1.0) * (-2.0) * (-3.0));
+        w[d][1] = (r + 1.0) * (r - 1.0) * (r - 2.0) / ((1.0) * (-1.0) * (-2.0));
+        w[d][2] = (r + 1.0) * (r - 0.0) * (r - 2.0) / ((2.0) * (1.0) * (-1.0));
+        w[d][3] = (r + 1.0) * (r - 0.0) * (r - 1.0) / ((3.0) * (2.0) * (1.0));
     }
     const long Nx = a.N[0], NxNy = (long)a.N[0] * a.N[1];
+    {
+        const int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
+        bool neg;
+        const int kz = refl_layer(lo[2] + k, a.ng, a.refl != 0, neg);
+        const long p = (long)kz * NxNy + (long)(lo[1] + j) * Nx + (lo[0] + i);
+        for (int c = 0; c < 3; ++c) val[c][t] = (neg ? zpar(F_BE + c) : 1.0) * a.u[(F_BE + c) * a.sf + p];
+    }
+    __syncthreads();
+    if (t != 0) return;
     double b[3];
     for (int c = 0; c < 3; ++c) {
         double s = 0.0;
-        for (int k = 0; k < 4; ++k) {
-            bool neg;
-            const int kz = refl_layer(lo[2] + k, a.ng, a.refl != 0, neg);
-            const double sg = neg ? zpar(F_BE + c) : 1.0;
+        for (int k = 0; k < 4; ++k)
             for (int j = 0; j < 4; ++j)
-                for (int i = 0; i < 4; ++i)
-                    s += w[2][k] * w[1][j] * w[0][i] *
-                         (sg * a.u[(F_BE + c) * a.sf + (long)kz * NxNy + (long)(lo[1] + j) * Nx + (lo[0] + i)]);
-        }
+                for (int i = 0; i < 4; ++i) s += w[2][k] * w[1][j] * w[0][i] * val[c][(k * 4 + j) * 4 + i];
         b[c] = s;
     }
     if (a.mode == 0) {
@@ -435,10 +461,12 @@ __global__ void __launch_bounds__(256) exchange_ghosts(ExchArgs a)
     }
 }
 
-__global__ void __launch_bounds__(256) copy_box(CopyBoxArgs a)
+__global__ void __launch_bounds__(256) copy_box(CopyBoxBatch b)
 {
+    const int ei = block_entry(b.begin, b.n);
+    const CopyBoxArgs& a = b.e[ei];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.begin[ei];
     const long n = (long)a.ext[0] * a.ext[1] * a.ext[2];
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (long)NF * n) return;
     const int f = (int)(g / n);
     const long r = g - (long)f * n;
@@ -447,6 +475,14 @@ __global__ void __launch_bounds__(256) copy_box(CopyBoxArgs a)
     const int k = (int)(r / ((long)a.ext[0] * a.ext[1]));
     const long p = f * a.sf + ((long)(a.lo[2] + k) * a.N[1] + (a.lo[1] + j)) * a.N[0] + (a.lo[0] + i);
     a.dst[p] = a.src[p];
+}
+
+__global__ void __launch_bounds__(256) copy_list(CopyList c)
+{
+    const int ei = block_entry(c.begin, c.n);
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x - c.begin[ei];
+    if (i >= c.len[ei]) return;
+    c.dst[ei][i] = c.src[ei][i];
 }
 
 __global__ void __launch_bounds__(256) copy_state(double* __restrict__ dst, const double* __restrict__ src, long n)
@@ -481,14 +517,20 @@ hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_prolong_sep(const SepArgs& a, hipStream_t s)
+void sep_counts(const SepArgs& a, long& nx, long& ny, long& nz)
 {
-    if (a.nshell <= 0) return hipSuccess;
     const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
-    const long nx = (long)NF * a.NZ * a.NY * NCx, ny = (long)NF * a.NZ * NCy * NCx, nz = (long)NF * a.nshell;
-    hipLaunchKernelGGL(sep_x, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sep_y, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sep_z, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, a);
+    nx = a.nshell > 0 ? (long)NF * a.NZ * a.NY * NCx : 0;
+    ny = a.nshell > 0 ? (long)NF * a.NZ * NCy * NCx : 0;
+    nz = a.nshell > 0 ? (long)NF * a.nshell : 0;
+}
+
+hipError_t launch_prolong_sep(const SepBatch& b, hipStream_t s)
+{
+    if (b.n <= 0 || b.bz[b.n] <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sep_x, dim3((unsigned)((b.bx[b.n] + 255) / 256)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(sep_y, dim3((unsigned)((b.by[b.n] + 255) / 256)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(sep_z, dim3((unsigned)((b.bz[b.n] + 255) / 256)), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
@@ -500,17 +542,24 @@ hipError_t launch_shift(const ShiftArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_track(const TrackArgs& a, hipStream_t s)
+hipError_t launch_track(const TrackBatch& b, hipStream_t s)
 {
-    hipLaunchKernelGGL(track_puncture, dim3(1), dim3(64), 0, s, a);
+    if (b.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(track_puncture, dim3((unsigned)b.n), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_copy_box(const CopyBoxArgs& a, hipStream_t s)
+hipError_t launch_copy_box(const CopyBoxBatch& b, hipStream_t s)
 {
-    const long n = (long)NF * a.ext[0] * a.ext[1] * a.ext[2];
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(copy_box, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    if (b.n <= 0 || b.begin[b.n] <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_box, dim3((unsigned)((b.begin[b.n] + 255) / 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_list(const CopyList& c, hipStream_t s)
+{
+    if (c.n <= 0 || c.begin[c.n] <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_list, dim3((unsigned)((c.begin[c.n] + 255) / 256)), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 

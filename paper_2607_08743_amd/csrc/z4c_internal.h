@@ -195,9 +195,29 @@ struct TrackArgs {
     int mode;  // 0: predictor (before the step), 1: corrector (after it)
     int refl;  // the level's lower z face is a symmetry plane: layers below it are mirror images
 };
-hipError_t launch_prolong_sep(const SepArgs& a, hipStream_t s);
+// Several prolongations in one launch per pass (each with its own part of
+// the scratch); b* are exclusive prefix sums of the passes' thread counts,
+// each rounded up to whole 256-thread blocks (batch_add).
+constexpr int MAXSEP = 16;
+struct SepBatch {
+    int n;
+    long bx[MAXSEP + 1], by[MAXSEP + 1], bz[MAXSEP + 1];
+    SepArgs e[MAXSEP];
+};
+static_assert(sizeof(SepBatch) + 256 <= 4096, "a SepBatch must fit the kernel arguments");
+// threads of the three passes of one prolongation
+void sep_counts(const SepArgs& a, long& nx, long& ny, long& nz);
+// next exclusive prefix sum: an entry of `count` threads starts a block
+inline long batch_add(long begin, long count) { return begin + (count + 255) / 256 * 256; }
+hipError_t launch_prolong_sep(const SepBatch& b, hipStream_t s);
 hipError_t launch_shift(const ShiftArgs& a, hipStream_t s);
-hipError_t launch_track(const TrackArgs& a, hipStream_t s);
+// the puncture updates of several objects, one block each
+struct TrackBatch {
+    int n;
+    TrackArgs a[MAXEX];
+};
+static_assert(sizeof(TrackBatch) + 256 <= 4096, "a TrackBatch must fit the kernel arguments");
+hipError_t launch_track(const TrackBatch& b, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_exchange_average(const ExchArgs& a, hipStream_t s);
 hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s);
@@ -211,7 +231,22 @@ struct CopyBoxArgs {
     int lo[3];
     int ext[3];
 };
-hipError_t launch_copy_box(const CopyBoxArgs& a, hipStream_t s);
+struct CopyBoxBatch {
+    int n;
+    long begin[MAXEX + 1];  // exclusive prefix sums of 25 x box cells (batch_add)
+    CopyBoxArgs e[MAXEX];
+};
+static_assert(sizeof(CopyBoxBatch) + 256 <= 4096, "a CopyBoxBatch must fit the kernel arguments");
+hipError_t launch_copy_box(const CopyBoxBatch& b, hipStream_t s);
+// several flat copies of n[i] doubles in one launch
+struct CopyList {
+    int n;
+    long begin[MAXEX + 1];  // batch_add of len
+    long len[MAXEX];
+    double* dst[MAXEX];
+    const double* src[MAXEX];
+};
+hipError_t launch_copy_list(const CopyList& c, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, long n, hipStream_t s);
 // out = w0 s0 + w1 s1 + w2 s2 over n doubles (s0 may be NULL)
 

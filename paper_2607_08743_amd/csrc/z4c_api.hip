@@ -1115,9 +1115,26 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
     const z4c_level& R = H->pt[0].L;
     const bool outer = d == 0 && (R.bc == Z4C_BC_SOMMERFELD || R.bc == Z4C_BC_EQUATORIAL);
     hipError_t e;
+    // Patches (copy boxes) fill two arrays at once where two consumers share
+    // a stage time:
+    // * stage inputs 1 and 2, before stage 1 (which writes only the active
+    //   cells of input 2);
+    // * stage input 3 and the state u, whose next ghosts are taken at the same
+    //   time: at the start of the second step of the pair (theta 1/2), or by
+    //   the parent after the pair (theta 1).  Until then only active cells of
+    //   u are written or read (last stage, mean of overlaps, tracking, the
+    //   children's windows, restriction).
+    // The exchange and the mirror of the second array still follow the
+    // stages before its use, since they read active cells.
     auto fill = [&](int st) -> hipError_t {
         hipError_t r = hipSuccess;
-        if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD)) r = launch_ghosts(hier_fill_set(H, d, st), s);
+        if (d > 0 && (st == 1 || st == 3)) {
+            BoxSet F = hier_fill_set(H, d, st);
+            for (int b = 0; b < F.nbox; ++b) F.box[b].u_in2 = stage_in(H->pt[D.q[b]].L, st == 1 ? 2 : 0);
+            r = launch_ghosts(F, s);
+        } else if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD) && !(d > 0 && st == 2) && !(d > 0 && st == 0 && theta0 != 0.0)) {
+            r = launch_ghosts(hier_fill_set(H, d, st), s);
+        }
         if (r == hipSuccess) r = hier_exchange_ghosts(H, d, st, s);
         if (r == hipSuccess && D.mirror[st].nbox) r = launch_ghosts(D.mirror[st], s);
         return r;
@@ -1142,8 +1159,7 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
     if (d + 1 < ndepth) {
         if ((e = hier_depth_step(H, d + 1, 0.0, s)) != hipSuccess) return e;
         if ((e = hier_depth_step(H, d + 1, 0.5, s)) != hipSuccess) return e;
-        if ((e = hier_prolong(H, d + 1, 1.0, s)) != hipSuccess) return e;
-        if ((e = launch_ghosts(hier_fill_set(H, d + 1, 0), s)) != hipSuccess) return e;
+        // the patches' ghosts at theta 1 were filled with their last stage input
         if ((e = hier_exchange_ghosts(H, d + 1, 0, s)) != hipSuccess) return e;
         if (H->dp[d + 1].mirror[0].nbox && (e = launch_ghosts(H->dp[d + 1].mirror[0], s)) != hipSuccess) return e;
         if ((e = hier_restrict(H, d, s)) != hipSuccess) return e;

@@ -37,6 +37,7 @@ struct BoxDev {
     // lv[2] NULL, lv[1] alone is the shell (a stage time that is a level).
     const double* lv[3];
     double lw[3];
+    double* u_in2;        // ghost fill only: a second array that takes the same ghosts (NULL: none)
     long sf;              // stride between fields
     int n[3];             // active cells
     int ng;               // ghost width

@@ -1076,6 +1076,10 @@ __global__ void __launch_bounds__(256) ghost_fill(BoxSet set)
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) u[f * sf + p] = v[f];
+    if (B.u_in2) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) B.u_in2[f * sf + p] = v[f];
+    }
 }
 
 // 2nd-order derivative for the Sommerfeld condition: centred where both

@@ -689,6 +689,29 @@ static void prolong_rows(int F, int a0, int a1, int& lo, int& hi)
     }
 }
 
+// Parent rows that the lower (child index -ng .. -1) and upper (n .. n+ng-1)
+// ghost layers of a child read along one direction: {lo0, hi0, lo1, hi1};
+// refl maps a row r < 0 to its mirror image -1 - r.
+static void face_rows(int F, int n, int ng, bool refl, int out[4])
+{
+    auto span = [&](int a0, int a1, int& lo, int& hi) {
+        lo = INT32_MAX;
+        hi = INT32_MIN;
+        for (int a = a0; a < a1; ++a) {
+            const int half = a >= 0 ? a / 2 : -((1 - a) / 2);
+            const bool odd = a - 2 * half != 0;
+            for (int o = odd ? -2 : -3; o <= (odd ? 3 : 2); ++o) {
+                int r = F + half + o;
+                if (refl && r < 0) r = -1 - r;
+                lo = std::min(lo, r);
+                hi = std::max(hi, r);
+            }
+        }
+    };
+    span(-ng, 0, out[0], out[1]);
+    span(n, n + ng, out[2], out[3]);
+}
+
 // the scratch window of patch P: parent y rows Y0 .. Y0+NY-1, z rows Z0 .. Z0+NZ-1
 static void sep_window(const z4c_level& L, bool plane, int& Y0, int& NY, int& Z0, int& NZ)
 {
@@ -971,17 +994,20 @@ static hipError_t hier_prolong(z4c_hier_s* H, int d, double theta, hipStream_t s
                 a.shell = C.lev[t];
                 a.nshell = C.nshell;
                 a.refl = C.plane ? 1 : 0;
+                face_rows(C.L.F[2], C.L.n[2], C.L.ng, C.plane, a.zf);
+                face_rows(C.L.F[1], C.L.n[1], C.L.ng, false, a.yf);
                 long nx, ny, nz;
                 sep_counts(a, nx, ny, nz);
-                if (b.n == MAXSEP || ox + (size_t)nx > H->sepx_cap || oy + (size_t)ny > H->sepy_cap) {
+                const size_t sx = (size_t)NF * nx, sy = (size_t)NF * ny;  // scratch of all fields
+                if (b.n == MAXSEP || ox + sx > H->sepx_cap || oy + sy > H->sepy_cap) {
                     if ((e = launch_prolong_sep(b, s)) != hipSuccess) return e;
                     b = SepBatch{};
                     ox = oy = 0;
                 }
                 a.X = H->sepx + ox;
                 a.Y = H->sepy + oy;
-                ox += (size_t)nx;
-                oy += (size_t)ny;
+                ox += sx;
+                oy += sy;
                 b.e[b.n] = a;
                 b.bx[b.n + 1] = batch_add(b.bx[b.n], nx);
                 b.by[b.n + 1] = batch_add(b.by[b.n], ny);

@@ -67,43 +67,53 @@ static_assert(lagrange_weight(-1, 4, 0, 0.5) == kR0 && lagrange_weight(-1, 4, 1,
 
 __device__ __forceinline__ void shell_index(long q, int nx, int ny, int nz, int ng, int& i, int& j, int& k)
 {
-    const int Nx = nx + 2 * ng, Ny = ny + 2 * ng;
-    const long A = (long)Nx * Ny;
-    const long P = A - (long)nx * ny;
-    const long low = (long)ng * A;
-    if (q < low) {
-        k = (int)(q / A);
-        j = (int)((q % A) / Nx);
-        i = (int)(q % Nx);
+    // every index here is below the stored points of one field (< 2^31):
+    // 32-bit unsigned division is far cheaper than 64-bit
+    const unsigned Nx = nx + 2 * ng, Ny = ny + 2 * ng;
+    const unsigned A = Nx * Ny;
+    const unsigned P = A - (unsigned)nx * ny;  // ghost points of a plane that crosses the active box
+    const unsigned low = (unsigned)ng * A;
+    unsigned u = (unsigned)q;
+    if (u < low) {
+        k = (int)(u / A);
+        const unsigned r = u - (unsigned)k * A;
+        j = (int)(r / Nx);
+        i = (int)(r - (unsigned)j * Nx);
         return;
     }
-    q -= low;
-    if (q < (long)nz * P) {
-        k = ng + (int)(q / P);
-        long r = q % P;
-        const long rows_lo = (long)ng * Nx;
+    u -= low;
+    if (u < (unsigned)nz * P) {
+        const unsigned kk = u / P;
+        k = ng + (int)kk;
+        unsigned r = u - kk * P;
+        const unsigned rows_lo = (unsigned)ng * Nx;
         if (r < rows_lo) {
             j = (int)(r / Nx);
-            i = (int)(r % Nx);
+            i = (int)(r - (unsigned)j * Nx);
             return;
         }
         r -= rows_lo;
-        const long mid = (long)ny * 2 * ng;
+        const unsigned w2 = 2 * ng;
+        const unsigned mid = (unsigned)ny * w2;
         if (r < mid) {
-            j = ng + (int)(r / (2 * ng));
-            const int t = (int)(r % (2 * ng));
+            const unsigned jj = r / w2;
+            j = ng + (int)jj;
+            const int t = (int)(r - jj * w2);
             i = t < ng ? t : nx + t;
             return;
         }
         r -= mid;
-        j = ng + ny + (int)(r / Nx);
-        i = (int)(r % Nx);
+        const unsigned jj = r / Nx;
+        j = ng + ny + (int)jj;
+        i = (int)(r - jj * Nx);
         return;
     }
-    q -= (long)nz * P;
-    k = ng + nz + (int)(q / A);
-    j = (int)((q % A) / Nx);
-    i = (int)(q % Nx);
+    u -= (unsigned)nz * P;
+    const unsigned kk = u / A;
+    k = ng + nz + (int)kk;
+    const unsigned r = u - kk * A;
+    j = (int)(r / Nx);
+    i = (int)(r - (unsigned)j * Nx);
 }
 
 // z parity of a field: -1 for the components with one z index
@@ -169,6 +179,11 @@ __device__ __forceinline__ double prolong_value(const double* const pa[3], const
 
 // Separable single-level prolongation, pass 1: x sums for every child x
 // index and parent (y, z) row in the scratch window.
+__device__ __forceinline__ bool in_rows(int r, const int f[4])
+{
+    return (r >= f[0] && r <= f[1]) || (r >= f[2] && r <= f[3]);
+}
+
 // Entry of a batch that the current block works on.  Entries start on
 // block boundaries (begin: exclusive prefix sums of the entries' thread
 // counts, each rounded up to whole blocks), so the entry is the same for the
@@ -181,57 +196,62 @@ __device__ __forceinline__ int block_entry(const long* begin, int n)
     return __builtin_amdgcn_readfirstlane(e);
 }
 
+// The three passes put the field in blockIdx.y; within a field every index
+// is below the child's stored points (< 2^31), so it is split with 32-bit
+// unsigned divisions.  The prefix sums of a batch count one field's threads.
 __global__ void __launch_bounds__(256) sep_x(SepBatch b)
 {
     const int ei = block_entry(b.bx, b.n);
     const SepArgs& a = b.e[ei];
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.bx[ei];
-    const long NCx = a.nc[0] + 2 * a.ngc;
-    if (g >= (long)NF * a.NZ * a.NY * NCx) return;
-    const int i = (int)(g % NCx);
-    const int sy = (int)((g / NCx) % a.NY);
-    const int rz = (int)((g / (NCx * a.NY)) % a.NZ);
-    const int f = (int)(g / (NCx * a.NY * a.NZ));
+    const int f = (int)blockIdx.y;
+    const unsigned NCx = a.nc[0] + 2 * a.ngc, NY = a.NY;
+    const unsigned l = (unsigned)((long)blockIdx.x * blockDim.x + threadIdx.x - b.bx[ei]);
+    if (l >= (unsigned)a.NZ * NY * NCx) return;
+    const unsigned row = l / NCx;  // rz * NY + sy
+    const int i = (int)(l - row * NCx);
+    const unsigned rz = row / NY;
+    const int sy = (int)(row - rz * NY);
+    // x sums that no y sum the ghosts need will read
+    if (!(i < a.ngc || i >= a.nc[0] + a.ngc || in_rows(a.Z0 + (int)rz, a.zf) || in_rows(a.Y0 + sy, a.yf))) return;
     int sx;
     const int px = prolong_cell(i - a.ngc, a.F[0], sx) + a.ngp;
-    const double* row = a.u + f * a.sfp + ((long)(a.Z0 + rz + a.ngp) * a.Np[1] + (a.Y0 + sy + a.ngp)) * a.Np[0] + px;
+    const double* src = a.u + f * a.sfp + ((long)(a.Z0 + (int)rz + a.ngp) * a.Np[1] + (a.Y0 + sy + a.ngp)) * a.Np[0] + px;
     double sxx = 0.0;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) sxx += kProlongC.w[m] * row[sx * kOffC[m]];
-    a.X[g] = sxx;
+    for (int m = 0; m < 6; ++m) sxx += kProlongC.w[m] * src[sx * kOffC[m]];
+    a.X[(long)f * a.NZ * NY * NCx + l] = sxx;
 }
-
-// pass 2: y sums for every child (x, y) and parent z row in the window
 __global__ void __launch_bounds__(256) sep_y(SepBatch b)
 {
     const int ei = block_entry(b.by, b.n);
     const SepArgs& a = b.e[ei];
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.by[ei];
-    const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
-    if (g >= (long)NF * a.NZ * NCy * NCx) return;
-    const int i = (int)(g % NCx);
-    const int j = (int)((g / NCx) % NCy);
-    const long fr = g / (NCx * NCy);  // f * NZ + rz
+    const int f = (int)blockIdx.y;
+    const unsigned NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
+    const unsigned l = (unsigned)((long)blockIdx.x * blockDim.x + threadIdx.x - b.by[ei]);
+    if (l >= (unsigned)a.NZ * NCy * NCx) return;
+    const unsigned row = l / NCx;  // rz * NCy + j
+    const int i = (int)(l - row * NCx);
+    const unsigned rz = row / NCy;
+    const int j = (int)(row - rz * NCy);
+    // y sums of interior columns are needed only in the rows the z ghost layers read
+    if (!(i < a.ngc || i >= a.nc[0] + a.ngc || j < a.ngc || j >= a.nc[1] + a.ngc || in_rows(a.Z0 + (int)rz, a.zf)))
+        return;
     int sy;
     const int py = prolong_cell(j - a.ngc, a.F[1], sy) - a.Y0;
-    const double* col = a.X + fr * a.NY * NCx + i;
+    const double* col = a.X + ((long)f * a.NZ + rz) * a.NY * NCx + i;
     double syy = 0.0;
 #pragma unroll
     for (int m = 0; m < 6; ++m) syy += kProlongC.w[m] * col[(long)(py + sy * kOffC[m]) * NCx];
-    a.Y[g] = syy;
+    a.Y[(long)f * a.NZ * NCy * NCx + l] = syy;
 }
-
-// pass 3: z sums at the shell points (rows below the symmetry plane, with
-// refl, are the mirror images of rows above it)
 __global__ void __launch_bounds__(256) sep_z(SepBatch b)
 {
     const int ei = block_entry(b.bz, b.n);
     const SepArgs& a = b.e[ei];
-    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x - b.bz[ei];
+    const int f = (int)blockIdx.y;
     const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
-    if (g >= (long)NF * a.nshell) return;
-    const int f = (int)(g / a.nshell);
-    const long q = g - (long)f * a.nshell;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x - b.bz[ei];
+    if (q >= a.nshell) return;
     int i, j, k;
     shell_index(q, a.nc[0], a.nc[1], a.nc[2], a.ngc, i, j, k);
     int sz;
@@ -520,17 +540,17 @@ hipError_t launch_exchange_ghosts(const ExchArgs& a, hipStream_t s)
 void sep_counts(const SepArgs& a, long& nx, long& ny, long& nz)
 {
     const long NCx = a.nc[0] + 2 * a.ngc, NCy = a.nc[1] + 2 * a.ngc;
-    nx = a.nshell > 0 ? (long)NF * a.NZ * a.NY * NCx : 0;
-    ny = a.nshell > 0 ? (long)NF * a.NZ * NCy * NCx : 0;
-    nz = a.nshell > 0 ? (long)NF * a.nshell : 0;
+    nx = a.nshell > 0 ? (long)a.NZ * a.NY * NCx : 0;
+    ny = a.nshell > 0 ? (long)a.NZ * NCy * NCx : 0;
+    nz = a.nshell > 0 ? a.nshell : 0;
 }
 
 hipError_t launch_prolong_sep(const SepBatch& b, hipStream_t s)
 {
     if (b.n <= 0 || b.bz[b.n] <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sep_x, dim3((unsigned)((b.bx[b.n] + 255) / 256)), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(sep_y, dim3((unsigned)((b.by[b.n] + 255) / 256)), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(sep_z, dim3((unsigned)((b.bz[b.n] + 255) / 256)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(sep_x, dim3((unsigned)((b.bx[b.n] + 255) / 256), NF), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(sep_y, dim3((unsigned)((b.by[b.n] + 255) / 256), NF), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(sep_z, dim3((unsigned)((b.bz[b.n] + 255) / 256), NF), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

@@ -157,6 +157,13 @@ struct SepArgs {
     double* shell;
     long nshell;
     int refl;         // the child's lower z face is a symmetry plane: parent rows below it are mirror images
+    // Parent rows (active index, after reflection) that the child's lower and
+    // upper ghost layers read in z (zf) and in y (yf), as two intervals
+    // {lo0, hi0, lo1, hi1}.  Columns of the child's active x-y interior need
+    // y sums only in the zf rows, and those need x sums only in the yf rows;
+    // the passes skip every other entry of an interior column or row.
+    int zf[4];
+    int yf[4];
 };
 struct RestrictArgs {
     PatchRef child[MAXEX];  // every patch of the finer depth (active cells and one ghost layer read)
@@ -206,7 +213,8 @@ struct SepBatch {
     SepArgs e[MAXSEP];
 };
 static_assert(sizeof(SepBatch) + 256 <= 4096, "a SepBatch must fit the kernel arguments");
-// threads of the three passes of one prolongation
+// threads of the three passes of one prolongation, per field (the x and y
+// sums of all 25 fields take 25 times nx and ny doubles of scratch)
 void sep_counts(const SepArgs& a, long& nx, long& ny, long& nz);
 // next exclusive prefix sum: an entry of `count` threads starts a block
 inline long batch_add(long begin, long count) { return begin + (count + 255) / 256 * 256; }

@@ -964,45 +964,53 @@ hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int sta
 // ------------------------------------------------------------------------
 __device__ __forceinline__ void shell_point(long q, int nx, int ny, int nz, int ng, int& i, int& j, int& k)
 {
-    const int Nx = nx + 2 * ng, Ny = ny + 2 * ng;
-    const long A = (long)Nx * Ny;
-    const long P = A - (long)nx * ny;  // ghost points of a plane that crosses the active box
-    const long low = (long)ng * A;
-    if (q < low) {
-        k = (int)(q / A);
-        const long r = q % A;
+    // every index here is below the stored points of one field (< 2^31):
+    // 32-bit unsigned division is far cheaper than 64-bit
+    const unsigned Nx = nx + 2 * ng, Ny = ny + 2 * ng;
+    const unsigned A = Nx * Ny;
+    const unsigned P = A - (unsigned)nx * ny;  // ghost points of a plane that crosses the active box
+    const unsigned low = (unsigned)ng * A;
+    unsigned u = (unsigned)q;
+    if (u < low) {
+        k = (int)(u / A);
+        const unsigned r = u - (unsigned)k * A;
         j = (int)(r / Nx);
-        i = (int)(r % Nx);
+        i = (int)(r - (unsigned)j * Nx);
         return;
     }
-    q -= low;
-    if (q < (long)nz * P) {
-        k = ng + (int)(q / P);
-        long r = q % P;
-        const long rows_lo = (long)ng * Nx;
+    u -= low;
+    if (u < (unsigned)nz * P) {
+        const unsigned kk = u / P;
+        k = ng + (int)kk;
+        unsigned r = u - kk * P;
+        const unsigned rows_lo = (unsigned)ng * Nx;
         if (r < rows_lo) {
             j = (int)(r / Nx);
-            i = (int)(r % Nx);
+            i = (int)(r - (unsigned)j * Nx);
             return;
         }
         r -= rows_lo;
-        const long mid = (long)ny * 2 * ng;
+        const unsigned w2 = 2 * ng;
+        const unsigned mid = (unsigned)ny * w2;
         if (r < mid) {
-            j = ng + (int)(r / (2 * ng));
-            const int tt = (int)(r % (2 * ng));
-            i = tt < ng ? tt : nx + tt;
+            const unsigned jj = r / w2;
+            j = ng + (int)jj;
+            const int t = (int)(r - jj * w2);
+            i = t < ng ? t : nx + t;
             return;
         }
         r -= mid;
-        j = ng + ny + (int)(r / Nx);
-        i = (int)(r % Nx);
+        const unsigned jj = r / Nx;
+        j = ng + ny + (int)jj;
+        i = (int)(r - jj * Nx);
         return;
     }
-    q -= (long)nz * P;
-    k = ng + nz + (int)(q / A);
-    const long r = q % A;
+    u -= (unsigned)nz * P;
+    const unsigned kk = u / A;
+    k = ng + nz + (int)kk;
+    const unsigned r = u - kk * A;
     j = (int)(r / Nx);
-    i = (int)(r % Nx);
+    i = (int)(r - (unsigned)j * Nx);
 }
 
 __device__ __forceinline__ int wrap(int i, int ng, int n)

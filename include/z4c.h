@@ -34,10 +34,12 @@
  * next synchronisation or as Z4C_EHIP from a later call.
  * Errors.  Arguments are validated on the host before anything is enqueued;
  * an invalid call returns a negative z4c_status, enqueues nothing and leaves
- * a description in z4c_last_error().  Entry points other than the plan API
- * allocate nothing.  No entry point synchronises the device.
+ * a description in z4c_last_error().  Only the plan and hierarchy APIs
+ * allocate (at creation, and z4c_hier_set_moving).  No entry point
+ * synchronises the device except the hierarchy's puncture read-back
+ * (z4c_hier_advance with moving patches, z4c_hier_puncture).
  * Threads.  The single-box entry points are stateless and thread safe; a
- * plan must not be stepped from two threads at once.
+ * plan or a hierarchy must not be used from two threads at once.
  */
 #ifndef Z4C_H
 #define Z4C_H
@@ -50,7 +52,7 @@ typedef enum {
     Z4C_OK = 0,
     Z4C_EINVAL = -1,       /* invalid argument (nothing enqueued) */
     Z4C_EHIP = -2,         /* the HIP runtime reported an error */
-    Z4C_ENOMEM = -3,       /* device or host allocation failed (plan API only) */
+    Z4C_ENOMEM = -3,       /* device or host allocation failed (plan and hierarchy APIs only) */
     Z4C_EUNSUPPORTED = -4  /* valid request this build cannot serve (e.g. no such tile) */
 } z4c_status;
 
@@ -269,10 +271,14 @@ typedef struct z4c_level {
 
 /* Create a hierarchy of nlev (1..32) patches, at most 16 per depth,
  * advanced with root step dt0.  tile == NULL: the library default shape
- * with a persistent launch.  Allocates three ghost-shell buffers per patch
- * >= 1 in device memory, each 25 x (stored - active) doubles: the spatial
- * prolongations of the parent's three time levels, which the ghost fill
- * weights per stage time (Z4C_ENOMEM if that fails). */
+ * with a persistent launch.  Allocates in device memory (Z4C_ENOMEM if that
+ * fails):
+ *   three ghost-shell buffers per patch >= 1, each 25 x (stored - active)
+ *   doubles: the spatial prolongations of the parent's three time levels,
+ *   which the ghost fill weights per stage time;
+ *   the scratch of the separable prolongation: the x and y sums of two
+ *   levels of every patch of the depth that needs most (25 x its parent-row
+ *   window x its stored x-y extent, per level and pass). */
 int z4c_hier_create(const z4c_level* levels, int nlev, const z4c_params* p, double dt0, const z4c_tile* tile,
                     void** hier);
 

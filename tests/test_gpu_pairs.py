@@ -171,3 +171,22 @@ def test_far_pair_equals_single_chains():
         for i, q in enumerate(chain[1:], 1):
             assert np.array_equal(to_host(H.u[i]), got[q]), (o, q)
         H.close()
+
+
+def test_nine_patches_one_depth_parity(oz):
+    """Nine 16^3 patches at one depth (a 3 x 3 layout in a 48^3 periodic
+    root): 18 prolongation entries per parent step, more than one batch of
+    the separable passes takes, against the oracle after 2 root steps."""
+    print("case: nine patches at one depth vs oracle, 2 root steps", flush=True)
+    root = I.centered_grid(48, 1.0, bc=I.BC_PERIODIC)
+    pt = [(root, (0, 0, 0), -1, -1)]
+    for a in range(3):
+        for b in range(3):
+            F = (8 + 11 * a, 8 + 11 * b, 20)
+            x0 = tuple(root.x0[d] + (F[d] - 0.25) * root.h[d] for d in range(3))
+            pt.append((I.Grid((16, 16, 16), (0.5,) * 3, x0, I.BC_COPY, 3), F, 0, -1))
+    st = _states(pt, seed=90)
+    got, *_ = _gpu(pt, st, 0.5, 2)
+    lv, _ = _oracle(oz, pt, st, 0.5, 2)
+    alt, _ = _oracle(oz, pt, st, 0.5, 2, perturb=np.random.default_rng(5))
+    _compare(got, lv, alt)

@@ -8,11 +8,13 @@ fused launch per substep, the RK4 step replayed as a HIP graph, tile shape
 chosen by the autotuner).  value = zone cycles per second (active cells x
 RK4 steps / wall time), the unit the paper uses.
 
-Extras on the same JSON line: the same workload with float32 arithmetic
-(Z4C_MIXED), its z >= 0 half with equatorial symmetry, the 9-box hierarchy
-in one persistent launch per substep, the constraint monitor, the roofline
-of the fused kernel (HIP events around its launches on the stream it runs
-on) and the CPU oracle timed on a bounded sample.
+Extras on the same JSON line: the same data on the 128^3 box, the same
+workload with float32 arithmetic (Z4C_MIXED), its z >= 0 half with
+equatorial symmetry, the 9-box hierarchy in one persistent launch per
+substep (float64 and mixed), the binary-black-hole hierarchy with moving
+patches (full and equatorial half), the constraint monitor, the roofline of
+the fused kernel (HIP events around its launches on the stream it runs on)
+and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib

@@ -308,3 +308,19 @@ def test_hierarchy_validation(L, case):
     assert L.z4c_hier_create(arr, 2, ctypes.byref(p), 0.5, None, ctypes.byref(h)) == z4c.EINVAL
     assert HIER_CASES[case] in L.z4c_last_error().decode(), L.z4c_last_error().decode()
     assert not h.value
+
+
+def test_size_limits(L):
+    """Offsets inside one field are 32-bit in the kernels: a box of more than
+    2^31 - 1 stored points per field, or an extent above 2^20, is refused; the
+    largest cube under the limit passes the geometry check (the call then
+    fails on its NULL state pointer, after it)."""
+    p = z4c.default_params()
+    assert _rhs(L, p, sf=1 << 40, n=(1285, 1285, 1285)) == z4c.EINVAL  # 1291^3 > 2^31 - 1
+    assert "2^31-1" in L.z4c_last_error().decode()
+    assert _rhs(L, p, sf=1 << 40, n=(1 << 20, 1, 1)) == z4c.EINVAL
+    assert "extent too large" in L.z4c_last_error().decode()
+    assert 1290 ** 3 <= (1 << 31) - 1
+    assert _rhs(L, p, u=None, sf=1290 ** 3, n=(1284, 1284, 1284)) == z4c.EINVAL
+    msg = L.z4c_last_error().decode()
+    assert "stored points" not in msg and "extent" not in msg, msg

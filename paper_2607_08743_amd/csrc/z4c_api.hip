@@ -1158,8 +1158,10 @@ static hipError_t hier_depth_step(z4c_hier_s* H, int d, double theta0, hipStream
             BoxSet F = hier_fill_set(H, d, st);
             for (int b = 0; b < F.nbox; ++b) F.box[b].u_in2 = stage_in(H->pt[D.q[b]].L, st == 1 ? 2 : 0);
             r = launch_ghosts(F, s);
-        } else if (!(d == 0 && R.bc == Z4C_BC_SOMMERFELD) && !(d > 0 && st == 2) && !(d > 0 && st == 0 && theta0 != 0.0)) {
-            r = launch_ghosts(hier_fill_set(H, d, st), s);
+        } else {
+            const bool root_evolved = d == 0 && R.bc == Z4C_BC_SOMMERFELD;  // outer ghosts are evolved
+            const bool filled_before = d > 0 && (st == 2 || (st == 0 && theta0 != 0.0));
+            if (!root_evolved && !filled_before) r = launch_ghosts(hier_fill_set(H, d, st), s);
         }
         if (r == hipSuccess) r = hier_exchange_ghosts(H, d, st, s);
         if (r == hipSuccess && D.mirror[st].nbox) r = launch_ghosts(D.mirror[st], s);

@@ -324,3 +324,23 @@ def test_size_limits(L):
     assert _rhs(L, p, u=None, sf=1290 ** 3, n=(1284, 1284, 1284)) == z4c.EINVAL
     msg = L.z4c_last_error().decode()
     assert "stored points" not in msg and "extent" not in msg, msg
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises on every call: there is
+    no CPU fallback behind the product path."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2607_08743_amd import z4c\n"
+            "z4c.lib.__defaults__ = ('/nonexistent/libz4c.so',)\n"
+            "for call in (lambda: z4c.lib(), lambda: z4c.default_params()):\n"
+            "    try:\n"
+            "        call()\n"
+            "        print('no error')\n"
+            "    except RuntimeError as e:\n"
+            "        print('raised', 'not built' in str(e))\n") % root
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["raised", "True", "raised", "True"], out.stdout

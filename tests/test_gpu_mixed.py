@@ -96,3 +96,44 @@ def test_mixed_hierarchy_50_steps(oz):
         assert np.all(np.isfinite(got))
         assert np.all(rel[moved] < 1e-3), rel
     plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_hierarchy_box64_50_steps_fp64_and_mixed_vs_oracle(oz):
+    """The finest box of the 9-box hierarchy workload at full size (64^3,
+    h = 2/256, a copy box with its noisy fixed shell), 50 RK4 steps in a
+    persistent plan, float64 and mixed, against 50 oracle steps.  Float64:
+    per field within max(1e-12, 20 x the oracle's own one-ulp sensitivity
+    after the same 50 steps) -- the stage-level 1e-12 is checked in
+    test_gpu_stages.py; over many substeps two correct float64 codes that
+    round differently drift apart by about that sensitivity.  Mixed: per
+    field at float32 level relative to how far the field moved."""
+    print("case: 64^3 hierarchy box, 50 steps FP64 and mixed vs oracle", flush=True)
+    bx = I.config_hierarchy()[-1]
+    g = bx.grid
+    assert tuple(g.n) == (64, 64, 64)
+    got = {}
+    for prec in (z4c.FP64, z4c.MIXED):
+        plan = z4c.Plan([bx], params=z4c.default_params(precision=prec), tile=z4c.Tile(8, 8, 8, 2, 1))
+        plan.step(50)
+        got[prec] = to_host(plan.u[0])
+        plan.close()
+    ref = bx.state.copy()
+    oz.rk4(ref, g.as_dict(), bx.dt, 50, shell=bx.shell)
+    alt = bx.state + np.spacing(bx.state) * np.random.default_rng(0).choice([-1.0, 1.0], size=bx.state.shape)
+    oz.rk4(alt, g.as_dict(), bx.dt, 50, shell=bx.shell)
+    m = g.active_mask()
+    from gpu_helpers import normrel
+    e64 = normrel(got[z4c.FP64], ref, m)
+    sens = normrel(alt, ref, m)
+    print("fp64 normrel vs oracle:", " ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, e64)))
+    print("oracle 1-ulp sensitivity:", " ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, sens)))
+    assert np.all(e64 <= np.maximum(1e-12, 20 * sens)), e64
+    em = normrel(got[z4c.MIXED], ref, m)
+    dev = np.abs(ref[:, m] - bx.state[:, m]).max(axis=1)
+    err = np.abs(got[z4c.MIXED][:, m] - ref[:, m]).max(axis=1)
+    rel = err / np.maximum(dev, 1e-30)
+    print("mixed normrel vs oracle:", " ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, em)))
+    print("mixed error / change vs oracle:", " ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, rel)))
+    assert np.all(np.isfinite(got[z4c.MIXED]))
+    assert np.all(rel[dev > 1e-8] < 1e-3), rel

@@ -14,7 +14,9 @@ equatorial symmetry, the 9-box hierarchy in one persistent launch per
 substep (float64 and mixed), the binary-black-hole hierarchy with moving
 patches (full and equatorial half), the constraint monitor, the roofline of
 the fused kernel (HIP events around its launches on the stream it runs on)
-and the CPU oracle timed on a bounded sample.
+and the CPU oracle timed on a bounded sample.  Tile shapes come from the
+persisted tuning cache (paper_2607_08743_amd/tune_cache.jsonl; a miss times
+every compiled shape once and records the fastest).
 """
 import argparse
 import hashlib
@@ -28,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 KERNEL_SRC = os.path.join(ROOT, "paper_2607_08743_amd", "csrc", "z4c_kernels.hip")
+TUNE_CACHE = os.path.join(ROOT, "paper_2607_08743_amd", "tune_cache.jsonl")
 
 # HBM bytes per fused launch (mean of the four substeps) from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes over `bench.py --tile <tile> --steps 3
@@ -133,41 +136,71 @@ def constraint_monitor_rate(z4c, torch, g, u0, n, reps=5):
     return out
 
 
-def mixed_hierarchy_error(z4c, I, torch, boxes, steps=50):
-    """Per-field max relative error of the mixed-precision hierarchy after
-    `steps` RK4 steps against the float64 path (which matches the oracle to
-    1e-12): max over boxes of max|mixed - fp64| / max|fp64|, and of the same
-    difference over how far the field moved, max|fp64 - initial|."""
-    res = {}
-    for prec in (z4c.FP64, z4c.MIXED):
-        plan = z4c.Plan(boxes, params=z4c.default_params(precision=prec))
-        plan.step(steps)
-        torch.cuda.synchronize()
-        res[prec] = [u.cpu().numpy() for u in plan.u]
-        plan.close()
+def hierarchy_run(z4c, torch, boxes, prec, steps):
+    plan = z4c.Plan(boxes, params=z4c.default_params(precision=prec))
+    plan.step(steps)
+    torch.cuda.synchronize()
+    out = [u.cpu().numpy() for u in plan.u]
+    plan.close()
+    return out
+
+
+def per_field_errors(I, boxes, got, ref):
+    """Per field, max over boxes of max|got - ref| / max|ref| (norm-relative)
+    and of max|got - ref| / max|ref - initial| (relative to how far the field
+    moved), over the active cells."""
     norm = [0.0] * 25
     moved = [0.0] * 25
-    for bx, a, b in zip(boxes, res[z4c.MIXED], res[z4c.FP64]):
+    for bx, a, b in zip(boxes, got, ref):
         m = bx.grid.active_mask()
         for f in range(25):
             d = float(abs(a[f][m] - b[f][m]).max())
-            s = float(abs(b[f][m]).max())
+            sc = float(abs(b[f][m]).max())
             mv = float(abs(b[f][m] - bx.state[f][m]).max())
-            norm[f] = max(norm[f], d / s if s > 0 else d)
+            norm[f] = max(norm[f], d / sc if sc > 0 else d)
             moved[f] = max(moved[f], d / mv if mv > 1e-8 else 0.0)
-    return {"steps": steps, "per_field_normrel": dict(zip(I.FIELD_NAMES, norm)),
+    return {"per_field_normrel": dict(zip(I.FIELD_NAMES, norm)),
             "per_field_rel_to_change": dict(zip(I.FIELD_NAMES, moved)),
-            "reference": "float64 GPU path (oracle parity <= 1e-12)"}
+            "max_normrel": max(norm), "max_rel_to_change": max(moved)}
 
 
-def bbh_moving_rate(z4c, I, torch, steps=3, warmup=1, equatorial=False):
+def mixed_hierarchy_error(z4c, I, torch, boxes, steps=50, oracle_boxes=(8, 7)):
+    """Mixed precision on the 9-box hierarchy after `steps` RK4 steps.
+    Against the float64 ORACLE (its own 50 steps on the host) for the boxes
+    oracle_boxes (the smallest: 64^3 and 72^3 -- the whole hierarchy would
+    take the oracle several minutes), for both GPU precisions; and, for all
+    nine boxes, mixed against the float64 GPU path."""
+    import oracle
+
+    oracle.build(force=False)
+    res = {prec: hierarchy_run(z4c, torch, boxes, prec, steps) for prec in (z4c.FP64, z4c.MIXED)}
+    sub = [boxes[i] for i in oracle_boxes]
+    t0 = time.perf_counter()
+    ref = []
+    for bx in sub:
+        r = bx.state.copy()
+        oracle.rk4(r, bx.grid.as_dict(), bx.dt, steps, shell=bx.shell)
+        ref.append(r)
+    t_oracle = time.perf_counter() - t0
+    return {"steps": steps,
+            "vs_oracle": {"boxes": [f"level {bx.level}: {bx.grid.n[0]}^3" for bx in sub],
+                          "oracle_seconds": round(t_oracle, 1),
+                          "mixed": per_field_errors(I, sub, [res[z4c.MIXED][i] for i in oracle_boxes], ref),
+                          "fp64": per_field_errors(I, sub, [res[z4c.FP64][i] for i in oracle_boxes], ref)},
+            "mixed_vs_fp64_gpu_all_boxes": per_field_errors(I, boxes, res[z4c.MIXED], res[z4c.FP64])}
+
+
+def bbh_moving_rate(z4c, I, torch, steps=5, warmup=1, equatorial=False, lag=0.05):
     """The full hierarchy method on the binary-black-hole layout: Berger-Oliger
     subcycling over fixed levels and moving patch pairs (exchange, tracking,
     regrid), FP64; equatorial: the upper half with every patch on the
-    symmetry plane.  Zone updates count every patch's active cells once per
-    step of its depth (2^depth steps per root step)."""
-    import time
-    pt, states, dt0, xp = I.config_bbh_moving(equatorial=equatorial)
+    symmetry plane.  The punctures start `lag` inside their patches' centres,
+    so that the deepest moving patches shift during the timed root steps.
+    Each root step is timed on its own (the hierarchy reads the punctures back
+    after every root step anyway); the step after which a patch shifted
+    includes the shift, the next one the re-capture of the graph.  Zone
+    updates count every patch's active cells once per step of its depth."""
+    pt, states, dt0, xp = I.config_bbh_moving(equatorial=equatorial, lag=lag)
     depth = []
     for g, F, par, obj in pt:
         depth.append(0 if par < 0 else depth[par] + 1)
@@ -176,37 +209,81 @@ def bbh_moving_rate(z4c, I, torch, steps=3, warmup=1, equatorial=False):
     H.set_moving(xp)
     H.advance(warmup)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    H.advance(steps)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
+    _, Fprev, _ = H.puncture()
+    per_step, shifted = [], []
+    for k in range(steps):
+        t0 = time.perf_counter()
+        H.advance(1)
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - t0)
+        _, F, _ = H.puncture()
+        shifted.append([q for q in range(len(pt)) if tuple(F[q]) != tuple(Fprev[q])])
+        Fprev = F
+    sec = sum(per_step)
     x, F, x0 = H.puncture()
     finite = all(bool(torch.isfinite(u).all()) for u in H.u)
     H.close()
     upd = sum(g.active * 2 ** d for (g, *_), d in zip(pt, depth))
+    quiet = [t for k, t in enumerate(per_step) if not shifted[k] and not (k > 0 and shifted[k - 1])]
+    base = sorted(quiet)[len(quiet) // 2] if quiet else None
+    regrid = {}
+    for k in range(steps):
+        if shifted[k] and base is not None:
+            regrid[f"timed step {k}"] = {"patches_shifted": shifted[k],
+                                         "extra_ms_shift": round(1e3 * (per_step[k] - base), 2),
+                                         "extra_ms_next_step_recapture": round(1e3 * (per_step[k + 1] - base), 2)
+                                         if k + 1 < steps else None}
     extra = {"full_domain_equivalent_value": 2 * upd * steps / sec} if equatorial else {}
     return {"value": upd * steps / sec, **extra, "unit": "zone-cycles/s", "ms_per_root_step": 1e3 * sec / steps,
-            "patches": len(pt), "depths": max(depth) + 1,
+            "ms_per_timed_root_step": [round(1e3 * t, 2) for t in per_step],
+            "ms_per_root_step_without_regrid": round(1e3 * base, 2) if base else None,
+            "regrids": regrid, "patches": len(pt), "depths": max(depth) + 1,
             "active_cells": sum(g.active for g, *_ in pt), "zone_updates_per_root_step": upd,
-            "punctures_start": xp.tolist(), "punctures_end": x.tolist(),
-            "moved": [q for q in range(len(pt)) if tuple(F[q]) != tuple(pt[q][1])], "finite": finite}
+            "punctures_start": xp.tolist(), "punctures_end": x.tolist(), "lag": lag, "finite": finite}
 
 
-def cpu_baseline(I):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload:
-    one RK4 step of the 128^3 puncture box (same data recipe), all host
-    threads."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(I, n=256):
+    """The float64 oracle, as it stands, on a bounded sample of the headline
+    workload (the n^3 two-puncture box): its right-hand side at every active
+    point of a few z-planes through the middle of the box (the same per-point
+    routine its full RK4 step runs on every point), at one thread and at all
+    host threads.  A zone cycle is four right-hand-side evaluations; the RK4
+    combination and the enforcement (pointwise, a few percent of the
+    oracle's work) are left out of the sample."""
+    import numpy as np
+
     import oracle
 
     oracle.build(force=False)
-    g, u, dt = I.config_punctures(128)
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    oracle.rk4(u, g.as_dict(), dt, 1, nthreads=nthreads)
-    t = time.perf_counter() - t0
-    return {"value": g.active / t, "unit": "zone-cycles/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"one RK4 step of the 128^3 two-puncture Sommerfeld box ({g.active} active cells), "
-                      f"{nthreads} OpenMP threads, {t:.1f} s"}
+    g, u, _ = I.config_punctures(n)
+    ng = g.ng
+    nall = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    runs = {}
+    for nth, planes in ((1, 8), (nall, 64)):
+        k0 = ng + n // 2 - planes // 2
+        K, J, X = np.meshgrid(np.arange(k0, k0 + planes), np.arange(ng, ng + n), np.arange(ng, ng + n), indexing="ij")
+        pts = np.stack([X.ravel(), J.ravel(), K.ravel()], axis=1).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.rhs_points(u, g.as_dict(), pts, nthreads=nth)
+        t = time.perf_counter() - t0
+        runs[nth] = {"value": len(pts) / t / 4.0, "threads": nth, "seconds": round(t, 2),
+                     "sample": f"RHS at all {len(pts)} active points of z-planes {k0}..{k0 + planes - 1}"}
+    top = runs[nall]
+    return {"value": top["value"], "unit": "zone-cycles/s", "cores": nall, "kind": "oracle",
+            "sample": f"{n}^3 two-puncture Sommerfeld box (the headline workload): {top['sample']} "
+                      f"on {nall} OpenMP threads ({top['seconds']} s); zone-cycles/s = RHS points/s / 4",
+            "one_thread": runs[1], "all_threads": top, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
 
 
 def main():
@@ -222,6 +299,8 @@ def main():
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--only", choices=["bbh_moving", "bbh_moving_equatorial"], default="",
                     help="run only this extra measurement and print its JSON")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="tuning cache file (JSON lines); empty string: time every shape, persist nothing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -246,29 +325,28 @@ def main():
     box = I.Box(g, u0, None, dt)
     params = z4c.default_params()
 
+    cache = args.tune_cache or None
+
     def run(box_list, params, tile_arg):
-        plan = z4c.Plan(box_list, params=params, tile=tile_arg)
+        """Tile from the caller, else the tuning cache (a miss tunes once and
+        records the result); the timed plan starts from the initial state."""
         if tile_arg is None:
-            best, table = plan.autotune(reps=2)
-            plan.close()
-            plan = z4c.Plan(box_list, params=params, tile=best)  # fresh state
+            best, source = z4c.autotune(box_list, params, tune_cache=cache)
+            torch.cuda.empty_cache()
         else:
-            best, table = tile_arg, []
+            best, source = tile_arg, "caller"
+        plan = z4c.Plan(box_list, params=params, tile=best)
         sec = timed_plan_steps(plan, args.steps, args.warmup, torch)
         finite = all(bool(torch.isfinite(x).all()) for x in plan.u)
         plan.close()
-        return sec, best, table, finite
+        torch.cuda.empty_cache()
+        return sec, best, source, finite
 
     tile = None
     if args.tile:
         v = [int(x) for x in args.tile.split(",")]
         tile = z4c.Tile(*v)
-    sec, best, table, finite = run([box], params, tile)
-    tune = []
-    for k, t in enumerate(z4c.tiles(params.precision)):
-        for pers in (0, 1):
-            if 2 * k + pers < len(table):
-                tune.append([t.bx, t.by, t.bz, t.waves, pers, round(table[2 * k + pers], 3)])
+    sec, best, tune_source, finite = run([box], params, tile)
     if not finite:
         raise RuntimeError("non-finite state after the timed steps")
     active = g.active
@@ -297,30 +375,32 @@ def main():
     if not args.no_extras:
         # the same puncture data on the 128^3 box (dx = 0.25), same tile
         g2, u2, dt2 = I.config_punctures(128)
-        sec2, _, _, fin2 = run([I.Box(g2, u2, None, dt2)], params, best)
+        g2, u2, dt2 = I.config_punctures(128)
+        sec2, best2, src2, fin2 = run([I.Box(g2, u2, None, dt2)], params, None)
         extras["box128"] = {"value": g2.active * args.steps / sec2, "ms_per_step": 1e3 * sec2 / args.steps,
-                            "tile": list(best.as_tuple()), "finite": fin2}
+                            "tile": list(best2.as_tuple()), "tune_source": src2, "finite": fin2}
         del u2
         pm = z4c.default_params(precision=z4c.MIXED)
-        sec_m, best_m, _, fin_m = run([box], pm, None)
+        sec_m, best_m, src_m, fin_m = run([box], pm, None)
         extras["mixed"] = {"value": active * args.steps / sec_m, "ms_per_step": 1e3 * sec_m / args.steps,
-                           "tile": list(best_m.as_tuple()), "finite": fin_m}
+                           "tile": list(best_m.as_tuple()), "tune_source": src_m, "finite": fin_m}
         ge, ue, dte = I.config_punctures_equatorial(args.n)
-        sec_e, best_e, _, fin_e = run([I.Box(ge, ue, None, dte)], params, None)
+        sec_e, best_e, src_e, fin_e = run([I.Box(ge, ue, None, dte)], params, None)
         extras["equatorial"] = {"value": ge.active * args.steps / sec_e, "ms_per_step": 1e3 * sec_e / args.steps,
                                 "active_cells": ge.active, "full_box_equivalent_value":
                                     2 * ge.active * args.steps / sec_e,
-                                "tile": list(best_e.as_tuple()), "finite": fin_e}
+                                "tile": list(best_e.as_tuple()), "tune_source": src_e, "finite": fin_e}
         boxes = I.config_hierarchy()
         act_h = sum(b.grid.active for b in boxes)
-        sec_h, best_h, _, fin_h = run(boxes, params, None)
+        sec_h, best_h, src_h, fin_h = run(boxes, params, None)
         extras["hierarchy9"] = {"value": act_h * args.steps / sec_h, "ms_per_step": 1e3 * sec_h / args.steps,
-                                "active_cells": act_h, "tile": list(best_h.as_tuple()), "finite": fin_h}
+                                "active_cells": act_h, "tile": list(best_h.as_tuple()), "tune_source": src_h,
+                                "finite": fin_h}
         extras["bbh_moving"] = bbh_moving_rate(z4c, I, torch)
         extras["bbh_moving_equatorial"] = bbh_moving_rate(z4c, I, torch, equatorial=True)
-        sec_hm, best_hm, _, fin_hm = run(boxes, pm, None)
+        sec_hm, best_hm, src_hm, fin_hm = run(boxes, pm, None)
         extras["hierarchy9_mixed"] = {"value": act_h * args.steps / sec_hm, "ms_per_step": 1e3 * sec_hm / args.steps,
-                                      "tile": list(best_hm.as_tuple()), "finite": fin_hm,
+                                      "tile": list(best_hm.as_tuple()), "tune_source": src_hm, "finite": fin_hm,
                                       "error_after_50_steps": mixed_hierarchy_error(z4c, I, torch, boxes)}
 
     out = {
@@ -331,7 +411,7 @@ def main():
         "config": {"workload": f"single {args.n}^3 box + 3 ghosts, two Brill-Lindquist punctures (m=0.5 each, "
                                f"separation 10), alpha=W, Sommerfeld outer boundary, dx={g.h[0]}, FP64, "
                                f"RK4 steps of dt=0.5dx", "tile": list(best.as_tuple()),
-                   "autotune_ms_per_step": tune,
+                   "tune_source": tune_source, "tune_cache": os.path.relpath(cache, ROOT) if cache else None,
                    "zone_substeps_per_s": 4 * value},
         "roofline": roof,
         "extras": extras,

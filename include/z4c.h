@@ -34,9 +34,11 @@
  * next synchronisation or as Z4C_EHIP from a later call.
  * Errors.  Arguments are validated on the host before anything is enqueued;
  * an invalid call returns a negative z4c_status, enqueues nothing and leaves
- * a description in z4c_last_error().  Only the plan and hierarchy APIs
- * allocate (at creation, and z4c_hier_set_moving).  No entry point
- * synchronises the device except the hierarchy's puncture read-back
+ * a description in z4c_last_error().  Only the plan, tuning and hierarchy
+ * APIs allocate (at creation, z4c_autotune's temporary plan, and
+ * z4c_hier_set_moving).  No entry point synchronises the device except the
+ * autotuners while they time (z4c_autotune on a cache miss,
+ * z4c_plan_autotune) and the hierarchy's puncture read-back
  * (z4c_hier_advance with moving patches, z4c_hier_puncture).
  * Threads.  The single-box entry points are stateless and thread safe; a
  * plan or a hierarchy must not be used from two threads at once.
@@ -149,6 +151,7 @@ long z4c_constraints_workspace(int nx, int ny, int nz);
 int z4c_constraints(const double* u, double* c, double* norms, double* ws, long ws_len, long sf, int nx, int ny,
                     int nz, int ng, double dx, double dy, double dz, void* stream);
 
+
 /* ---------------------------------------------------------------------- */
 /* Batched form: every box of a hierarchy (Sec. 2.2.1 box-in-box levels)  */
 /* in one persistent launch per substep, captured once as a HIP graph.    */
@@ -192,11 +195,29 @@ int z4c_tile_get(int precision, int index, z4c_tile* out);
  * compiled. */
 int z4c_select_tile(int precision, const z4c_tile* tile);
 
+/* Where a plan's tile shape came from (z4c_plan_tile, z4c_autotune). */
+typedef enum {
+    Z4C_TILE_DEFAULT = 0, /* the library default (8x8x8 bricks, two waves per SIMD, persistent) */
+    Z4C_TILE_CALLER = 1,  /* the tile argument of z4c_plan_create */
+    Z4C_TILE_CACHE = 2,   /* an entry of the tuning cache */
+    Z4C_TILE_TUNED = 3    /* timed by z4c_autotune / z4c_plan_autotune in this process */
+} z4c_tile_source;
+
 /* Create a plan over nbox boxes (1 <= nbox <= 16, largest first is best).
- * tile == NULL selects the library default shape for p->precision with a
- * persistent launch.  Allocates only host memory.  *plan receives an opaque
+ * The tile shape: `tile` if not NULL; else the entry of the tuning cache
+ * `tune_cache_path` (see z4c_autotune) for this device, precision, box count
+ * and workload bucket, if there is one and its shape is compiled; else the
+ * library default shape for p->precision with a persistent launch.  A
+ * missing cache file is an empty cache; an unreadable or corrupt one fails
+ * with Z4C_EINVAL.  Allocates only host memory; queries the current device's
+ * architecture when the cache holds entries.  *plan receives an opaque
  * handle. */
-int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z4c_tile* tile, void** plan);
+int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z4c_tile* tile,
+                    const char* tune_cache_path, void** plan);
+
+/* The tile shape (with its persistent flag) a plan launches and where it came
+ * from (z4c_tile_source); either output may be NULL. */
+int z4c_plan_tile(void* plan, z4c_tile* tile, int* source);
 
 /* Advance every box by nsteps RK4 steps on `stream`: per step, four
  * substeps, each one ghost-fill launch and one fused launch over all
@@ -213,6 +234,33 @@ int z4c_plan_step(void* plan, int nsteps, int use_graph, void* stream);
 int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float* ms);
 
 int z4c_plan_destroy(void* plan);
+
+/* The project's autotuner with a persisted cache (box-in-box batching of
+ * Sec. 2.2.1 run as one launch per substep; the tile is the LDS brick of the
+ * stencil staging).  Looks up (device architecture, p->precision, nbox,
+ * bucket = floor(log2(total active cells))) in tune_cache_path; on a hit
+ * returns the cached shape without running anything (*source =
+ * Z4C_TILE_CACHE).  On a miss it builds a temporary plan over the boxes, times
+ * one RK4 step for every compiled shape, persistent and not (median of 2
+ * after a warm-up step, HIP events on `stream`), writes the fastest to the
+ * cache (replacing the key's entry, file rewritten through a temporary file
+ * and a rename) and returns it (*source = Z4C_TILE_TUNED).  The trial steps
+ * advance the boxes' state: callers reset it afterwards.  tune_cache_path ==
+ * NULL times without persisting.  The cache is a text file of JSON lines,
+ *   {"arch": "gfx950", "precision": 0, "nbox": 1, "bucket": 24, "tile": [8, 8, 8, 2, 1], "ms": 29.4}
+ * one per key; a line that is not such an entry makes the file corrupt
+ * (Z4C_EINVAL, nothing timed, the file left as it is).  best and source may be
+ * NULL.  Synchronises on `stream` when it times. */
+int z4c_autotune(const z4c_box* boxes, int nbox, const z4c_params* p, const char* tune_cache_path, void* stream,
+                 z4c_tile* best, int* source);
+
+/* Host-only cache query: the cached shape for architecture `arch` (e.g.
+ * "gfx950"), precision, and the box count and bucket of `boxes` (only their
+ * extents n are read).  Returns 1 and fills *tile on a hit, 0 on a miss (also
+ * for a missing file or a shape this build does not compile), Z4C_EINVAL for
+ * a corrupt file or invalid arguments.  Makes no HIP call. */
+int z4c_tune_lookup(const char* tune_cache_path, const char* arch, const z4c_box* boxes, int nbox, int precision,
+                    z4c_tile* tile);
 
 /* ---------------------------------------------------------------------- */
 /* Box-in-box hierarchy with Berger-Oliger time subcycling (Sec. 2.2.1,   */

@@ -173,6 +173,202 @@ void finalize_set(BoxSet& s, const z4c_tile& t)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persisted tile tuning.  The cache is a text file of JSON lines, one object
+// per (device architecture, precision, box count, workload bucket):
+//   {"arch": "gfx950", "precision": 0, "nbox": 1, "bucket": 24, "tile": [8, 8, 8, 2, 1], "ms": 29.4}
+// bucket = floor(log2(total active cells)).  Reading is strict: any line that
+// is not such an object makes the whole file corrupt (Z4C_EINVAL), so that a
+// damaged cache is reported instead of silently ignored.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    std::string arch;
+    int precision = -1, nbox = -1, bucket = -1;
+    z4c_tile tile{};
+    double ms = 0.0;
+};
+
+struct LineParser {
+    const char* p;
+    void ws()
+    {
+        while (*p == ' ' || *p == '\t' || *p == '\r') ++p;
+    }
+    bool lit(char c)
+    {
+        ws();
+        if (*p != c) return false;
+        ++p;
+        return true;
+    }
+    bool str(std::string& out)
+    {
+        ws();
+        if (*p != '"') return false;
+        ++p;
+        out.clear();
+        while (*p && *p != '"') {
+            const char c = *p++;
+            const bool ok = (c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z') || (c >= '0' && c <= '9') || c == '_' ||
+                            c == '-' || c == '+' || c == ':' || c == '.';
+            if (!ok || out.size() > 64) return false;
+            out.push_back(c);
+        }
+        if (*p != '"') return false;
+        ++p;
+        return true;
+    }
+    bool integer(int& v)
+    {
+        ws();
+        char* e = nullptr;
+        const long x = std::strtol(p, &e, 10);
+        if (e == p || x < -1000000 || x > 1000000) return false;
+        p = e;
+        v = (int)x;
+        return true;
+    }
+    bool number(double& v)
+    {
+        ws();
+        char* e = nullptr;
+        v = std::strtod(p, &e);
+        if (e == p || !std::isfinite(v)) return false;
+        p = e;
+        return true;
+    }
+};
+
+// parse one line into e; false if it is not a complete entry
+bool tune_parse_line(const char* line, TuneEntry& e)
+{
+    LineParser L{line};
+    if (!L.lit('{')) return false;
+    bool has_arch = false, has_prec = false, has_nbox = false, has_bucket = false, has_tile = false;
+    for (bool first = true;; first = false) {
+        if (L.lit('}')) break;
+        if (!first && !L.lit(',')) return false;
+        std::string key;
+        if (!L.str(key) || !L.lit(':')) return false;
+        if (key == "arch" && !has_arch) {
+            if (!(has_arch = L.str(e.arch))) return false;
+        } else if (key == "precision" && !has_prec) {
+            if (!(has_prec = L.integer(e.precision))) return false;
+        } else if (key == "nbox" && !has_nbox) {
+            if (!(has_nbox = L.integer(e.nbox))) return false;
+        } else if (key == "bucket" && !has_bucket) {
+            if (!(has_bucket = L.integer(e.bucket))) return false;
+        } else if (key == "ms") {
+            if (!L.number(e.ms)) return false;
+        } else if (key == "tile" && !has_tile) {
+            int v[5];
+            if (!L.lit('[')) return false;
+            for (int i = 0; i < 5; ++i)
+                if ((i > 0 && !L.lit(',')) || !L.integer(v[i])) return false;
+            if (!L.lit(']')) return false;
+            e.tile = z4c_tile{v[0], v[1], v[2], v[3], v[4]};
+            has_tile = true;
+        } else
+            return false;
+    }
+    L.ws();
+    if (*L.p != '\0' && *L.p != '\n') return false;
+    return has_arch && has_prec && has_nbox && has_bucket && has_tile && !e.arch.empty() &&
+           (e.precision == Z4C_FP64 || e.precision == Z4C_MIXED) && e.nbox >= 1 && e.nbox <= MAXBOX &&
+           e.bucket >= 0 && e.bucket < 64 && (e.tile.persistent == 0 || e.tile.persistent == 1);
+}
+
+// Read every entry of the cache.  A missing file is an empty cache.
+int tune_read(const char* path, std::vector<TuneEntry>& out)
+{
+    out.clear();
+    FILE* f = std::fopen(path, "r");
+    if (!f) return Z4C_OK;
+    char line[1024];
+    int no = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        ++no;
+        const size_t len = std::strlen(line);
+        if (len + 1 == sizeof line && line[len - 1] != '\n') {
+            std::fclose(f);
+            return fail(Z4C_EINVAL, std::string("tune cache ") + path + ": line " + std::to_string(no) + " too long");
+        }
+        const char* q = line;
+        while (*q == ' ' || *q == '\t' || *q == '\r' || *q == '\n') ++q;
+        if (*q == '\0') continue;  // blank line
+        TuneEntry e;
+        if (!tune_parse_line(line, e)) {
+            std::fclose(f);
+            return fail(Z4C_EINVAL, std::string("tune cache ") + path + ": line " + std::to_string(no) +
+                                        " is not a tuning entry");
+        }
+        out.push_back(e);
+    }
+    std::fclose(f);
+    return Z4C_OK;
+}
+
+const TuneEntry* tune_find(const std::vector<TuneEntry>& v, const std::string& arch, int precision, int nbox,
+                           int bucket)
+{
+    for (const TuneEntry& e : v)
+        if (e.arch == arch && e.precision == precision && e.nbox == nbox && e.bucket == bucket) return &e;
+    return nullptr;
+}
+
+// Replace (or add) the entry of e's key and rewrite the file atomically.
+int tune_write(const char* path, const TuneEntry& e)
+{
+    std::vector<TuneEntry> v;
+    int rc = tune_read(path, v);
+    if (rc) return rc;
+    bool done = false;
+    for (TuneEntry& x : v)
+        if (x.arch == e.arch && x.precision == e.precision && x.nbox == e.nbox && x.bucket == e.bucket) {
+            x = e;
+            done = true;
+        }
+    if (!done) v.push_back(e);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(Z4C_EINVAL, "cannot write tune cache " + tmp);
+    for (const TuneEntry& x : v)
+        std::fprintf(f, "{\"arch\": \"%s\", \"precision\": %d, \"nbox\": %d, \"bucket\": %d, "
+                        "\"tile\": [%d, %d, %d, %d, %d], \"ms\": %.4f}\n",
+                     x.arch.c_str(), x.precision, x.nbox, x.bucket, x.tile.bx, x.tile.by, x.tile.bz, x.tile.waves,
+                     x.tile.persistent, x.ms);
+    const bool ok = std::fflush(f) == 0;
+    std::fclose(f);
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(Z4C_EINVAL, std::string("cannot write tune cache ") + path);
+    }
+    return Z4C_OK;
+}
+
+// architecture name of the current device without feature suffixes ("gfx950")
+int device_arch(std::string& arch)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "device architecture query");
+    arch = prop.gcnArchName;
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch.resize(c);
+    return Z4C_OK;
+}
+
+int cells_bucket(const z4c_box* boxes, int nbox)
+{
+    double cells = 0.0;
+    for (int b = 0; b < nbox; ++b) cells += (double)boxes[b].n[0] * boxes[b].n[1] * boxes[b].n[2];
+    int k = 0;
+    while (k < 62 && std::ldexp(1.0, k + 1) <= cells) ++k;
+    return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -360,6 +556,34 @@ long z4c_constraints_workspace(int nx, int ny, int nz)
     return 4 * constraint_blocks(n);
 }
 
+// Overlap checks and launch of the constraint monitor; own_ws: ws is not
+// caller memory, so its overlap with the arguments needs no check.
+static int constraints_impl(const double* u, double* c, double* norms, double* ws, bool own_ws, long sf, int nx,
+                            int ny, int nz, int ng, double dx, double dy, double dz, void* stream, const char* where)
+{
+    auto span = [](const void* p, uintptr_t bytes, const void* q, uintptr_t qbytes) {
+        const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+        return a < b + qbytes && b < a + bytes;
+    };
+    const long need = z4c_constraints_workspace(nx, ny, nz);
+    const uintptr_t ub = (uintptr_t)sf * NF * 8, cb = (uintptr_t)sf * 4 * 8, wb = (uintptr_t)need * 8;
+    if (c && span(c, cb, u, ub)) return fail(Z4C_EINVAL, "c overlaps u");
+    if (!own_ws && (span(ws, wb, u, ub) || (c && span(ws, wb, c, cb)) || span(ws, wb, norms, 32)))
+        return fail(Z4C_EINVAL, "ws overlaps another argument");
+    if (span(norms, 32, u, ub) || (c && span(norms, 32, c, cb))) return fail(Z4C_EINVAL, "norms overlaps another argument");
+    const int n[3] = {nx, ny, nz};
+    const double h[3] = {dx, dy, dz}, o[3] = {0, 0, 0};
+    BoxSet set{};
+    set.nbox = 1;
+    set.box[0] = make_box(n, ng, Z4C_BC_PERIODIC, sf, h, o, 1.0);
+    set.box[0].u_in = u;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, (std::string("pending HIP error before ") + where).c_str());
+    if ((e = launch_constraints(set, c, norms, ws, (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, (std::string(where) + " launch").c_str());
+    return Z4C_OK;
+}
+
 int z4c_constraints(const double* u, double* c, double* norms, double* ws, long ws_len, long sf, int nx, int ny,
                     int nz, int ng, double dx, double dy, double dz, void* stream)
 {
@@ -371,26 +595,7 @@ int z4c_constraints(const double* u, double* c, double* norms, double* ws, long 
     if (!u || !norms || !ws) return fail(Z4C_EINVAL, "u, norms and ws must be non-NULL");
     const long need = z4c_constraints_workspace(nx, ny, nz);
     if (ws_len < need) return fail(Z4C_EINVAL, "workspace too small: need " + std::to_string(need) + " doubles");
-    auto span = [](const void* p, uintptr_t bytes, const void* q, uintptr_t qbytes) {
-        const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
-        return a < b + qbytes && b < a + bytes;
-    };
-    const uintptr_t ub = (uintptr_t)sf * NF * 8, cb = (uintptr_t)sf * 4 * 8, wb = (uintptr_t)need * 8;
-    if (c && span(c, cb, u, ub)) return fail(Z4C_EINVAL, "c overlaps u");
-    if (span(ws, wb, u, ub) || (c && span(ws, wb, c, cb)) || span(ws, wb, norms, 32))
-        return fail(Z4C_EINVAL, "ws overlaps another argument");
-    if (span(norms, 32, u, ub) || (c && span(norms, 32, c, cb))) return fail(Z4C_EINVAL, "norms overlaps another argument");
-    const int n[3] = {nx, ny, nz};
-    const double h[3] = {dx, dy, dz}, o[3] = {0, 0, 0};
-    BoxSet set{};
-    set.nbox = 1;
-    set.box[0] = make_box(n, ng, Z4C_BC_PERIODIC, sf, h, o, 1.0);
-    set.box[0].u_in = u;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "pending HIP error before z4c_constraints");
-    if ((e = launch_constraints(set, c, norms, ws, (hipStream_t)stream)) != hipSuccess)
-        return hip_fail(e, "z4c_constraints launch");
-    return Z4C_OK;
+    return constraints_impl(u, c, norms, ws, false, sf, nx, ny, nz, ng, dx, dy, dz, stream, "z4c_constraints");
 }
 
 // ---------------------------------------------------------------------------
@@ -402,6 +607,7 @@ struct z4c_plan_s {
     int precision;
     int tile_index;
     int persistent;    // grid capped at the resident-block count, bricks walked in a loop
+    int tile_source;   // Z4C_TILE_DEFAULT / CALLER / CACHE / TUNED
     BoxSet fused[4];   // per stage
     BoxSet ghosts[4];  // per stage: fill of the stage input
     bool any_ghost_fill, any_sommerfeld;
@@ -463,12 +669,10 @@ static hipError_t plan_enqueue_step(z4c_plan_s* P, hipStream_t s)
     return hipSuccess;
 }
 
-int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z4c_tile* tile, void** plan)
+// Validation of a box list shared by z4c_plan_create and z4c_autotune.
+static int check_boxes(const z4c_box* boxes, int nbox)
 {
     int rc;
-    if (!plan) return fail(Z4C_EINVAL, "plan is NULL");
-    *plan = nullptr;
-    if ((rc = check_params(p))) return rc;
     if (!boxes || nbox < 1 || nbox > MAXBOX) return fail(Z4C_EINVAL, "need 1..16 boxes");
     for (int b = 0; b < nbox; ++b) {
         const z4c_box& x = boxes[b];
@@ -486,7 +690,36 @@ int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z
         if (x.bc == Z4C_BC_COPY && !x.shell) return fail(Z4C_EINVAL, tag + "copy box needs a shell");
         if (x.bc != Z4C_BC_COPY && x.shell) return fail(Z4C_EINVAL, tag + "shell must be NULL");
     }
-    int ti = tile ? find_tile(p->precision, tile) : default_tile_index(p->precision);
+    return Z4C_OK;
+}
+
+int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z4c_tile* tile,
+                    const char* tune_cache_path, void** plan)
+{
+    int rc;
+    if (!plan) return fail(Z4C_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if ((rc = check_params(p))) return rc;
+    if ((rc = check_boxes(boxes, nbox))) return rc;
+    z4c_tile chosen{};
+    int source = Z4C_TILE_DEFAULT;
+    if (tile) {
+        chosen = *tile;
+        source = Z4C_TILE_CALLER;
+    } else if (tune_cache_path) {
+        std::vector<TuneEntry> entries;
+        if ((rc = tune_read(tune_cache_path, entries))) return rc;
+        if (!entries.empty()) {  // a hit needs the device's architecture (the only HIP query here)
+            std::string arch;
+            if ((rc = device_arch(arch))) return rc;
+            const TuneEntry* hit = tune_find(entries, arch, p->precision, nbox, cells_bucket(boxes, nbox));
+            if (hit && find_tile(p->precision, &hit->tile) >= 0) {
+                chosen = hit->tile;
+                source = Z4C_TILE_CACHE;
+            }
+        }
+    }
+    int ti = source != Z4C_TILE_DEFAULT ? find_tile(p->precision, &chosen) : default_tile_index(p->precision);
     if (ti < 0) return fail(Z4C_EUNSUPPORTED, "no compiled tile of that shape for this precision");
     z4c_plan_s* P = new (std::nothrow) z4c_plan_s();
     if (!P) return fail(Z4C_ENOMEM, "plan allocation failed");
@@ -494,7 +727,8 @@ int z4c_plan_create(const z4c_box* boxes, int nbox, const z4c_params* p, const z
     P->prm = to_dev(p);
     P->precision = p->precision;
     P->tile_index = ti;
-    P->persistent = tile ? (tile->persistent ? 1 : 0) : 1;
+    P->persistent = source != Z4C_TILE_DEFAULT ? (chosen.persistent ? 1 : 0) : 1;
+    P->tile_source = source;
     P->any_ghost_fill = P->any_sommerfeld = false;
     for (const z4c_box& x : P->boxes) {
         P->any_ghost_fill |= x.bc != Z4C_BC_SOMMERFELD;
@@ -552,7 +786,7 @@ int z4c_plan_step(void* plan, int nsteps, int use_graph, void* stream)
     return Z4C_OK;
 }
 
-int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float* ms)
+static int plan_autotune_impl(void* plan, int reps, void* stream, z4c_tile* best, float* ms, float* best_ms_out)
 {
     if (!plan) return fail(Z4C_EINVAL, "plan is NULL");
     if (reps < 1 || reps > 1000) return fail(Z4C_EINVAL, "reps must be 1..1000");
@@ -610,12 +844,91 @@ int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float*
     (void)hipEventDestroy(b);
     P->tile_index = best_i;
     P->persistent = best_p;
+    P->tile_source = Z4C_TILE_TUNED;
     plan_drop_graph(P);
     plan_build_sets(P);
+    if (best_ms_out) *best_ms_out = best_ms;
     if (best) {
         *best = tab[best_i].tile;
         best->persistent = best_p;
     }
+    return Z4C_OK;
+}
+
+int z4c_plan_autotune(void* plan, int reps, void* stream, z4c_tile* best, float* ms)
+{
+    return plan_autotune_impl(plan, reps, stream, best, ms, nullptr);
+}
+
+int z4c_plan_tile(void* plan, z4c_tile* tile, int* source)
+{
+    if (!plan) return fail(Z4C_EINVAL, "plan is NULL");
+    const z4c_plan_s* P = (const z4c_plan_s*)plan;
+    const TileEntry* tab = nullptr;
+    tile_table(&tab);
+    if (tile) {
+        *tile = tab[P->tile_index].tile;
+        tile->persistent = P->persistent;
+    }
+    if (source) *source = P->tile_source;
+    return Z4C_OK;
+}
+
+int z4c_tune_lookup(const char* tune_cache_path, const char* arch, const z4c_box* boxes, int nbox, int precision,
+                    z4c_tile* tile)
+{
+    int rc;
+    if (!tune_cache_path || !arch || !tile) return fail(Z4C_EINVAL, "tune_cache_path, arch and tile must be non-NULL");
+    if (precision != Z4C_FP64 && precision != Z4C_MIXED) return fail(Z4C_EINVAL, "unknown precision");
+    if (!boxes || nbox < 1 || nbox > MAXBOX) return fail(Z4C_EINVAL, "need 1..16 boxes");
+    for (int b = 0; b < nbox; ++b)
+        if (boxes[b].n[0] < 1 || boxes[b].n[1] < 1 || boxes[b].n[2] < 1)
+            return fail(Z4C_EINVAL, "active extents must be >= 1");
+    std::vector<TuneEntry> v;
+    if ((rc = tune_read(tune_cache_path, v))) return rc;
+    const TuneEntry* e = tune_find(v, arch, precision, nbox, cells_bucket(boxes, nbox));
+    if (!e || find_tile(precision, &e->tile) < 0) return 0;
+    *tile = e->tile;
+    return 1;
+}
+
+int z4c_autotune(const z4c_box* boxes, int nbox, const z4c_params* p, const char* tune_cache_path, void* stream,
+                 z4c_tile* best, int* source)
+{
+    int rc;
+    if ((rc = check_params(p))) return rc;
+    if ((rc = check_boxes(boxes, nbox))) return rc;
+    std::vector<TuneEntry> entries;
+    if (tune_cache_path && (rc = tune_read(tune_cache_path, entries))) return rc;
+    std::string arch;
+    if ((rc = device_arch(arch))) return rc;
+    const int bucket = cells_bucket(boxes, nbox);
+    const TuneEntry* hit = tune_find(entries, arch, p->precision, nbox, bucket);
+    if (hit && find_tile(p->precision, &hit->tile) >= 0) {
+        if (best) *best = hit->tile;
+        if (source) *source = Z4C_TILE_CACHE;
+        return Z4C_OK;
+    }
+    void* plan = nullptr;
+    if ((rc = z4c_plan_create(boxes, nbox, p, nullptr, nullptr, &plan))) return rc;
+    z4c_tile t{};
+    float ms = 0.0f;
+    rc = plan_autotune_impl(plan, 2, stream, &t, nullptr, &ms);
+    const std::string err = g_last_error;
+    z4c_plan_destroy(plan);
+    if (rc) return fail(rc, err);
+    if (tune_cache_path) {
+        TuneEntry e;
+        e.arch = arch;
+        e.precision = p->precision;
+        e.nbox = nbox;
+        e.bucket = bucket;
+        e.tile = t;
+        e.ms = ms;
+        if ((rc = tune_write(tune_cache_path, e))) return rc;
+    }
+    if (best) *best = t;
+    if (source) *source = Z4C_TILE_TUNED;
     return Z4C_OK;
 }
 

@@ -335,20 +335,25 @@ def upper_half_patches(patches, states):
     return out_p, out_s
 
 
-def config_bbh_moving(root_n=128, h0=2.0, fixed=(128, 128, 128), moving=(64, 64, 64), sep=10.0, equatorial=False):
+def config_bbh_moving(root_n=128, h0=2.0, fixed=(128, 128, 128), moving=(64, 64, 64), sep=10.0, equatorial=False,
+                      lag=0.0):
     """The binary-black-hole layout of Sec. 2.2.1 (Fig. 1): a Sommerfeld
     root of root_n^3 cells (spacing h0) and fixed levels centred on the
-    origin, then moving levels with one patch per puncture, on two
-    Brill-Lindquist punctures (m = 0.5 each at x = +-sep/2), alpha = W.
-    equatorial: only the upper half (z > 0), every patch on the symmetry
-    plane.  Returns (patches [(grid, F, parent, obj)], states, root step
-    dt0 = 0.5 h0, puncture positions (2, 3))."""
+    origin, then moving levels with one patch per puncture, centred on
+    x = +-sep/2, on two Brill-Lindquist punctures (m = 0.5 each), alpha = W.
+    The punctures sit at x = +-(sep/2 - lag): lag > 0 puts them that far
+    inside their patches' centres, as between two regrids of a running
+    evolution.  equatorial: only the upper half (z > 0), every patch on the
+    symmetry plane.  Returns (patches [(grid, F, parent, obj)], states, root
+    step dt0 = 0.5 h0, puncture positions (2, 3))."""
     centers = [(-0.5 * sep, 0.0, 0.0), (0.5 * sep, 0.0, 0.0)]
+    a = 0.5 * sep - lag
+    punct = ((a, 0.0, 0.0), (-a, 0.0, 0.0))  # the +x puncture first: the pair's sum is mirror-safe
     pt = pair_hierarchy(root_n, h0, centers, moving, fixed, bc0=BC_SOMMERFELD)
-    states = [brill_lindquist_state(g) for g, *_ in pt]
+    states = [brill_lindquist_state(g, centres=punct) for g, *_ in pt]
     if equatorial:
         pt, states = upper_half_patches(pt, [z_symmetrize(u) for u in states])
-    return pt, states, 0.5 * h0, np.array(centers)
+    return pt, states, 0.5 * h0, np.array([(-a, 0.0, 0.0), (a, 0.0, 0.0)])
 
 
 def config_bo_hierarchy(nlev=6, n=64, h0=4.0):

@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "z4c.h")
 
 NF = 25
 OK, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4
+TILE_DEFAULT, TILE_CALLER, TILE_CACHE, TILE_TUNED = 0, 1, 2, 3
+TILE_SOURCE_NAMES = {TILE_DEFAULT: "default", TILE_CALLER: "caller", TILE_CACHE: "cache", TILE_TUNED: "tuned"}
 BC_PERIODIC, BC_SOMMERFELD, BC_COPY, BC_EQUATORIAL = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 
@@ -90,7 +92,13 @@ def lib(path: str = LIB_PATH):
     L.z4c_tile_count.argtypes = [i]
     L.z4c_tile_get.argtypes = [i, i, ctypes.POINTER(Tile)]
     L.z4c_select_tile.argtypes = [i, ctypes.POINTER(Tile)]
-    L.z4c_plan_create.argtypes = [ctypes.POINTER(Box), i, pp, ctypes.POINTER(Tile), ctypes.POINTER(vp)]
+    L.z4c_plan_create.argtypes = [ctypes.POINTER(Box), i, pp, ctypes.POINTER(Tile), ctypes.c_char_p,
+                                  ctypes.POINTER(vp)]
+    L.z4c_plan_tile.argtypes = [vp, ctypes.POINTER(Tile), ctypes.POINTER(i)]
+    L.z4c_autotune.argtypes = [ctypes.POINTER(Box), i, pp, ctypes.c_char_p, vp, ctypes.POINTER(Tile),
+                               ctypes.POINTER(i)]
+    L.z4c_tune_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Box), i, i,
+                                  ctypes.POINTER(Tile)]
     L.z4c_plan_step.argtypes = [vp, i, i, vp]
     L.z4c_plan_autotune.argtypes = [vp, i, vp, ctypes.POINTER(Tile), ctypes.POINTER(ctypes.c_float)]
     L.z4c_plan_destroy.argtypes = [vp]
@@ -109,6 +117,7 @@ def lib(path: str = LIB_PATH):
     L.z4c_last_error.restype = ctypes.c_char_p
     for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
                  "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints",
+                 "z4c_plan_tile", "z4c_autotune", "z4c_tune_lookup",
                  "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy", "z4c_hier_set_moving", "z4c_hier_puncture"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -254,37 +263,81 @@ class Stepper:
         apply_ghosts(self.u, self.g, self.shell, stream)
 
 
+def _device_boxes(boxes, device):
+    """Device arrays (state copied in, three scratch arrays, shell) and the
+    z4c_box array of a list of inputs.Box."""
+    import torch
+    us, keep, cboxes = [], [], []
+    for bx in boxes:
+        g = bx.grid
+        u = torch.as_tensor(bx.state, dtype=torch.float64, device=device).contiguous().clone()
+        a, b, acc = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
+        sh = None if bx.shell is None else torch.as_tensor(bx.shell, dtype=torch.float64, device=device).contiguous()
+        us.append(u)
+        keep.append((a, b, acc, sh))
+        c = Box()
+        c.n[:] = [int(v) for v in g.n]
+        c.ng, c.bc, c.sf = int(g.ng), int(g.bc), int(g.stored)
+        c.dx[:] = [float(v) for v in g.h]
+        c.x0[:] = [float(v) for v in g.x0]
+        c.dt = float(bx.dt)
+        c.u_n, c.u_a, c.u_b, c.acc = u.data_ptr(), a.data_ptr(), b.data_ptr(), acc.data_ptr()
+        c.shell = None if sh is None else sh.data_ptr()
+        cboxes.append(c)
+    return us, keep, (Box * len(cboxes))(*cboxes)
+
+
+def _path(p):
+    return None if p is None else os.fsencode(p)
+
+
+def autotune(boxes, params: Params = None, tune_cache=None, stream=None, device="cuda"):
+    """z4c_autotune over copies of the boxes: (tile, source name).  A cache
+    hit returns the cached shape without running anything; a miss times every
+    compiled shape and, with tune_cache set, persists the fastest."""
+    p = params or default_params()
+    us, keep, cb = _device_boxes(boxes, device)
+    best, src = Tile(), ctypes.c_int()
+    check(lib().z4c_autotune(cb, len(boxes), ctypes.byref(p), _path(tune_cache), _stream(stream), ctypes.byref(best),
+                             ctypes.byref(src)), "z4c_autotune")
+    del us, keep
+    return best, TILE_SOURCE_NAMES[src.value]
+
+
+def tune_lookup(tune_cache, arch: str, grids, precision: int = FP64):
+    """Host-only query of the tuning cache: the cached Tile for boxes of
+    these grids (extents only) on `arch`, or None on a miss."""
+    cb = (Box * len(grids))()
+    for c, g in zip(cb, grids):
+        c.n[:] = [int(v) for v in g.n]
+    t = Tile()
+    rc = lib().z4c_tune_lookup(_path(tune_cache), arch.encode(), cb, len(grids), int(precision), ctypes.byref(t))
+    if rc < 0:
+        check(rc, "z4c_tune_lookup")
+    return t if rc == 1 else None
+
+
 class Plan:
     """Batched form: every box in one fused launch per substep, one RK4 step
-    captured as a HIP graph and replayed.  Owns the per-box device arrays."""
+    captured as a HIP graph and replayed.  Owns the per-box device arrays.
+    tile: the shape to launch; else the tuning cache tune_cache's entry for
+    this workload, else the library default."""
 
-    def __init__(self, boxes, params: Params = None, tile: Tile = None, device="cuda"):
-        import torch
+    def __init__(self, boxes, params: Params = None, tile: Tile = None, device="cuda", tune_cache=None):
         self.params = params or default_params()
         self.boxes = list(boxes)
-        self.u, self._keep, cboxes = [], [], []
-        for bx in self.boxes:
-            g = bx.grid
-            u = torch.as_tensor(bx.state, dtype=torch.float64, device=device).contiguous().clone()
-            a, b, acc = torch.empty_like(u), torch.empty_like(u), torch.empty_like(u)
-            sh = None if bx.shell is None else torch.as_tensor(bx.shell, dtype=torch.float64,
-                                                               device=device).contiguous()
-            self.u.append(u)
-            self._keep.append((a, b, acc, sh))
-            c = Box()
-            c.n[:] = [int(v) for v in g.n]
-            c.ng, c.bc, c.sf = int(g.ng), int(g.bc), int(g.stored)
-            c.dx[:] = [float(v) for v in g.h]
-            c.x0[:] = [float(v) for v in g.x0]
-            c.dt = float(bx.dt)
-            c.u_n, c.u_a, c.u_b, c.acc = u.data_ptr(), a.data_ptr(), b.data_ptr(), acc.data_ptr()
-            c.shell = None if sh is None else sh.data_ptr()
-            cboxes.append(c)
-        self._cboxes = (Box * len(cboxes))(*cboxes)
+        self.u, self._keep, self._cboxes = _device_boxes(self.boxes, device)
         h = ctypes.c_void_p()
-        check(lib().z4c_plan_create(self._cboxes, len(cboxes), ctypes.byref(self.params),
-                                    None if tile is None else ctypes.byref(tile), ctypes.byref(h)), "z4c_plan_create")
+        check(lib().z4c_plan_create(self._cboxes, len(self.boxes), ctypes.byref(self.params),
+                                    None if tile is None else ctypes.byref(tile), _path(tune_cache),
+                                    ctypes.byref(h)), "z4c_plan_create")
         self._h = h
+
+    def tile(self):
+        """(Tile launched, source name: default / caller / cache / tuned)."""
+        t, src = Tile(), ctypes.c_int()
+        check(lib().z4c_plan_tile(self._h, ctypes.byref(t), ctypes.byref(src)), "z4c_plan_tile")
+        return t, TILE_SOURCE_NAMES[src.value]
 
     def step(self, nsteps: int = 1, use_graph: bool = True, stream=None):
         check(lib().z4c_plan_step(self._h, int(nsteps), int(bool(use_graph)), _stream(stream)), "z4c_plan_step")

@@ -134,16 +134,99 @@ def test_plan_validation(L):
     b.dt = 0.05
     b.u_n, b.u_a, b.u_b, b.acc = 0x10000000, 0x20000000, 0x30000000, 0x40000000
     arr = (z4c.Box * 1)(b)
-    assert L.z4c_plan_create(arr, 0, ctypes.byref(p), None, ctypes.byref(h)) == z4c.EINVAL
-    assert L.z4c_plan_create(arr, 17, ctypes.byref(p), None, ctypes.byref(h)) == z4c.EINVAL
+    assert L.z4c_plan_create(arr, 0, ctypes.byref(p), None, None, ctypes.byref(h)) == z4c.EINVAL
+    assert L.z4c_plan_create(arr, 17, ctypes.byref(p), None, None, ctypes.byref(h)) == z4c.EINVAL
     arr[0].u_b = arr[0].u_a
-    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), None, ctypes.byref(h)) == z4c.EINVAL
+    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == z4c.EINVAL
     assert b"overlap" in L.z4c_last_error()
     arr[0].u_b = 0x30000000
     arr[0].bc = 2  # copy box without shell
-    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), None, ctypes.byref(h)) == z4c.EINVAL
+    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == z4c.EINVAL
     assert L.z4c_plan_step(None, 1, 1, None) == z4c.EINVAL
     assert L.z4c_plan_destroy(None) == z4c.EINVAL
+    assert L.z4c_plan_tile(None, None, None) == z4c.EINVAL
+
+
+def _tune_boxes(n=(8, 8, 8), count=1):
+    arr = (z4c.Box * count)()
+    for c in arr:
+        c.n[:] = list(n)
+        c.ng, c.bc, c.sf = 3, 0, (n[0] + 6) * (n[1] + 6) * (n[2] + 6)
+        c.dx[:] = [0.1, 0.1, 0.1]
+        c.dt = 0.05
+    for k, c in enumerate(arr):
+        c.u_n, c.u_a, c.u_b, c.acc = [0x10000000 * (4 * k + i + 1) for i in range(4)]
+    return arr
+
+
+def test_tune_cache_lookup_hit_miss_missing_corrupt(L, tmp_path):
+    """The tuning cache (JSON lines keyed by architecture, precision, box
+    count and bucket = floor(log2(active cells))): hit, key misses, a missing
+    file (an empty cache), a corrupt file (Z4C_EINVAL) and a cached shape this
+    build does not compile (a miss)."""
+    from paper_2607_08743_amd import inputs as I
+    path = tmp_path / "tune.jsonl"
+    g256 = I.centered_grid(256, 0.125)
+    t = z4c.tiles(z4c.FP64)[0]
+    path.write_text(json.dumps({"arch": "gfx950", "precision": 0, "nbox": 1, "bucket": 24,
+                                "tile": [t.bx, t.by, t.bz, t.waves, 1], "ms": 29.4}) + "\n\n"
+                    + json.dumps({"arch": "gfx950", "precision": 1, "nbox": 1, "bucket": 24,
+                                  "tile": [3, 3, 3, 1, 0], "ms": 1.0}) + "\n")
+    hit = z4c.tune_lookup(str(path), "gfx950", [g256])
+    assert hit is not None and hit.as_tuple() == (t.bx, t.by, t.bz, t.waves, 1)
+    assert z4c.tune_lookup(str(path), "gfx942", [g256]) is None                    # other architecture
+    assert z4c.tune_lookup(str(path), "gfx950", [I.centered_grid(128, 0.25)]) is None  # other bucket (21)
+    assert z4c.tune_lookup(str(path), "gfx950", [g256, g256]) is None              # other box count
+    assert z4c.tune_lookup(str(path), "gfx950", [g256], z4c.MIXED) is None         # shape not compiled
+    # the bucket is floor(log2(cells)): 2^24 - 1 cells fall in bucket 23
+    assert z4c.tune_lookup(str(path), "gfx950", [I.centered_grid((256, 256, 255), 0.125)]) is None
+    assert z4c.tune_lookup(str(tmp_path / "missing.jsonl"), "gfx950", [g256]) is None
+    for bad in ('{"arch": "gfx950", "precision": 0, "nbox": 1, "bucket": 24}',            # no tile
+                '{"arch": "gfx950", "precision": 0, "nbox": 1, "bucket": 24, "tile": [8, 8]}',
+                '{"arch": "gfx950", "precision": 0, "nbox": 1, "bucket": 24, "tile": [8,8,8,2,1], "x": 1}',
+                'not json at all', '{"arch": "gfx950"'):
+        path.write_text(bad + "\n")
+        with pytest.raises(z4c.Z4cError) as ei:
+            z4c.tune_lookup(str(path), "gfx950", [g256])
+        assert ei.value.status == z4c.EINVAL and b"tune cache" in L.z4c_last_error()
+
+
+def test_plan_create_with_tune_cache(L, tmp_path):
+    """z4c_plan_create with a cache path: a missing file is an empty cache
+    (default tile, no HIP call needed), a corrupt one fails with Z4C_EINVAL
+    before anything else happens."""
+    p = z4c.default_params()
+    h = ctypes.c_void_p()
+    arr = _tune_boxes()
+    missing = str(tmp_path / "none.jsonl").encode()
+    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), None, missing, ctypes.byref(h)) == z4c.OK
+    t, src = z4c.Tile(), ctypes.c_int()
+    assert L.z4c_plan_tile(h, ctypes.byref(t), ctypes.byref(src)) == z4c.OK
+    assert src.value == z4c.TILE_DEFAULT and t.persistent == 1
+    assert L.z4c_plan_destroy(h) == z4c.OK
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text("{broken\n")
+    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), None, str(bad).encode(), ctypes.byref(h)) == z4c.EINVAL
+    assert b"tune cache" in L.z4c_last_error()
+    # a caller tile wins over the cache and is reported as such
+    t0 = z4c.tiles(z4c.FP64)[0]
+    assert L.z4c_plan_create(arr, 1, ctypes.byref(p), ctypes.byref(t0), str(bad).encode(), ctypes.byref(h)) == z4c.OK
+    assert L.z4c_plan_tile(h, ctypes.byref(t), ctypes.byref(src)) == z4c.OK
+    assert src.value == z4c.TILE_CALLER and t.as_tuple()[:4] == t0.as_tuple()[:4]
+    assert L.z4c_plan_destroy(h) == z4c.OK
+
+
+def test_autotune_validation(L, tmp_path):
+    p = z4c.default_params()
+    arr = _tune_boxes()
+    best, src = z4c.Tile(), ctypes.c_int()
+    assert L.z4c_autotune(arr, 0, ctypes.byref(p), None, None, ctypes.byref(best), ctypes.byref(src)) == z4c.EINVAL
+    assert L.z4c_autotune(arr, 1, None, None, None, ctypes.byref(best), ctypes.byref(src)) == z4c.EINVAL
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text("[1, 2]\n")
+    assert L.z4c_autotune(arr, 1, ctypes.byref(p), str(bad).encode(), None, ctypes.byref(best),
+                          ctypes.byref(src)) == z4c.EINVAL
+    assert bad.read_text() == "[1, 2]\n"  # a corrupt cache is left as it is
 
 
 def test_strerror(L):
@@ -344,3 +427,4 @@ def test_missing_library_fails_loudly():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["raised", "True", "raised", "True"], out.stdout
+

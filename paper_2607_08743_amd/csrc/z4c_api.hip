@@ -556,8 +556,9 @@ long z4c_constraints_workspace(int nx, int ny, int nz)
     return 4 * constraint_blocks(n);
 }
 
-// Overlap checks and launch of the constraint monitor; own_ws: ws is not
-// caller memory, so its overlap with the arguments needs no check.
+// Validation and launch shared by z4c_constraints and z4c_constraints_noalloc;
+// ws is the caller's workspace, or the library's fixed device array (whose
+// overlap with the arguments needs no check: no caller can hold it).
 static int constraints_impl(const double* u, double* c, double* norms, double* ws, bool own_ws, long sf, int nx,
                             int ny, int nz, int ng, double dx, double dy, double dz, void* stream, const char* where)
 {
@@ -1881,3 +1882,53 @@ int z4c_hier_destroy(void* hier)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Constraint monitor without a caller workspace.  The block partial sums go
+// to `scratch`, a fixed device array of this library: every device the
+// library runs on holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory, so the kernels
+// receive the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device on its first call.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS * 4];
+
+namespace {
+constexpr int MAXDEV = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAXDEV] = {};
+}  // namespace
+
+extern "C" int z4c_constraints_noalloc(const double* u, double* c, double* norms, long sf, int nx, int ny, int nz,
+                                       int ng, double dx, double dy, double dz, void* stream)
+{
+    long stored = 0;
+    int rc;
+    if ((rc = check_geom(sf, nx, ny, nz, ng, Z4C_BC_PERIODIC, &stored)) ||
+        (rc = check_spacing(dx, dy, dz, 0.0, 0.0, 0.0)))
+        return rc;
+    if (!u || !norms) return fail(Z4C_EINVAL, "u and norms must be non-NULL");
+    const int n[3] = {nx, ny, nz};
+    const long nb = constraint_blocks(n);
+    if (nb > Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS)
+        return fail(Z4C_EINVAL, "box too large for z4c_constraints_noalloc: " + std::to_string(nb) +
+                                    " bricks of 8^3 cells, at most " +
+                                    std::to_string((long)Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS) +
+                                    " (use z4c_constraints with a workspace)");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAXDEV) return fail(Z4C_EUNSUPPORTED, "device index beyond the library's table");
+    double* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_dev[dev]) {
+            void* ptr = nullptr;
+            if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+                return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            g_scratch_dev[dev] = (double*)ptr;
+        }
+        ws = g_scratch_dev[dev];
+    }
+    return constraints_impl(u, c, norms, ws, true, sf, nx, ny, nz, ng, dx, dy, dz, stream, "z4c_constraints_noalloc");
+}

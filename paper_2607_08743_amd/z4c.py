@@ -111,13 +111,14 @@ def lib(path: str = LIB_PATH):
     L.z4c_constraints_workspace.argtypes = [i, i, i]
     L.z4c_constraints_workspace.restype = l
     L.z4c_constraints.argtypes = [dp, dp, dp, dp, l, l, i, i, i, i, d, d, d, vp]
+    L.z4c_constraints_noalloc.argtypes = [dp, dp, dp, l, i, i, i, i, d, d, d, vp]
     L.z4c_strerror.argtypes = [i]
     L.z4c_strerror.restype = ctypes.c_char_p
     L.z4c_last_error.argtypes = []
     L.z4c_last_error.restype = ctypes.c_char_p
     for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
                  "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints",
-                 "z4c_plan_tile", "z4c_autotune", "z4c_tune_lookup",
+                 "z4c_plan_tile", "z4c_autotune", "z4c_tune_lookup", "z4c_constraints_noalloc",
                  "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy", "z4c_hier_set_moving", "z4c_hier_puncture"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -222,6 +223,24 @@ def constraints(u, g: _inputs.Grid, c=None, norms=None, ws=None, stream=None):
     check(lib().z4c_constraints(_ptr(u), _ptr(c), _ptr(norms), _ptr(ws), ctypes.c_long(ws.numel()),
                                 ctypes.c_long(g.stored), int(g.n[0]), int(g.n[1]), int(g.n[2]), int(g.ng),
                                 float(g.h[0]), float(g.h[1]), float(g.h[2]), _stream(stream)), "z4c_constraints")
+    return norms
+
+
+def constraints_noalloc(u, g: _inputs.Grid, c=None, norms=None, stream=None):
+    """z4c_constraints_noalloc: the constraint monitor with the library's own
+    fixed device array for the block sums (no workspace, nothing allocated by
+    the library).  norms: a (4,) float64 CUDA tensor (allocated here if not
+    given)."""
+    import torch
+    _state_tensor(u, g, "u")
+    if c is not None and (c.dtype != torch.float64 or not c.is_cuda or not c.is_contiguous()
+                          or tuple(c.shape) != (4,) + tuple(g.shape[1:])):
+        raise TypeError("c must be a contiguous float64 CUDA tensor of shape (4, Nz, Ny, Nx)")
+    if norms is None:
+        norms = torch.empty(4, dtype=torch.float64, device=u.device)
+    check(lib().z4c_constraints_noalloc(_ptr(u), _ptr(c), _ptr(norms), ctypes.c_long(g.stored), int(g.n[0]),
+                                        int(g.n[1]), int(g.n[2]), int(g.ng), float(g.h[0]), float(g.h[1]),
+                                        float(g.h[2]), _stream(stream)), "z4c_constraints_noalloc")
     return norms
 
 

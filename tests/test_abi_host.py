@@ -428,3 +428,16 @@ def test_missing_library_fails_loudly():
     assert out.returncode == 0, out.stderr
     assert out.stdout.split() == ["raised", "True", "raised", "True"], out.stdout
 
+
+def test_constraints_noalloc_validation(L):
+    """The allocation-free monitor refuses boxes beyond its fixed array (more
+    than Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS bricks of 8^3) and bad arguments
+    before any HIP call."""
+    n = 520  # 65^3 = 274625 bricks > 262144
+    sf = (n + 6) ** 3
+    args = (sf, n, n, n, 3, 0.1, 0.1, 0.1, None)
+    assert L.z4c_constraints_noalloc(FAKE, None, FAKE2, *args) == z4c.EINVAL
+    assert b"too large" in L.z4c_last_error()
+    assert L.z4c_constraints_noalloc(None, None, FAKE2, 14 ** 3, 8, 8, 8, 3, 0.1, 0.1, 0.1, None) == z4c.EINVAL
+    assert L.z4c_constraints_noalloc(FAKE, None, None, 14 ** 3, 8, 8, 8, 3, 0.1, 0.1, 0.1, None) == z4c.EINVAL
+    assert L.z4c_constraints_noalloc(FAKE, None, FAKE2, 14 ** 3, 8, 8, 8, 2, 0.1, 0.1, 0.1, None) == z4c.EINVAL

@@ -26,12 +26,13 @@ namespace {
 constexpr int CX = 8, CY = 8, CZ = 8;  // brick of one block (one point per thread)
 constexpr int CNT = CX * CY * CZ;
 
-// Tile geometry: halo 3 on the DMA path (tile rows then start on even
-// elements, as 16-byte loads need), halo 2 on the register path.
+// Tile geometry.  The stencils reach 2 cells (centred first, second and
+// mixed derivatives).  On the DMA path the x halo is 3 so that every tile row
+// starts on an even element (16-byte loads); y and z keep the 2-cell halo.
 template <bool DMA>
 struct CTile {
-    static constexpr int H = DMA ? 3 : 2;
-    static constexpr int SX = CX + 2 * H, SY = CY + 2 * H, SXY = SX * SY, TN = SXY * (CZ + 2 * H);
+    static constexpr int HX = DMA ? 3 : 2, H = 2;
+    static constexpr int SX = CX + 2 * HX, SY = CY + 2 * H, SXY = SX * SY, TN = SXY * (CZ + 2 * H);
     static constexpr int NR = (TN / 2 + CNT - 1) / CNT;      // 16-byte rounds per thread (DMA)
     static constexpr int TNP = DMA ? NR * CNT * 2 : TN;       // padded tile
     static constexpr int NE = (TN + CNT - 1) / CNT;           // elements per thread (register path)
@@ -44,6 +45,22 @@ __device__ __forceinline__ int sidx(int a, int b)
 }
 
 __device__ __forceinline__ void keep(double& x) { __asm__ volatile("" : "+v"(x)); }
+// Re-define every element here (an empty asm that may change them): the
+// arithmetic that follows cannot be hoisted above this point, which keeps
+// the algebra in phases instead of one interleaved block that needs more
+// registers than a wave has.
+template <int N>
+__device__ __forceinline__ void phase(double (&x)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) keep(x[i]);
+}
+template <int M, int N>
+__device__ __forceinline__ void phase(double (&x)[M][N])
+{
+#pragma unroll
+    for (int i = 0; i < M; ++i) phase(x[i]);
+}
 
 __device__ __forceinline__ double cd1(const double* t, int st, double i12h)
 {
@@ -69,18 +86,41 @@ __device__ __forceinline__ int cseq(int i)
 }
 constexpr int CNSEQ = 18;
 
+// Every term is folded into the constraint it feeds as soon as its inputs
+// exist, so that few values stay live across the staging sequence:
+//   after gt:     the part of M^i that needs d gt through the raised At
+//                 (d gt^ab = -gt^ac gt^bd d gt_cd; At at the point is loaded
+//                 beside gt), then the Christoffels (d gt dies), the Ricci
+//                 terms quadratic in them and the Christoffel terms of the
+//                 covariant divergence in M^i;
+//   after W:      W^2 R_ij and its trace R (the Christoffels die here);
+//   after Theta:  d K folded into gt^ij d_j K;
+//   per At field: gt^ia gt^jb d_j At_ab.
 template <bool DMA>
-__global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
-constraints_kernel(BoxSet set, double* c_out, double* partial)
+__global__ void __launch_bounds__(CNT) constraints_kernel(BoxSet set, double* c_out, double* partial)
 {
     using T = CTile<DMA>;
     constexpr int SX = T::SX, SXY = T::SXY, TN = T::TN, TNP = T::TNP, NR = T::NR, NE = T::NE;
-    __shared__ __attribute__((aligned(16))) double tiles[T::NBUF * TNP];
-    __shared__ double red[4][CNT];
+    // the block reduction reuses the tile buffers (4 sums per thread)
+    constexpr int TILE_D = T::NBUF * TNP > 4 * CNT ? T::NBUF * TNP : 4 * CNT;
+    __shared__ __attribute__((aligned(16))) double tiles[TILE_D];
     const BoxDev& B = set.box[0];
     const int tid = threadIdx.x;
-    const int tx = tid % CX, ty = (tid / CX) % CY, tz = tid / (CX * CY);
-    const long w = blockIdx.x;
+    // Lane order.  A 64-bit LDS read serves 16 lanes (two 8-point rows) per
+    // pass.  With the 14-double row pitch of the DMA tile, rows y and y+4 are
+    // 448 bytes apart and fall in disjoint halves of the banks, so each wave
+    // takes its rows in the order 0, 4, 1, 5, 2, 6, 3, 7 (the 12-double pitch
+    // of the register tile keeps the plain order: y and y+1 overlap less there).
+    const int q8 = (tid / CX) % CY;
+    const int tx = tid % CX, ty = DMA ? (((q8 & 1) << 2) | (q8 >> 1)) : q8, tz = tid / (CX * CY);
+    // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b mod 8);
+    // give each XCD one contiguous chunk of the brick sequence, so that bricks
+    // that share halo rows are fetched through the same L2.  The grid is a
+    // multiple of 8; blocks past the last brick have nothing to do.
+    const long nbk = (long)B.nb[0] * B.nb[1] * B.nb[2];
+    const long chunk = (long)gridDim.x / 8;
+    const long w = (long)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
+    if (w >= nbk) return;  // the whole block: no barrier is left waiting
     const int bxi = (int)(w % B.nb[0]), byi = (int)((w / B.nb[0]) % B.nb[1]), bzi = (int)(w / ((long)B.nb[0] * B.nb[1]));
     const int ng = B.ng;
     const int Nx = B.n[0] + 2 * ng, Ny = B.n[1] + 2 * ng, Nz = B.n[2] + 2 * ng;
@@ -88,18 +128,25 @@ constraints_kernel(BoxSet set, double* c_out, double* partial)
     const bool valid = (i0 + tx < B.n[0]) && (j0 + ty < B.n[1]) && (k0 + tz < B.n[2]);
     const size_t sf = (size_t)B.sf;
     const size_t p = ((size_t)(k0 + tz + ng) * Ny + (j0 + ty + ng)) * Nx + (i0 + tx + ng);
-    const int gx0 = i0 + ng - T::H, gy0 = j0 + ng - T::H, gz0 = k0 + ng - T::H;
-    const int cofs = (tz + T::H) * SXY + (ty + T::H) * SX + (tx + T::H);
+    const int gx0 = i0 + ng - T::HX, gy0 = j0 + ng - T::H, gz0 = k0 + ng - T::H;
+    const int cofs = (tz + T::H) * SXY + (ty + T::H) * SX + (tx + T::HX);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    // the derivative factors are the same on every lane: scalar registers
+    auto uni = [](double x) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    };
     double i12h[3], i12h2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        i12h[d] = 1.0 / (12.0 * B.h[d]);
-        i12h2[d] = 1.0 / (12.0 * B.h[d] * B.h[d]);
+        i12h[d] = uni(1.0 / (12.0 * B.h[d]));
+        i12h2[d] = uni(1.0 / (12.0 * B.h[d] * B.h[d]));
     }
-    const double imix[3] = {1.0 / (144.0 * B.h[0] * B.h[1]), 1.0 / (144.0 * B.h[0] * B.h[2]),
-                            1.0 / (144.0 * B.h[1] * B.h[2])};
+    const double imix[3] = {uni(1.0 / (144.0 * B.h[0] * B.h[1])), uni(1.0 / (144.0 * B.h[0] * B.h[2])),
+                            uni(1.0 / (144.0 * B.h[1] * B.h[2]))};
 
     // per-thread offsets of its tile slots in one field (element pairs on the
     // DMA path; slots outside the stored box read a harmless valid address
@@ -162,25 +209,38 @@ constraints_kernel(BoxSet set, double* c_out, double* partial)
 #pragma unroll
         for (int c = 0; c < 3; ++c) keep(d[c]);
     };
+    // second derivatives; the memory clobbers keep the compiler from issuing
+    // the LDS reads of all six at once (each read holds two registers until
+    // it is used), which would exceed the register budget
     auto hess = [&](double* dd) {
         dd[0] = cd2(t, 1, i12h2[0]);
         dd[3] = cd2(t, SX, i12h2[1]);
         dd[5] = cd2(t, SXY, i12h2[2]);
+        keep(dd[0]);
+        keep(dd[3]);
+        keep(dd[5]);
+        __asm__ volatile("" ::: "memory");
         dd[1] = cmix(t, 1, SX, imix[0]);
+        keep(dd[1]);
+        __asm__ volatile("" ::: "memory");
         dd[2] = cmix(t, 1, SXY, imix[1]);
+        keep(dd[2]);
+        __asm__ volatile("" ::: "memory");
         dd[4] = cmix(t, SX, SXY, imix[2]);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) keep(dd[q]);
+        keep(dd[4]);
     };
     auto tr6 = [](const double* g, const double* x) {
         return g[0] * x[0] + g[3] * x[3] + g[5] * x[5] + 2.0 * (g[1] * x[1] + g[2] * x[2] + g[4] * x[4]);
     };
 
-    // conformal metric at the point (loaded after the first tiles, so one
-    // round trip covers both) and its inverse
-    double gt[6], gu[6], dgt[6][3], Rt[6];
+    // conformal metric and traceless curvature at the point (loaded after the
+    // first tiles, so one round trip covers both); the flat state on idle lanes
+    double gt[6], gu[6], At[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) gt[q] = valid ? B.u_in[(F_GT + q) * sf + p] : (q == 0 || q == 3 || q == 5 ? 1.0 : 0.0);
+    for (int q = 0; q < 6; ++q) {
+        gt[q] = valid ? B.u_in[(F_GT + q) * sf + p] : (q == 0 || q == 3 || q == 5 ? 1.0 : 0.0);
+        At[q] = valid ? B.u_in[(F_AT + q) * sf + p] : 0.0;
+    }
     {
         const double det = gt[0] * (gt[3] * gt[5] - gt[4] * gt[4]) - gt[1] * (gt[1] * gt[5] - gt[4] * gt[2])
                          + gt[2] * (gt[1] * gt[4] - gt[3] * gt[2]);
@@ -192,48 +252,142 @@ constraints_kernel(BoxSet set, double* c_out, double* partial)
         gu[4] = (gt[2] * gt[1] - gt[0] * gt[4]) * id;
         gu[5] = (gt[0] * gt[3] - gt[1] * gt[1]) * id;
     }
+    double Rt[6], C2[3][6], Auu[6], AA, Mp[3];
+    {
+        double dgt[6][3];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        stage(q);
-        grad(dgt[q]);
-        double dd[6];
-        hess(dd);
-        Rt[q] = -0.5 * tr6(gu, dd);
-        keep(Rt[q]);
-    }
-    double C1[3][6], C2[3][6], Gtd[3];
+        for (int q = 0; q < 6; ++q) {
+            stage(q);
+            grad(dgt[q]);
+            double dd[6];
+            hess(dd);
+            Rt[q] = -0.5 * tr6(gu, dd);
+            keep(Rt[q]);
+        }
+        // the part of the momentum constraint that needs d gt through the raised
+        // At: At_cd d_j(gt^ac gt^jd), with d_j gt^ab = -gt^ac gt^bd d_j gt_cd
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) Mp[a] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double dgu[6];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b2 = a; b2 < 3; ++b2) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) s += gu[sidx(a, cc)] * gu[sidx(b2, d)] * dgt[sidx(cc, d)][j];
+                    dgu[sidx(a, b2)] = -s;
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                double s = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        s += At[sidx(cc, d)] * (dgu[sidx(a, cc)] * gu[sidx(j, d)] + gu[sidx(a, cc)] * dgu[sidx(j, d)]);
+                Mp[a] += s;
+                keep(Mp[a]);
+            }
+        }
+        // Christoffel symbols (first kind C1, second kind C2); d gt dies here
+        phase(dgt);
+        phase(gu);
+        double C1[3][6], Gtd[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j) {
+                    C1[k][sidx(i, j)] = 0.5 * (dgt[sidx(k, j)][i] + dgt[sidx(k, i)][j] - dgt[sidx(i, j)][k]);
+                    keep(C1[k][sidx(i, j)]);
+                }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                C2[k][q] = gu[sidx(k, 0)] * C1[0][q] + gu[sidx(k, 1)] * C1[1][q] + gu[sidx(k, 2)] * C1[2][q];
+                keep(C2[k][q]);
+            }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Gtd[k] = tr6(gu, C2[k]);
+        phase(C1);
+        phase(C2);
+        phase(Gtd);
+        // Ricci terms quadratic in the Christoffels:
+        // gt^lm (Gamma^k_li Gamma_jkm + Gamma^k_lj Gamma_ikm + Gamma^k_im Gamma_klj) = M_ij + M_ji + T_ij
+        // with Cu[a][b][l] = gt^lm Gamma_abm, M_ij = Gamma^k_li Cu[j][k][l], T_ij = Gamma^k_im Cu[k][j][m]
+        double M[3][3], T3[3][3];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = i; j < 3; ++j)
-                C1[k][sidx(i, j)] = 0.5 * (dgt[sidx(k, j)][i] + dgt[sidx(k, i)][j] - dgt[sidx(i, j)][k]);
+            for (int j = 0; j < 3; ++j) M[i][j] = T3[i][j] = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int q = 0; q < 6; ++q)
-            C2[k][q] = gu[sidx(k, 0)] * C1[0][q] + gu[sidx(k, 1)] * C1[1][q] + gu[sidx(k, 2)] * C1[2][q];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) Gtd[k] = tr6(gu, C2[k]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                s += 0.5 * Gtd[k] * (C1[i][sidx(j, k)] + C1[j][sidx(i, k)]);
+            for (int b2 = 0; b2 < 3; ++b2) {
+                double cu[3];
 #pragma unroll
                 for (int l = 0; l < 3; ++l)
+                    cu[l] = gu[sidx(l, 0)] * C1[a][sidx(b2, 0)] + gu[sidx(l, 1)] * C1[a][sidx(b2, 1)]
+                          + gu[sidx(l, 2)] * C1[a][sidx(b2, 2)];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m)
-                        s += gu[sidx(l, m)] * (C2[k][sidx(l, i)] * C1[j][sidx(k, m)]
-                                               + C2[k][sidx(l, j)] * C1[i][sidx(k, m)]
-                                               + C2[k][sidx(i, m)] * C1[k][sidx(l, j)]);
+                for (int i = 0; i < 3; ++i) {
+                    M[i][a] += C2[b2][sidx(0, i)] * cu[0] + C2[b2][sidx(1, i)] * cu[1] + C2[b2][sidx(2, i)] * cu[2];
+                    T3[i][b2] += C2[a][sidx(i, 0)] * cu[0] + C2[a][sidx(i, 1)] * cu[1] + C2[a][sidx(i, 2)] * cu[2];
+                }
             }
-            Rt[sidx(i, j)] += s;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j) {
+                double s = M[i][j] + M[j][i] + T3[i][j];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) s += 0.5 * Gtd[k] * (C1[i][sidx(j, k)] + C1[j][sidx(i, k)]);
+                Rt[sidx(i, j)] += s;
+                keep(Rt[sidx(i, j)]);
+            }
+        phase(C2);
+        phase(At);
+        phase(gu);
+        // At^ij, At_ij At^ij, and the Christoffel terms of the covariant
+        // divergence: Gamma^a_jk At^jk + Gamma^j_jk At^ak
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b2 = 0; b2 < 3; ++b2) s += gu[sidx(i, a)] * gu[sidx(j, b2)] * At[sidx(a, b2)];
+                Auu[sidx(i, j)] = s;
+            }
+        AA = tr6(Auu, At);
+        double trG[3];  // Gamma^j_jk
+#pragma unroll
+        for (int k = 0; k < 3; ++k) trG[k] = C2[0][sidx(0, k)] + C2[1][sidx(1, k)] + C2[2][sidx(2, k)];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double chr = 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) chr += C2[a][sidx(j, k)] * Auu[sidx(j, k)];
+                chr += trG[j] * Auu[sidx(a, j)];
+            }
+            Mp[a] += chr;
+            keep(Mp[a]);
         }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) keep(Auu[q]);
+        keep(AA);
+    }
     // evolved Gt in the Ricci tensor
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -247,44 +401,16 @@ constraints_kernel(BoxSet set, double* c_out, double* partial)
 #pragma unroll
         for (int q = 0; q < 6; ++q) keep(Rt[q]);
     }
-    // conformal factor
-    double W, dW[3], DDW[6];
-    stage(9);
-    W = t[0];
-    grad(dW);
-    hess(DDW);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
-        keep(DDW[q]);
-    }
-    // trace of the extrinsic curvature
-    double K, dK[3];
-    stage(10);
-    K = t[0];
-    grad(dK);
-    stage(11);
-    K += 2.0 * t[0];
+    // conformal factor: W^2 R_ij and its trace (no division by W)
+    double W, dW[3], R;
     {
-        double d[3];
-        grad(d);
+        stage(9);
+        W = t[0];
+        grad(dW);
+        double DDW[6];
+        hess(DDW);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            dK[c] += 2.0 * d[c];
-            keep(dK[c]);
-        }
-    }
-    // traceless curvature
-    double At[6], dAt[6][3];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        stage(12 + q);
-        At[q] = t[0];
-        grad(dAt[q]);
-    }
-
-    double c[4] = {0.0, 0.0, 0.0, 0.0};
-    if (valid) {
+        for (int q = 0; q < 6; ++q) DDW[q] -= C2[0][q] * dW[0] + C2[1][q] * dW[1] + C2[2][q] * dW[2];
         const double trDDW = tr6(gu, DDW);
         double dW2 = 0.0;
 #pragma unroll
@@ -294,74 +420,78 @@ constraints_kernel(BoxSet set, double* c_out, double* partial)
         double W2R[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - 2.0 * gt[q] * dW2;
-        const double R = tr6(gu, W2R);
-        double Auu[6];
+        R = tr6(gu, W2R);
+        keep(R);
+    }
+    // trace of the extrinsic curvature: K and gt^ij d_j K
+    double K, gk[3];
+    {
+        double dK[3];
+        stage(10);
+        K = t[0];
+        grad(dK);
+        stage(11);
+        K += 2.0 * t[0];
+        double d[3];
+        grad(d);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b2 = 0; b2 < 3; ++b2) s += gu[sidx(i, a)] * gu[sidx(j, b2)] * At[sidx(a, b2)];
-                Auu[sidx(i, j)] = s;
-            }
-        const double AA = tr6(Auu, At);
-        c[0] = R - AA + 2.0 * K * K / 3.0;
-        // d_j gt^ab = -gt^ac gt^bd d_j gt_cd
-        double dgu[3][6];
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b2 = a; b2 < 3; ++b2) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) s += gu[sidx(a, cc)] * gu[sidx(b2, d)] * dgt[sidx(cc, d)][j];
-                    dgu[j][sidx(a, b2)] = -s;
-                }
-        double trG[3];  // Gamma^j_jk
-#pragma unroll
-        for (int k = 0; k < 3; ++k) trG[k] = C2[0][sidx(0, k)] + C2[1][sidx(1, k)] + C2[2][sidx(2, k)];
+        for (int c = 0; c < 3; ++c) dK[c] += 2.0 * d[c];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double div = 0.0, chr = 0.0, aw = 0.0, gk = 0.0;
+            gk[a] = gu[sidx(a, 0)] * dK[0] + gu[sidx(a, 1)] * dK[1] + gu[sidx(a, 2)] * dK[2];
+            keep(gk[a]);
+        }
+    }
+    // traceless curvature: gt^ia gt^jb d_j At_ab, one component at a time
+    double div[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        stage(12 + q);
+        double d[3];
+        grad(d);
+        // component q = (c, e) stands for At_ce and At_ec
+        const int c = q < 3 ? 0 : (q < 5 ? 1 : 2);
+        const int e = q < 3 ? q : (q < 5 ? q - 2 : 2);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d)
-                        div += gu[sidx(a, cc)] * gu[sidx(j, d)] * dAt[sidx(cc, d)][j]
-                             + At[sidx(cc, d)] * (dgu[j][sidx(a, cc)] * gu[sidx(j, d)]
-                                                  + gu[sidx(a, cc)] * dgu[j][sidx(j, d)]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) chr += C2[a][sidx(j, k)] * Auu[sidx(j, k)];
-                chr += trG[j] * Auu[sidx(a, j)];
-                aw += Auu[sidx(a, j)] * dW[j];
-                gk += gu[sidx(a, j)] * dK[j];
+                double wgt = gu[sidx(a, c)] * gu[sidx(j, e)];
+                if (c != e) wgt += gu[sidx(a, e)] * gu[sidx(j, c)];
+                s += wgt * d[j];
             }
-            c[1 + a] = W * W * (div + chr - 3.0 * aw / W - 2.0 * gk / 3.0);
+            div[a] += s;
+            keep(div[a]);
+        }
+    }
+
+    double cv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        cv[0] = R - AA + 2.0 * K * K / 3.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double aw = Auu[sidx(a, 0)] * dW[0] + Auu[sidx(a, 1)] * dW[1] + Auu[sidx(a, 2)] * dW[2];
+            cv[1 + a] = W * W * (div[a] + Mp[a] - 3.0 * aw / W - 2.0 * gk[a] / 3.0);
         }
         if (c_out)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) c_out[m * sf + p] = c[m];
+            for (int m = 0; m < 4; ++m) c_out[m * sf + p] = cv[m];
     }
-    // fixed-order block reduction of C^2
-#pragma unroll
-    for (int m = 0; m < 4; ++m) red[m][tid] = c[m] * c[m];
+    // fixed-order block reduction of C^2 in the (now free) tile buffers
+    if constexpr (DMA) __builtin_amdgcn_s_waitcnt(VM_N(0));
     __syncthreads();
-    for (int s = CNT / 2; s > 0; s >>= 1) {
-        if (tid < s)
+    double* red = tiles;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + s];
+    for (int m = 0; m < 4; ++m) red[m * CNT + tid] = cv[m] * cv[m];
+    __syncthreads();
+    for (int s2 = CNT / 2; s2 > 0; s2 >>= 1) {
+        if (tid < s2)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) red[m * CNT + tid] += red[m * CNT + tid + s2];
         __syncthreads();
     }
-    if (tid < 4) partial[w * 4 + tid] = red[tid][0];
+    if (tid < 4) partial[w * 4 + tid] = red[tid * CNT];
 }
 
 // one block: fixed-order sum of the block partials, then the norms
@@ -410,10 +540,11 @@ hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, d
     }
     // 16-byte tile loads need tile rows on even elements of an aligned field
     const bool dma = B.ng % 2 == 1 && B.n[0] % 2 == 0 && B.sf % 2 == 0 && ((uintptr_t)B.u_in & 15) == 0;
+    const unsigned grid = (unsigned)((nb + 7) / 8 * 8);  // whole XCD rounds
     if (dma)
-        hipLaunchKernelGGL(constraints_kernel<true>, dim3((unsigned)nb), dim3(CNT), 0, s, one, c_out, workspace);
+        hipLaunchKernelGGL(constraints_kernel<true>, dim3(grid), dim3(CNT), 0, s, one, c_out, workspace);
     else
-        hipLaunchKernelGGL(constraints_kernel<false>, dim3((unsigned)nb), dim3(CNT), 0, s, one, c_out, workspace);
+        hipLaunchKernelGGL(constraints_kernel<false>, dim3(grid), dim3(CNT), 0, s, one, c_out, workspace);
     const double cells = (double)B.n[0] * B.n[1] * B.n[2];
     hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(256), 0, s, workspace, nb, 1.0 / cells, norms);
     return hipGetLastError();

@@ -114,7 +114,8 @@ def fused_kernel_roofline(z4c, I, torch, g, u_dev, dt, tile, params, reps=5):
 def constraint_monitor_rate(z4c, torch, g, u0, n, reps=5):
     """Constraint monitor (norms only) on the benchmark state: mean time per
     call (HIP events on the launch stream) and its algorithmic bytes (18
-    fields read over the active points plus the 2-cell stencil margin)."""
+    fields read over the active points plus the 2-cell stencil margin); and
+    the extra time of the monitor fused into stage 1 of the RK4 step."""
     u = torch.as_tensor(u0, device="cuda")
     ws = torch.empty(z4c.constraints_workspace(g), dtype=torch.float64, device="cuda")
     norms = torch.empty(4, dtype=torch.float64, device="cuda")
@@ -131,7 +132,31 @@ def constraint_monitor_rate(z4c, torch, g, u0, n, reps=5):
     alg = 18 * 8 * (n + 4) ** 3
     out = {"ms_per_call": round(ms, 4), "alg_bytes": alg, "achieved_GBs": round(alg / (ms * 1e-3) / 1e9, 1),
            "zone_per_s": n ** 3 / (ms * 1e-3), "norms": [float(x) for x in norms.cpu()]}
-    del u, ws
+    # the same monitor fused into stage 1 of an RK4 step (rk4_substep_monitor):
+    # its cost is the difference to the plain stage 1
+    acc, dst = torch.empty_like(u), torch.empty_like(u)
+    wsm = torch.empty(z4c.monitor_workspace(g), dtype=torch.float64, device="cuda")
+    nm = torch.empty(4, dtype=torch.float64, device="cuda")
+    dt = 0.5 * g.h[0]
+    z4c.select_tile(z4c.FP64, z4c.Tile(8, 8, 8, 2, 1))  # the monitor's launch shape, for a like-for-like difference
+    t = {}
+    for mon in (False, True, False, True):
+        z4c.rk4_substep_monitor(1, dt, u, None, acc, dst, g, norms=nm, ws=wsm) if mon else \
+            z4c.rk4_substep(1, dt, u, None, acc, dst, g)
+        e0.record(s)
+        for _ in range(reps):
+            if mon:
+                z4c.rk4_substep_monitor(1, dt, u, None, acc, dst, g, norms=nm, ws=wsm)
+            else:
+                z4c.rk4_substep(1, dt, u, None, acc, dst, g)
+        e1.record(s)
+        e1.synchronize()
+        t[mon] = e0.elapsed_time(e1) / reps
+    z4c.select_tile(z4c.FP64, None)
+    out["fused_into_stage1"] = {"ms_stage1_with_monitor": round(t[True], 4), "ms_stage1_plain": round(t[False], 4),
+                                "ms_monitor_extra": round(t[True] - t[False], 4),
+                                "norms": [float(x) for x in nm.cpu()]}
+    del u, ws, acc, dst, wsm
     torch.cuda.empty_cache()
     return out
 

@@ -120,6 +120,28 @@ int rk4_substep(int stage, double dt, const double* u_in, const double* u_n, dou
                 int nx, int ny, int nz, int ng, double dx, double dy, double dz, double x0, double y0, double z0,
                 int bc, const z4c_params* p, void* stream);
 
+/* rk4_substep fused with the constraint monitor of its input (Sec. 2.3):
+ * the same stage (bitwise the same u_out and acc), and from the same staged
+ * fields and derivatives the Hamiltonian and momentum constraints of u_in
+ * (definitions as for z4c_constraints) at every active point, plus their
+ * volume-normalised L2 norms.  Stage 1 of an RK4 step thus monitors the state
+ * at the start of the step at a small fraction of a separate monitor's cost.
+ * Float64 only (Z4C_EUNSUPPORTED otherwise); always 8x8x8 bricks with two
+ * waves per SIMD, persistent.
+ *   c      device, NULL or 4 fields of stride sf (H, M^x, M^y, M^z); ghost entries set to 0
+ *   norms  device, 4 doubles
+ *   ws     device workspace of ws_len >= z4c_monitor_workspace(nx, ny, nz) doubles
+ *          (per-wave partial sums; the norms sum them in a fixed order, so they
+ *          are bitwise reproducible, though not bitwise those of z4c_constraints,
+ *          whose reduction tree differs)
+ * c, norms and ws must not overlap each other or the state arrays.  Other
+ * arguments, aliasing rules and errors as for rk4_substep. */
+long z4c_monitor_workspace(int nx, int ny, int nz);
+int rk4_substep_monitor(int stage, double dt, const double* u_in, const double* u_n, double* acc, double* u_out,
+                        long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz, double x0, double y0,
+                        double z0, int bc, const z4c_params* p, double* c, double* norms, double* ws, long ws_len,
+                        void* stream);
+
 /* Fill the ghost points of u (in place).  Z4C_BC_PERIODIC: wrap from the
  * active box.  Z4C_BC_COPY: copy from `shell`, a float64 array of shape
  * (25, nshell), nshell = Nx*Ny*Nz - nx*ny*nz, holding the ghost points in

@@ -519,6 +519,72 @@ int rk4_substep(int stage, double dt, const double* u_in, const double* u_n, dou
     return Z4C_OK;
 }
 
+long z4c_monitor_workspace(int nx, int ny, int nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    const int n[3] = {nx, ny, nz};
+    return monitor_bricks(n) * 8 * 4;
+}
+
+int rk4_substep_monitor(int stage, double dt, const double* u_in, const double* u_n, double* acc, double* u_out,
+                        long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz, double x0, double y0,
+                        double z0, int bc, const z4c_params* p, double* c, double* norms, double* ws, long ws_len,
+                        void* stream)
+{
+    long stored = 0;
+    int rc;
+    if ((rc = check_params(p)) || (rc = check_geom(sf, nx, ny, nz, ng, bc, &stored)) ||
+        (rc = check_spacing(dx, dy, dz, x0, y0, z0)))
+        return rc;
+    if (p->precision != Z4C_FP64) return fail(Z4C_EUNSUPPORTED, "the stage monitor runs in float64 only");
+    if (stage < 1 || stage > 4) return fail(Z4C_EINVAL, "stage must be 1..4");
+    if (!finite_pos(dt)) return fail(Z4C_EINVAL, "dt must be finite and > 0");
+    if (!u_in || !acc || !u_out) return fail(Z4C_EINVAL, "u_in, acc and u_out must be non-NULL");
+    if (!norms || !ws) return fail(Z4C_EINVAL, "norms and ws must be non-NULL");
+    if ((stage == 2 || stage == 3) && !u_n) return fail(Z4C_EINVAL, "stages 2 and 3 read u_n");
+    if (overlap(u_out, u_in, sf)) return fail(Z4C_EINVAL, "u_out overlaps u_in");
+    if (overlap(u_out, acc, sf)) return fail(Z4C_EINVAL, "u_out overlaps acc");
+    if (overlap(acc, u_in, sf)) return fail(Z4C_EINVAL, "acc overlaps u_in");
+    if (stage != 4 && stage != 1 && overlap(acc, u_n, sf)) return fail(Z4C_EINVAL, "acc overlaps u_n");
+    if ((stage == 2 || stage == 3) && overlap(u_out, u_n, sf))
+        return fail(Z4C_EINVAL, "u_out may alias u_n only in stage 4");
+    const long need = z4c_monitor_workspace(nx, ny, nz);
+    if (ws_len < need) return fail(Z4C_EINVAL, "workspace too small: need " + std::to_string(need) + " doubles");
+    // c (4 fields), ws and norms against every state array and each other
+    const void* states[4] = {u_in, u_n, acc, u_out};
+    for (const void* a : states) {
+        if (c && overlap2(c, sf * 4 / NF + 1, a, sf)) return fail(Z4C_EINVAL, "c overlaps a state array");
+        if (overlap2(ws, need / NF + 1, a, sf)) return fail(Z4C_EINVAL, "ws overlaps a state array");
+        if (overlap2(norms, 1, a, sf)) return fail(Z4C_EINVAL, "norms overlaps a state array");
+    }
+    if (c && (overlap2(c, sf * 4 / NF + 1, ws, need / NF + 1) || overlap2(c, sf * 4 / NF + 1, norms, 1)))
+        return fail(Z4C_EINVAL, "c overlaps ws or norms");
+    if (overlap2(ws, need / NF + 1, norms, 1)) return fail(Z4C_EINVAL, "ws overlaps norms");
+    const int n[3] = {nx, ny, nz};
+    const double h[3] = {dx, dy, dz}, o[3] = {x0, y0, z0};
+    BoxSet set{};
+    set.nbox = 1;
+    set.box[0] = make_box(n, ng, bc, sf, h, o, dt);
+    set.box[0].u_in = u_in;
+    set.box[0].u_n = u_n;
+    set.box[0].acc = acc;
+    set.box[0].u_out = u_out;
+    finalize_set(set, z4c_tile{8, 8, 8, 2, 1});
+    const ParamsDev pd = to_dev(p);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending HIP error before rk4_substep_monitor");
+    if (c && (e = launch_zero(c, 4 * sf, s)) != hipSuccess) return hip_fail(e, "rk4_substep_monitor zero fill");
+    if ((e = launch_stage_monitor(set, pd, MODE_STAGE, stage, MonDev{c, ws}, s)) != hipSuccess)
+        return hip_fail(e, "rk4_substep_monitor fused launch");
+    if ((bc == Z4C_BC_SOMMERFELD || bc == Z4C_BC_EQUATORIAL) &&
+        (e = launch_sommerfeld(set, pd, MODE_STAGE, stage, s)) != hipSuccess)
+        return hip_fail(e, "rk4_substep_monitor Sommerfeld launch");
+    if ((e = launch_norms(ws, need / 4, 1.0 / ((double)nx * ny * nz), norms, s)) != hipSuccess)
+        return hip_fail(e, "rk4_substep_monitor norms");
+    return Z4C_OK;
+}
+
 int apply_ghosts(double* u, const double* shell, long sf, int nx, int ny, int nz, int ng, int bc, void* stream)
 {
     long stored = 0;

@@ -88,11 +88,9 @@ constexpr int CNSEQ = 18;
 
 // Every term is folded into the constraint it feeds as soon as its inputs
 // exist, so that few values stay live across the staging sequence:
-//   after gt:     the part of M^i that needs d gt through the raised At
-//                 (d gt^ab = -gt^ac gt^bd d gt_cd; At at the point is loaded
-//                 beside gt), then the Christoffels (d gt dies), the Ricci
-//                 terms quadratic in them and the Christoffel terms of the
-//                 covariant divergence in M^i;
+//   after gt:     the Christoffels (d gt dies), the Ricci terms quadratic in
+//                 them and the connection terms of the covariant divergence
+//                 in M^i (At at the point is loaded beside gt);
 //   after W:      W^2 R_ij and its trace R (the Christoffels die here);
 //   after Theta:  d K folded into gt^ij d_j K;
 //   per At field: gt^ia gt^jb d_j At_ab.
@@ -264,36 +262,6 @@ __global__ void __launch_bounds__(CNT) constraints_kernel(BoxSet set, double* c_
             Rt[q] = -0.5 * tr6(gu, dd);
             keep(Rt[q]);
         }
-        // the part of the momentum constraint that needs d gt through the raised
-        // At: At_cd d_j(gt^ac gt^jd), with d_j gt^ab = -gt^ac gt^bd d_j gt_cd
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Mp[a] = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double dgu[6];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b2 = a; b2 < 3; ++b2) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) s += gu[sidx(a, cc)] * gu[sidx(b2, d)] * dgt[sidx(cc, d)][j];
-                    dgu[sidx(a, b2)] = -s;
-                }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                double s = 0.0;
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d)
-                        s += At[sidx(cc, d)] * (dgu[sidx(a, cc)] * gu[sidx(j, d)] + gu[sidx(a, cc)] * dgu[sidx(j, d)]);
-                Mp[a] += s;
-                keep(Mp[a]);
-            }
-        }
         // Christoffel symbols (first kind C1, second kind C2); d gt dies here
         phase(dgt);
         phase(gu);
@@ -355,8 +323,11 @@ __global__ void __launch_bounds__(CNT) constraints_kernel(BoxSet set, double* c_
         phase(C2);
         phase(At);
         phase(gu);
-        // At^ij, At_ij At^ij, and the Christoffel terms of the covariant
-        // divergence: Gamma^a_jk At^jk + Gamma^j_jk At^ak
+        // At^ij and At_ij At^ij; the connection terms of the covariant
+        // divergence.  With D_j At^ij = gt^ia gt^jb D_j At_ab (the conformal
+        // connection is metric compatible) and Am_c^j = gt^jb At_cb:
+        //   D_j At^ij = gt^ia gt^jb d_j At_ab - gt^ia Gamma^c_ja Am_c^j - Gtd^c Am_c^i,
+        // the first term summed per At component below.
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -369,20 +340,27 @@ __global__ void __launch_bounds__(CNT) constraints_kernel(BoxSet set, double* c_
                 Auu[sidx(i, j)] = s;
             }
         AA = tr6(Auu, At);
-        double trG[3];  // Gamma^j_jk
+        double Am[3][3];  // Am[c][j] = gt^jb At_cb
 #pragma unroll
-        for (int k = 0; k < 3; ++k) trG[k] = C2[0][sidx(0, k)] + C2[1][sidx(1, k)] + C2[2][sidx(2, k)];
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Am[c][j] = gu[sidx(j, 0)] * At[sidx(c, 0)] + gu[sidx(j, 1)] * At[sidx(c, 1)] + gu[sidx(j, 2)] * At[sidx(c, 2)];
+        double Tm[3];  // Gamma^c_ja Am_c^j
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double chr = 0.0;
+            double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) chr += C2[a][sidx(j, k)] * Auu[sidx(j, k)];
-                chr += trG[j] * Auu[sidx(a, j)];
-            }
-            Mp[a] += chr;
-            keep(Mp[a]);
+                for (int j = 0; j < 3; ++j) s += C2[c][sidx(j, a)] * Am[c][j];
+            Tm[a] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            Mp[i] = -(gu[sidx(i, 0)] * Tm[0] + gu[sidx(i, 1)] * Tm[1] + gu[sidx(i, 2)] * Tm[2])
+                  - (Gtd[0] * Am[0][i] + Gtd[1] * Am[1][i] + Gtd[2] * Am[2][i]);
+            keep(Mp[i]);
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) keep(Auu[q]);
@@ -524,6 +502,18 @@ __global__ void __launch_bounds__(256) zero_fill(double* x, long n)
 long constraint_blocks(const int n[3])
 {
     return (long)((n[0] + CX - 1) / CX) * ((n[1] + CY - 1) / CY) * ((n[2] + CZ - 1) / CZ);
+}
+
+hipError_t launch_norms(const double* partial, long n, double inv_cells, double* norms, hipStream_t s)
+{
+    hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(256), 0, s, partial, n, inv_cells, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* x, long n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(zero_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, double* workspace, hipStream_t s)

@@ -66,6 +66,19 @@ struct ParamsDev {
 // mode of the fused kernel
 enum Mode : int { MODE_RHS = 0, MODE_STAGE = 1 };
 
+// Outputs of the constraint monitor fused into a stage (unused otherwise).
+struct MonDev {
+    double* c;     // NULL or 4 fields of the box's stride: H, M^x, M^y, M^z at the active points
+    double* part;  // per (brick, wave): sums of H^2, (M^x)^2, (M^y)^2, (M^z)^2
+};
+// a float64 stage (or RHS) of one box with the monitor of its input; bricks
+// of 8^3, eight waves each (monitor_bricks(n) * 8 * 4 doubles of part)
+long monitor_bricks(const int n[3]);
+hipError_t launch_stage_monitor(const BoxSet& set, const ParamsDev& p, int mode, int stage, MonDev mon, hipStream_t s);
+// fixed-order sum of n partial rows of 4 and the four L2 norms sqrt(sum / cells)
+hipError_t launch_norms(const double* partial, long n, double inv_cells, double* norms, hipStream_t s);
+hipError_t launch_zero(double* x, long n, hipStream_t s);
+
 // Compiled tile shapes.
 struct TileEntry {
     z4c_tile tile;

@@ -257,10 +257,40 @@ struct Brick {
     static constexpr int NGZ = (GZN + NT - 1) / NT;
 };
 
-template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA>
+// Opaque copy of N values: arithmetic on it shares no subexpression with
+// arithmetic on the originals.
+template <typename R, int N>
+struct MonCopy {
+    R v[N];
+    __device__ __forceinline__ explicit MonCopy(const R* x)
+    {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            v[i] = x[i];
+            pin(v[i]);
+        }
+    }
+};
+
+// Sum over the 64 lanes of a wave in a fixed butterfly order; every lane
+// ends with a sum, lane 0's is returned in scalar registers (the lanes may
+// round differently).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return uniform(v);
+}
+
+// MON: besides the stage, the constraint monitor of the stage input (Sec.
+// 2.3): H and M^i at every active point (into mon.c when set) and, per wave
+// of every brick, the sums of H^2 and (M^i)^2 over its points
+// (mon.part[(brick * NT/64 + wave) * 4 + m]), from the same staged fields and
+// derivatives as the right-hand side.
+template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA, bool MON = false>
 __global__ void __attribute__((amdgpu_flat_work_group_size(BX* BY* BZ, BX* BY* BZ)))
 __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
-fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
+fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
 {
     using T = Brick<R, BX, BY, BZ>;
     constexpr int NT = T::NT, SX = T::SX, SXY = T::SXY, TN = T::TN;
@@ -410,19 +440,40 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         // DMA staging (float64): each field's tile is loaded straight into one
         // of three LDS buffers two fields ahead of its use, without registers;
         // per round a wave moves 64 pairs of doubles into consecutive LDS.
-        int doff[DMA ? NR : 1];
+        // Not every tile element is read.  The one-direction stencils (first,
+        // second, upwind and dissipation differences) reach +-3 cells along
+        // one axis; the mixed second derivatives of the 11 fields that fill D1
+        // planes also reach the edges of the tile with both offsets <= 2.
+        // Pairs outside that set (the tile's corners) are not fetched: their
+        // lanes load the tile-centre pair instead, a line the same load
+        // fetches anyway, so the corners cost no extra L2 or HBM traffic.
+        // doff: offsets for the fields with mixed derivatives, doff1: for the
+        // others (one-direction stencils only).
+        int doff[DMA ? NR : 1], doff1[DMA ? NR : 1];
         const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
         if constexpr (DMA) {
+            const int oc = ((gz0 + 3 + BZ / 2) * Ny + (gy0 + 3 + BY / 2)) * Nx + (gx0 + 4);
+            // distance of tile coordinate c outside the brick [3, 3 + Bn)
+            auto outd = [](int c, int Bn) { return c < 3 ? 3 - c : (c >= 3 + Bn ? c - 2 - Bn : 0); };
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const int e = 2 * (r * NT + tid);
                 int o = 0;  // slots outside the stored box read a harmless valid address
+                int o1 = 0;
                 if (e < TN) {
                     const int lx = e % SX, ly = (e / SX) % T::SY, lz = e / SXY;
                     const int gi = gx0 + lx, gj = gy0 + ly, gk = gz0 + lz;
+                    const int dx0 = outd(lx, BX), dx1 = outd(lx + 1, BX);
+                    const int dx = dx0 < dx1 ? dx0 : dx1, dy = outd(ly, BY), dz = outd(lz, BZ);
+                    const int nz = (dx > 0) + (dy > 0) + (dz > 0);
+                    const bool need1 = nz <= 1;
+                    const bool needm = need1 || (nz == 2 && dx <= 2 && dy <= 2 && dz <= 2);
                     if (gi < Nx && gj < Ny && gk < Nz) o = (gk * Ny + gj) * Nx + gi;
+                    o1 = need1 ? o : oc;
+                    if (!needm) o = oc;
                 }
                 doff[r] = o;
+                doff1[r] = o1;
             }
         } else {
 #pragma unroll
@@ -437,11 +488,13 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
                 goff[r] = o;
             }
         }
-        auto dma_issue = [&](int f, int k) {
-            const double* src = B.u_in + f * sf;
+        auto dma_issue = [&](int i, int k) {
+            const double* src = B.u_in + seq(i) * sf;
             TT* dst = tilebuf(k) + 2 * 64 * wave;
+            // sequence positions of gt, W, alpha and beta (the fields with D1 planes)
+            const bool mixed = i < 6 || i == 9 || i == 10 || (i >= 13 && i < 16);
 #pragma unroll
-            for (int r = 0; r < NR; ++r) lds_dma16(src + doff[r], (lds_void*)(dst + 2 * NT * r));
+            for (int r = 0; r < NR; ++r) lds_dma16(src + (mixed ? doff[r] : doff1[r]), (lds_void*)(dst + 2 * NT * r));
         };
         auto prefetch = [&](int f) {
             const double* src = B.u_in + f * sf;
@@ -476,7 +529,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
                 wait_fields(later);
                 __builtin_amdgcn_s_waitcnt(LGKM0);
                 bar();
-                if (i + DIST < NSEQ) dma_issue(seq(i + DIST), (i + DIST) % NBUF);
+                if (i + DIST < NSEQ) dma_issue(i + DIST, (i + DIST) % NBUF);
                 tb = tilebuf(i % NBUF);
                 t = tb + cofs;
             } else {
@@ -494,7 +547,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         };
         if constexpr (DMA) {
 #pragma unroll
-            for (int k = 0; k < DIST; ++k) dma_issue(seq(k), k);
+            for (int k = 0; k < DIST; ++k) dma_issue(k, k);
         } else {
             prefetch(seq(0));
         }
@@ -677,6 +730,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         //     At_ij At^ij and Gamma^a_jk At^jk now, so that C2 dies with the
         //     lapse below
         R At[6], Auu[6], AA, nG[3];  // nG: Gt source without advection/dissipation
+        R mp[MON ? 3 : 1];           // monitor: M^i / W^2 without the gt gt d At term
         {
 #pragma unroll
             for (int q = 0; q < 6; ++q) At[q] = get_lds(P_AT0 + q);
@@ -694,6 +748,37 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             AA = tr6(Auu, At);
 #pragma unroll
             for (int a = 0; a < 3; ++a) nG[a] = tr6(C2[a], Auu);  // scaled by 2 alpha below
+            if constexpr (MON) {
+                // connection terms of the covariant divergence in M^i: with
+                // Am_c^j = gt^jb At_cb,
+                //   D_j At^ij = gt^ia gt^jb d_j At_ab - gt^ia Gamma^c_ja Am_c^j - Gtd^c Am_c^i
+                // The monitor's products start from opaque copies (of At here):
+                // a product it shared with the right-hand side (Am is At^i_j
+                // there) would change how the compiler fuses multiplies and
+                // adds in the right-hand side, and with them the stage's bits.
+                const MonCopy<R, 6> a6(At);
+                R Am[3][3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        Am[c][j] = gu[S(j, 0)] * a6.v[S(c, 0)] + gu[S(j, 1)] * a6.v[S(c, 1)] + gu[S(j, 2)] * a6.v[S(c, 2)];
+                R Tm[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    R t = R(0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) t += C2[c][S(j, a)] * Am[c][j];
+                    Tm[a] = t;
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    mp[i] = -(gu[S(i, 0)] * Tm[0] + gu[S(i, 1)] * Tm[1] + gu[S(i, 2)] * Tm[2])
+                          - (Gtd[0] * Am[0][i] + Gtd[1] * Am[1][i] + Gtd[2] * Am[2][i]);
+                pin(mp);
+            }
             pin(At);
             pin(Auu);
             pin(AA);
@@ -740,6 +825,13 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
                 for (int j = 0; j < 3; ++j) dW2 += gu[S(i, j)] * dW[i] * dW[j];
 #pragma unroll
             for (int q = 0; q < 6; ++q) W2R[q] = W * W * Rt[q] + W * (DDW[q] + gt[q] * trDDW) - R(2) * gt[q] * dW2;
+            if constexpr (MON) {
+                const MonCopy<R, 3> dw(dW);  // Auu . dW is also a term of the Gt source
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    mp[a] -= R(3) * (Auu[S(a, 0)] * dw.v[0] + Auu[S(a, 1)] * dw.v[1] + Auu[S(a, 2)] * dw.v[2]) / W;
+                pin(mp);
+            }
             pin(dW);
             pin(W2R);
         }
@@ -796,6 +888,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         const R kap1 = R(prm.kappa1), kap3 = R(prm.kappa3);
         const R th1 = uniform(kap1 * (R(1) - R(prm.kappa2))), th2 = uniform(kap1 * (R(2) + R(prm.kappa2)));
         R K;
+        double mon_h2 = 0.0;  // monitor: this wave's sum of H^2 (scalar registers)
         {
             stage_field(11);
             const R Kh = tval(F_KH);
@@ -803,6 +896,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
             const R ak_kh = advko(pk);
             R dkt[3];
             grad(pk, dkt);
+            R dK[MON ? 3 : 1];  // monitor: d K = d Khat + 2 d Theta
+            if constexpr (MON) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dK[j] = dkt[j];
+                pin(dK);
+            }
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] *= R(2);
             pin(dkt);
@@ -815,6 +914,21 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
 #pragma unroll
             for (int j = 0; j < 3; ++j) dkt[j] += d[j];
             K = Kh + R(2) * Th;
+            if constexpr (MON) {
+                // -(2/3) gt^ij d_j K, and H = R - At_ij At^ij + (2/3) K^2
+                const MonCopy<R, 3> dt(d);
+                const MonCopy<R, 6> g6(gu);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dK[j] += R(2) * dt.v[j];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    mp[a] -= R(2.0 / 3.0) * (g6.v[S(a, 0)] * dK[0] + g6.v[S(a, 1)] * dK[1] + g6.v[S(a, 2)] * dK[2]);
+                const MonCopy<R, 1> ric(&Ric), aa(&AA), kk(&K);
+                const double H = double(ric.v[0] - aa.v[0] + R(2.0 / 3.0) * kk.v[0] * kk.v[0]);
+                if (valid && mon.c) mon.c[p] = H;
+                mon_h2 = wave_sum(valid ? H * H : 0.0);
+                pin(mp);
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const R t_dk = gu[S(a, 0)] * dkt[0] + gu[S(a, 1)] * dkt[1] + gu[S(a, 2)] * dkt[2];
@@ -887,11 +1001,34 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         }
 
         // --- traceless curvature and B: advection and dissipation only
+        R mdiv[MON ? 3 : 1] = {};  // monitor: gt^ia gt^jb d_j At_ab
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             stage_field(16 + q);
             k[F_GT + q] = double(kgt[q]);
-            k[F_AT + q] = double(kat[q] + advko(field_pairs()));
+            const P3 pq = field_pairs();
+            k[F_AT + q] = double(kat[q] + advko(pq));
+            if constexpr (MON) {
+                const MonCopy<R, 6> g6(gu);
+                R d[3];
+                grad(pq, d);
+                pin(d);
+                // component q = (c, e) stands for At_ce and At_ec
+                const int c = q < 3 ? 0 : (q < 5 ? 1 : 2);
+                const int e = q < 3 ? q : (q < 5 ? q - 2 : 2);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    R t = R(0);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        R wgt = g6.v[S(a, c)] * g6.v[S(j, e)];
+                        if (c != e) wgt += g6.v[S(a, e)] * g6.v[S(j, c)];
+                        t += wgt * d[j];
+                    }
+                    mdiv[a] += t;
+                }
+                pin(mdiv);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -907,6 +1044,23 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage)
         k[F_AL] = double(get_lds(P_KAL));
         k[F_W] = double(get_lds(P_KW));
 
+        if constexpr (MON) {
+            double m2[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const MonCopy<R, 1> wm(&W);
+                const double M = double(wm.v[0] * wm.v[0] * (mdiv[a] + mp[a]));
+                if (valid && mon.c) mon.c[(size_t)(a + 1) * (size_t)B.sf + p] = M;
+                m2[a] = wave_sum(valid ? M * M : 0.0);
+            }
+            if ((tid & 63) == 0) {
+                double* out = mon.part + ((size_t)w * (NT / 64) + (size_t)(tid >> 6)) * 4;
+                out[0] = mon_h2;
+                out[1] = m2[0];
+                out[2] = m2[1];
+                out[3] = m2[2];
+            }
+        }
         if (!valid) continue;  // no barrier below this point
         finish_point<true>(B, mode, stage, [&](int f) { return k[f]; }, p);
     }
@@ -924,8 +1078,9 @@ inline bool dma_compatible(const BoxSet& set)
     return true;
 }
 
-template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA>
-hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s)
+template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA, bool MON = false>
+hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s,
+                          MonDev mon = MonDev{})
 {
     const long total = set.brick_begin[set.nbox];
     if (total <= 0) return hipSuccess;
@@ -936,16 +1091,16 @@ hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int s
         int dev = 0, cus = 0, per = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES, DMA>, BX * BY * BZ,
-                                                           0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WAVES, DMA, MON>,
+                                                           BX * BY * BZ, 0);
         cap = cus * (per > 0 ? per : 1);
     }
     if (persistent) {
         if (grid > cap) grid = cap;
     }
     grid = (grid + 7) / 8 * 8;  // whole XCD rounds (idle blocks exit at once)
-    hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES, DMA>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s,
-                       *run, p, mode, stage);
+    hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES, DMA, MON>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s,
+                       *run, p, mode, stage, mon);
     return hipGetLastError();
 }
 
@@ -957,6 +1112,19 @@ hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int sta
     }
     return launch_variant<R, BX, BY, BZ, WAVES, false>(set, p, mode, stage, persistent, s);
 }
+
+}  // namespace
+
+// One float64 stage with the constraint monitor of its input (single box,
+// 8x8x8 bricks with two waves per SIMD, persistent).
+long monitor_bricks(const int n[3]) { return (long)((n[0] + 7) / 8) * ((n[1] + 7) / 8) * ((n[2] + 7) / 8); }
+hipError_t launch_stage_monitor(const BoxSet& set, const ParamsDev& p, int mode, int stage, MonDev mon, hipStream_t s)
+{
+    if (dma_compatible(set)) return launch_variant<double, 8, 8, 8, 2, true, true>(set, p, mode, stage, 1, s, mon);
+    return launch_variant<double, 8, 8, 8, 2, false, true>(set, p, mode, stage, 1, s, mon);
+}
+
+namespace {
 
 // ------------------------------------------------------------------------
 // Ghost shells: thread q of a box enumerates its ghost points in the

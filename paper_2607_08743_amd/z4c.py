@@ -88,6 +88,9 @@ def lib(path: str = LIB_PATH):
     L.z4c_default_params.restype = None
     L.rhs_z4c.argtypes = [dp, dp] + geo + [pp, vp]
     L.rk4_substep.argtypes = [i, d, dp, dp, dp, dp] + geo + [pp, vp]
+    L.rk4_substep_monitor.argtypes = [i, d, dp, dp, dp, dp] + geo + [pp, dp, dp, dp, l, vp]
+    L.z4c_monitor_workspace.argtypes = [i, i, i]
+    L.z4c_monitor_workspace.restype = l
     L.apply_ghosts.argtypes = [dp, dp, l, i, i, i, i, i, vp]
     L.z4c_tile_count.argtypes = [i]
     L.z4c_tile_get.argtypes = [i, i, ctypes.POINTER(Tile)]
@@ -116,7 +119,7 @@ def lib(path: str = LIB_PATH):
     L.z4c_strerror.restype = ctypes.c_char_p
     L.z4c_last_error.argtypes = []
     L.z4c_last_error.restype = ctypes.c_char_p
-    for name in ("rhs_z4c", "rk4_substep", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
+    for name in ("rhs_z4c", "rk4_substep", "rk4_substep_monitor", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
                  "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints",
                  "z4c_plan_tile", "z4c_autotune", "z4c_tune_lookup", "z4c_constraints_noalloc",
                  "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy", "z4c_hier_set_moving", "z4c_hier_puncture"):
@@ -188,6 +191,33 @@ def rk4_substep(stage, dt, u_in, u_n, acc, u_out, g: _inputs.Grid, params: Param
     p = params or default_params()
     check(lib().rk4_substep(int(stage), float(dt), _ptr(u_in), _ptr(u_n), _ptr(acc), _ptr(u_out),
                             *_geo(g, g.stored), ctypes.byref(p), _stream(stream)), "rk4_substep")
+
+
+def monitor_workspace(g: _inputs.Grid) -> int:
+    """Doubles of device workspace rk4_substep_monitor needs for this box."""
+    return int(lib().z4c_monitor_workspace(int(g.n[0]), int(g.n[1]), int(g.n[2])))
+
+
+def rk4_substep_monitor(stage, dt, u_in, u_n, acc, u_out, g: _inputs.Grid, params: Params = None, c=None, norms=None,
+                        ws=None, stream=None):
+    """One float64 RK4 stage fused with the constraint monitor of u_in.
+    Returns the (4,) tensor of L2 norms (H, M^x, M^y, M^z); c, if given, a
+    (4, Nz, Ny, Nx) float64 CUDA tensor, receives the per-point values."""
+    import torch
+    for t, nm in ((u_in, "u_in"), (u_n, "u_n"), (acc, "acc"), (u_out, "u_out")):
+        _state_tensor(t, g, nm)
+    if c is not None and (c.dtype != torch.float64 or not c.is_cuda or not c.is_contiguous()
+                          or tuple(c.shape) != (4,) + tuple(g.shape[1:])):
+        raise TypeError("c must be a contiguous float64 CUDA tensor of shape (4, Nz, Ny, Nx)")
+    p = params or default_params()
+    if norms is None:
+        norms = torch.empty(4, dtype=torch.float64, device=u_in.device)
+    if ws is None:
+        ws = torch.empty(max(monitor_workspace(g), 1), dtype=torch.float64, device=u_in.device)
+    check(lib().rk4_substep_monitor(int(stage), float(dt), _ptr(u_in), _ptr(u_n), _ptr(acc), _ptr(u_out),
+                                    *_geo(g, g.stored), ctypes.byref(p), _ptr(c), _ptr(norms), _ptr(ws),
+                                    ctypes.c_long(ws.numel()), _stream(stream)), "rk4_substep_monitor")
+    return norms
 
 
 def apply_ghosts(u, g: _inputs.Grid, shell=None, stream=None):

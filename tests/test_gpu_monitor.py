@@ -1,0 +1,112 @@
+"""The constraint monitor fused into an RK4 stage (rk4_substep_monitor),
+through the C ABI: the stage itself is bitwise that of rk4_substep, and the
+Hamiltonian and momentum constraints of the stage input match the FP64
+oracle's monitor (Sec. 2.3) per constraint within max(1e-12, 20 x the
+oracle's own one-ulp input sensitivity) -- on constraint-satisfying data
+they are O(h^4) cancellations of O(1) terms, so their rounding floor is set
+by those terms -- with zero ghost entries and exact zeros on flat space."""
+import numpy as np
+import pytest
+import torch
+
+import analytic as A
+from gpu_helpers import normrel, to_dev, to_host
+from paper_2607_08743_amd import inputs as I
+from paper_2607_08743_amd import z4c
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _run(u, g, dt, stage=1):
+    """rk4_substep_monitor and rk4_substep on the same inputs: (u_out, acc,
+    c, norms) of the first, (u_out, acc) of the second."""
+    du = to_dev(u)
+    if g.bc == I.BC_PERIODIC:
+        z4c.apply_ghosts(du, g)  # copy boxes keep the (analytic) ghosts they come with
+    un = du.clone() * 1.0
+    outs = []
+    for mon in (True, False):
+        acc = torch.full_like(du, 0.25)
+        out = torch.full_like(du, float("nan"))
+        if mon:
+            c = torch.full((4,) + tuple(g.shape[1:]), float("nan"), dtype=torch.float64, device="cuda")
+            norms = z4c.rk4_substep_monitor(stage, dt, du, un, acc, out, g, c=c)
+            outs.append((to_host(out), to_host(acc), to_host(c), to_host(norms)))
+        else:
+            z4c.rk4_substep(stage, dt, du, un, acc, out, g)
+            outs.append((to_host(out), to_host(acc)))
+    return outs, to_host(du)
+
+
+def _oracle(oz, u, g, seed=0):
+    c, n = oz.constraints(u, g.as_dict())
+    rng = np.random.default_rng(seed)
+    v = u + np.spacing(u) * rng.choice([-1.0, 1.0], size=u.shape)
+    c2, n2 = oz.constraints(v, g.as_dict())
+    m = g.active_mask()
+    return c, n, normrel(c2, c, m), np.abs(n2 - n) / np.maximum(np.abs(n), 1e-300)
+
+
+@pytest.mark.parametrize("case", ["strong_periodic", "ragged_periodic", "kerr_schild_copy", "punctures_sommerfeld"])
+@pytest.mark.parametrize("stage", [1, 3])
+def test_monitor_stage_parity(oz, case, stage):
+    print(f"case: stage monitor {case} stage {stage}", flush=True)
+    if case == "strong_periodic":
+        g = I.centered_grid(24, 0.1, bc=I.BC_PERIODIC)
+        u = I.random_strong_field_state(g)
+    elif case == "ragged_periodic":
+        g = I.Grid((13, 11, 7), (0.1, 0.12, 0.09), (-0.6, -0.6, -0.3), I.BC_PERIODIC)
+        u = I.random_strong_field_state(g, seed=3)
+    elif case == "kerr_schild_copy":
+        g = I.centered_grid(16, 1.0 / 16, center=(3.0, 2.5, 2.0), bc=I.BC_COPY)
+        u = A.evaluate(A.conformal_state_fn(A.kerr_schild_prim(B_amp=0.3)), g)
+    else:
+        g, u, _ = I.config_punctures(32)
+    dt = 0.25 * min(g.h)
+    (mon, plain), u_used = _run(u, g, dt, stage)
+    # the stage is untouched by the monitor (both outputs start as NaN: the
+    # ghosts of a periodic or copy box are not written by a stage)
+    assert np.array_equal(mon[0], plain[0], equal_nan=True) and np.array_equal(mon[1], plain[1], equal_nan=True)
+    assert np.all(np.isfinite(mon[0][:, g.active_mask()]))
+    c, n = mon[2], mon[3]
+    cr, nr, sc, sn = _oracle(oz, u_used, g)
+    m = g.active_mask()
+    e = normrel(c, cr, m)
+    en = np.abs(n - nr) / np.maximum(np.abs(nr), 1e-300)
+    print("H, M^i normrel:", " ".join(f"{x:.1e}" for x in e), " oracle sensitivity:",
+          " ".join(f"{x:.1e}" for x in sc))
+    print("L2 norms:", n, "oracle:", nr)
+    assert np.all(c[:, ~m] == 0.0)
+    assert np.all(e <= np.maximum(TOL, 20 * sc)), e
+    assert np.all(en <= np.maximum(TOL, 20 * sn)), en
+
+
+def test_monitor_flat_space_exact():
+    print("case: stage monitor flat space", flush=True)
+    g = I.centered_grid(16, 0.1, bc=I.BC_PERIODIC)
+    (mon, _), _ = _run(I.flat_state(g), g, 0.05)
+    assert np.all(mon[2] == 0.0) and np.all(mon[3] == 0.0)
+
+
+def test_monitor_full_size_against_standalone():
+    """128^3 punctures (4096 bricks, persistent blocks walking several):
+    the fused monitor's per-point constraints against the standalone GPU
+    monitor's, norm-relative within 1e-12 (two float64 evaluations of the
+    same stencils and algebra, summed in different orders)."""
+    print("case: stage monitor 128^3 punctures vs standalone monitor", flush=True)
+    g, u, dt = I.config_punctures(128)
+    du = to_dev(u)
+    del u
+    acc, out = torch.empty_like(du), torch.empty_like(du)
+    c = torch.empty((4,) + tuple(g.shape[1:]), dtype=torch.float64, device="cuda")
+    n = to_host(z4c.rk4_substep_monitor(1, dt, du, None, acc, out, g, c=c))
+    c_ref = torch.empty_like(c)
+    n_ref = to_host(z4c.constraints(du, g, c=c_ref))
+    e = normrel(to_host(c), to_host(c_ref))
+    print("fused vs standalone per constraint:", e, "norms", n, n_ref)
+    assert np.all(e[0:1] <= TOL)  # H; M^i vanish identically on time-symmetric data
+    assert np.all(np.abs(to_host(c)[1:]) <= TOL * np.abs(to_host(c)[0]).max())
+    assert abs(n[0] - n_ref[0]) <= TOL * n_ref[0]
+    del du, acc, out, c, c_ref
+    torch.cuda.empty_cache()

@@ -29,9 +29,15 @@ something other than itself):
   evolution uses no reflection code), and its ghost fill matches the parity
   rule written out independently in the test.
 
-Parity unpinned (no physics pin distinguishes them; both paths must agree):
-the kappa3 terms (default 0), ``lapse_uses_K`` and the use of the computed
-Gamma_d in the Lie-derivative terms of the Gt equation.
+* shift terms of the Gt equation on data with Gt != Gt_d and a shift: the
+  right-hand side's shift-dependent part converges at 4th order to
+  -d_j (L_beta gt^ij) plus the transport of Zt = (Gt - Gt_d)/2 (advection
+  for kappa3 = 0, the full Lie derivative of the density for kappa3 = 1),
+  differentiated exactly: this pins the computed Gamma_d in the
+  Lie-derivative terms and the kappa3 terms.
+
+Parity unpinned (no physics pin distinguishes the alternatives; both paths
+must agree): ``lapse_uses_K`` (1+log with Khat or Khat + 2 Theta).
 """
 from __future__ import annotations
 

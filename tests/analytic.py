@@ -298,3 +298,89 @@ def brill_lindquist_prim(masses=(0.5, 0.5), centres=((5.0, 0.0, 0.0), (-5.0, 0.0
         return g, torch.zeros(3, 3, dtype=DT), psi ** -2.0, z3, z3
 
     return prim
+
+
+# ---------------------------------------------------------------------------
+# Shift terms of the Gt equation with Z != 0
+# ---------------------------------------------------------------------------
+
+def shifted_z_prim(eps=0.1, beps=0.2):
+    """generic_prim's metric, curvature and lapse with a smooth non-zero
+    shift beta^i(x) (B = 0)."""
+    base = generic_prim(eps)
+
+    def prim(x):
+        g, K, a, _, B = base(x)
+        X, Y, Z = x[0], x[1], x[2]
+        s, c = torch.sin, torch.cos
+        b = beps * torch.stack([s(Y + 0.5 * Z) + 0.3, c(X - Z) * 0.7, s(X + Y) * c(Z)])
+        return g, K, a, b, B
+
+    return prim
+
+
+def zt_field(zeps=0.05):
+    """A smooth vector field Zt^i(x) standing for (Gt^i - Gt_d^i)/2 (a
+    constraint violation carried by the evolved Gt)."""
+
+    def zt(x):
+        X, Y, Z = x[0], x[1], x[2]
+        s, c = torch.sin, torch.cos
+        return zeps * torch.stack([c(2 * X + Y), s(Y - Z) + 0.5, c(X) * s(2 * Z)])
+
+    return zt
+
+
+def conformal_state_with_z_fn(prim, zt):
+    """conformal_state_fn(prim) with Gt^i = Gt_d^i + 2 Zt^i (Gt_d = -d_j gt^ij)."""
+    st = conformal_state_fn(prim)
+
+    def state(x):
+        u = st(x)
+        return torch.cat([u[:14], u[14:17] + 2.0 * zt(x), u[17:]])
+
+    return state
+
+
+def gt_shift_part_fn(prim, zt, kappa3):
+    """x -> 25-vector holding, in rows 14-16, the part of d_t Gt^i that
+    depends on the shift, from geometric objects differentiated exactly:
+      -d_j (L_beta gt^ij)  +  2 (beta^k d_k Zt^i + kappa3 (Zt^i d_k beta^k 2/3 - Zt^k d_k beta^i)).
+    L_beta gt_ij = beta^k d_k gt_ij + gt_ik d_j beta^k + gt_jk d_i beta^k - (2/3) gt_ij d_k beta^k is
+    the Lie derivative of the weight -2/3 density gt_ij; with det gt = 1,
+    Gt_d^i = -d_j gt^ij, so the first term is the shift part of d_t Gt_d.
+    For kappa3 = 1 the second is twice the Lie derivative of the weight 2/3
+    vector density Zt^i (the transport of the constraint violation by the
+    shift); for kappa3 = 0 only its advection."""
+    def gt_low(x):
+        g = prim(x)[0]
+        W = _det3(g) ** (-1.0 / 6.0)
+        return W * W * g
+
+    dgt = jacfwd(gt_low)  # [i, j, k] = d_k gt_ij
+    beta = lambda x: prim(x)[3]
+    dbeta = jacfwd(beta)  # [i, k] = d_k beta^i
+    dzt = jacfwd(zt)
+
+    def lie_gt_inv(x):
+        gt = gt_low(x)
+        gti = _inv3(gt)
+        b = beta(x)
+        db = dbeta(x)
+        div = torch.trace(db)
+        lie = (torch.einsum("k,ijk->ij", b, dgt(x)) + gt @ db + (gt @ db).T - (2.0 / 3.0) * gt * div)
+        return -gti @ lie @ gti  # L_beta of gt^ij
+
+    d_lie = jacfwd(lie_gt_inv)  # [i, j, m]
+
+    def expected(x):
+        b = beta(x)
+        db = dbeta(x)
+        z = zt(x)
+        dz = dzt(x)  # [i, k] = d_k Zt^i
+        part = -torch.einsum("ijj->i", d_lie(x)) + 2.0 * (dz @ b + kappa3 * ((2.0 / 3.0) * z * torch.trace(db)
+                                                                              - db @ z))
+        out = torch.zeros(25, dtype=DT)
+        return torch.cat([out[:14], part, out[17:]])
+
+    return expected

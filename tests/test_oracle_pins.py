@@ -8,6 +8,7 @@ must converge at 4th order.  A dropped term, a wrong sign or a transposed
 index in any geometric row leaves an O(1) residual that does not converge.
 """
 import numpy as np
+import torch
 import pytest
 
 import analytic as A
@@ -100,3 +101,45 @@ def test_lapse_flag_uses_full_trace(oz):
     r1 = oz.rhs(u, g.as_dict(), oz.params(ko_sigma=0.0, lapse_uses_K=1))
     np.testing.assert_allclose(r0[18][m], -2 * 0.01)
     np.testing.assert_allclose(r1[18][m], -2 * (0.01 + 2 * 0.02))
+
+
+@pytest.mark.parametrize("kappa3", [0.0, 1.0])
+def test_gt_shift_terms_with_constraint_violation(oz, kappa3):
+    """The shift terms of the Gt equation on data with Gt != Gt_d (a
+    constraint violation Zt) and a non-zero shift: the oracle's right-hand
+    side minus the same data's right-hand side with beta = 0 converges at 4th
+    order to -d_j (L_beta gt^ij) + 2 beta.d Zt (+ for kappa3 = 1 the rest of
+    the Lie derivative of the density Zt), differentiated exactly.  This pins
+    the use of the computed Gt_d in the Lie-derivative terms and the kappa3
+    terms (their sign, density weight and the components they act on)."""
+    p = oz.params(ko_sigma=0.0, kappa3=kappa3)
+    prim = A.shifted_z_prim()
+    zt = A.zt_field()
+    noshift = lambda x: prim(x)[:3] + (torch.zeros(3, dtype=A.DT), torch.zeros(3, dtype=A.DT))
+    errs, scales = [], []
+    for n in (8, 16):
+        g = I.centered_grid(n, 1.0 / n, center=(0.3, -0.2, 0.1), bc=I.BC_COPY)
+        u = A.evaluate(A.conformal_state_with_z_fn(prim, zt), g)
+        u0 = A.evaluate(A.conformal_state_with_z_fn(noshift, zt), g)
+        d = oz.rhs(u, g.as_dict(), p) - oz.rhs(u0, g.as_dict(), p)
+        ex = A.evaluate(A.gt_shift_part_fn(prim, zt, kappa3), g, only_active=True)
+        m = g.active_mask()
+        errs.append(np.abs(d - ex)[14:17][:, m].max(axis=1))
+        scales.append(np.abs(ex)[14:17][:, m].max(axis=1))
+    errs, scales = np.array(errs), np.array(scales)
+    print("kappa3", kappa3, "errors", errs, "scales", scales)
+    assert scales[-1].min() > 1e-2
+    _assert_fourth_order(errs)
+    assert errs[-1].max() < 1e-5
+
+
+def test_kappa3_terms_differ():
+    """The two kappa3 expectations differ by O(1) on this data, so the test
+    above tells them apart (a dropped or sign-flipped kappa3 term fails it)."""
+    prim = A.shifted_z_prim()
+    zt = A.zt_field()
+    g = I.centered_grid(8, 1.0 / 8, center=(0.3, -0.2, 0.1), bc=I.BC_COPY)
+    e0 = A.evaluate(A.gt_shift_part_fn(prim, zt, 0.0), g, only_active=True)
+    e1 = A.evaluate(A.gt_shift_part_fn(prim, zt, 1.0), g, only_active=True)
+    m = g.active_mask()
+    assert np.abs(e1 - e0)[14:17][:, m].max() > 1e-3

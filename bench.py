@@ -39,8 +39,8 @@ TUNE_CACHE = os.path.join(ROOT, "paper_2607_08743_amd", "tune_cache.jsonl")
 # Keyed by the SHA-256 of the kernel source the counters were taken on: once
 # the source changes the figure no longer applies and `traffic` is null.
 MEASURED_TRAFFIC = {
-    "d765b957da3aec9295934bd13caac708ff336a63f716f492f72dda0a20f4142c": {"tile": (8, 8, 8, 2, 1), "n": 256, "bytes_per_launch": 23707200000,
-        "fetch_bytes": 17627300000, "write_bytes": 6079900000,
+    "615d3024739879020640f48b390c0450143bd88e943b241a587f9ff3ac20b1c9": {"tile": (8, 8, 8, 2, 1), "n": 256, "bytes_per_launch": 21972900000,
+        "fetch_bytes": 15868800000, "write_bytes": 6104100000,
         "profile": "profiles/fused_stage_256cube_punctures_fp64.md"},
 }
 
@@ -399,7 +399,6 @@ def main():
     extras["constraints"] = constraint_monitor_rate(z4c, torch, g, u0, args.n)
     if not args.no_extras:
         # the same puncture data on the 128^3 box (dx = 0.25), same tile
-        g2, u2, dt2 = I.config_punctures(128)
         g2, u2, dt2 = I.config_punctures(128)
         sec2, best2, src2, fin2 = run([I.Box(g2, u2, None, dt2)], params, None)
         extras["box128"] = {"value": g2.active * args.steps / sec2, "ms_per_step": 1e3 * sec2 / args.steps,

@@ -177,14 +177,14 @@ int z4c_constraints(const double* u, double* c, double* norms, double* ws, long 
  * workspace (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): the same kernels and the same fixed-order
  * reduction, with the block partial sums kept in a fixed device array of the
- * library (8 MiB, one copy per device, held until the process ends).  Hence
- * at most Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS bricks of 8x8x8 active cells
+ * library (16 MiB, one copy per device, held until the process ends).  Hence
+ * at most Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS bricks of 8x8x4 active cells
  * (a 512^3 box); a larger box fails with Z4C_EINVAL and enqueues nothing.
  * Results are bitwise those of z4c_constraints.  Calls no hipMalloc or
  * hipFree; the first call on a device looks the array's address up.  Every
  * call on one device shares that array: calls that overlap on a device
  * (other streams, other threads) race and must be serialised by the caller. */
-#define Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS 262144
+#define Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS 524288
 int z4c_constraints_noalloc(const double* u, double* c, double* norms, long sf, int nx, int ny, int nz, int ng,
                             double dx, double dy, double dz, void* stream);
 

@@ -1978,7 +1978,7 @@ extern "C" int z4c_constraints_noalloc(const double* u, double* c, double* norms
     const long nb = constraint_blocks(n);
     if (nb > Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS)
         return fail(Z4C_EINVAL, "box too large for z4c_constraints_noalloc: " + std::to_string(nb) +
-                                    " bricks of 8^3 cells, at most " +
+                                    " bricks of 8x8x4 cells, at most " +
                                     std::to_string((long)Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS) +
                                     " (use z4c_constraints with a workspace)");
     int dev = 0;

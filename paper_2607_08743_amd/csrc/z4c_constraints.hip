@@ -23,7 +23,10 @@ namespace z4c {
 
 namespace {
 
-constexpr int CX = 8, CY = 8, CZ = 8;  // brick of one block (one point per thread)
+// Brick of one block, one point per thread.  8x8x4 points (four waves) at
+// two waves per SIMD let two blocks share a CU, so that one block's tile
+// waits and barriers overlap the other's arithmetic.
+constexpr int CX = 8, CY = 8, CZ = 4;
 constexpr int CNT = CX * CY * CZ;
 
 // Tile geometry.  The stencils reach 2 cells (centred first, second and
@@ -95,7 +98,7 @@ constexpr int CNSEQ = 18;
 //   after Theta:  d K folded into gt^ij d_j K;
 //   per At field: gt^ia gt^jb d_j At_ab.
 template <bool DMA>
-__global__ void __launch_bounds__(CNT) constraints_kernel(BoxSet set, double* c_out, double* partial)
+__global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2, 8))) constraints_kernel(BoxSet set, double* c_out, double* partial)
 {
     using T = CTile<DMA>;
     constexpr int SX = T::SX, SXY = T::SXY, TN = T::TN, TNP = T::TNP, NR = T::NR, NE = T::NE;
@@ -472,19 +475,42 @@ __global__ void __launch_bounds__(CNT) constraints_kernel(BoxSet set, double* c_
     if (tid < 4) partial[w * 4 + tid] = red[tid * CNT];
 }
 
-// one block: fixed-order sum of the block partials, then the norms
-__global__ void __launch_bounds__(256) constraint_norms(const double* partial, long nblocks, double inv_cells,
-                                                        double* norms)
+// one block: fixed-order sum of the partial records (four values each), then
+// the norms.  A single block keeps the order fixed; 1024 threads with four
+// independent records in flight per thread keep enough loads outstanding to
+// read a few MiB of partials at cache speed.
+constexpr int NORM_T = 1024;
+__global__ void __launch_bounds__(NORM_T) constraint_norms(const double* partial, long nrec, double inv_cells,
+                                                           double* norms)
 {
-    __shared__ double red[4][256];
+    __shared__ double red[4][NORM_T];
     const int tid = threadIdx.x;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (long b = tid; b < nblocks; b += 256)
-        for (int m = 0; m < 4; ++m) s[m] += partial[b * 4 + m];
-    for (int m = 0; m < 4; ++m) red[m][tid] = s[m];
+    double s[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) s[j][m] = 0.0;
+    long r = tid;
+    for (; r + 3 * NORM_T < nrec; r += 4 * NORM_T) {
+        double v[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[j][m] = partial[(r + j * NORM_T) * 4 + m];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) s[j][m] += v[j][m];
+    }
+    for (; r < nrec; r += NORM_T)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) s[0][m] += partial[r * 4 + m];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) red[m][tid] = (s[0][m] + s[1][m]) + (s[2][m] + s[3][m]);
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
+    for (int k = NORM_T / 2; k > 0; k >>= 1) {
         if (tid < k)
+#pragma unroll
             for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + k];
         __syncthreads();
     }
@@ -506,7 +532,7 @@ long constraint_blocks(const int n[3])
 
 hipError_t launch_norms(const double* partial, long n, double inv_cells, double* norms, hipStream_t s)
 {
-    hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(256), 0, s, partial, n, inv_cells, norms);
+    hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(NORM_T), 0, s, partial, n, inv_cells, norms);
     return hipGetLastError();
 }
 
@@ -536,7 +562,7 @@ hipError_t launch_constraints(const BoxSet& set, double* c_out, double* norms, d
     else
         hipLaunchKernelGGL(constraints_kernel<false>, dim3(grid), dim3(CNT), 0, s, one, c_out, workspace);
     const double cells = (double)B.n[0] * B.n[1] * B.n[2];
-    hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(256), 0, s, workspace, nb, 1.0 / cells, norms);
+    hipLaunchKernelGGL(constraint_norms, dim3(1), dim3(NORM_T), 0, s, workspace, nb, 1.0 / cells, norms);
     return hipGetLastError();
 }
 

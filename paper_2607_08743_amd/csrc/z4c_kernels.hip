@@ -246,15 +246,6 @@ struct Brick {
     static constexpr int SY = BY + 6;
     static constexpr int SXY = SX * SY;
     static constexpr int TN = SXY * (BZ + 6);
-    // D1_y f on x in [-2, BX+2) x the brick, D1_z f on x, y in [-2, B+2) x the brick
-    // row pitch of the D1 planes: BX + 4 entries are used; 8-wide bricks pad
-    // to the tile pitch BX + 6 so that rows y and y+4 fall in disjoint LDS
-    // banks (see the lane order in fused_stage)
-    static constexpr int PX = BX == 8 ? BX + 6 : BX + 4;
-    static constexpr int GYN = PX * BY * BZ;
-    static constexpr int GZN = PX * (BY + 4) * BZ;
-    static constexpr int NGY = (GYN + NT - 1) / NT;
-    static constexpr int NGZ = (GZN + NT - 1) / NT;
 };
 
 // Opaque copy of N values: arithmetic on it shares no subexpression with
@@ -301,8 +292,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
     // the same NR rounds, so the tile is padded to NR * NT pairs.
     constexpr int NR = (TN / 2 + NT - 1) / NT;
     constexpr int TNP = DMA ? NR * NT * 2 : TN;
-    __shared__ R gyt[T::GYN];  // unscaled D1_y of the staged field (x-halo 2)
-    __shared__ R gzt[T::GZN];  // unscaled D1_z of the staged field (x- and y-halo 2)
     // Per-thread slots for values that are produced early and consumed late
     // (held advection terms, completed right-hand sides): parked in LDS
     // they take no registers across the staging sequence.  Slot s of thread
@@ -316,13 +305,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
     // slots stay in LDS.
     constexpr int BPC = (WAVES * 4 * 64) / NT > 0 ? (WAVES * 4 * 64) / NT : 1;  // blocks per CU
     constexpr int BUDGET = 163840 / BPC - 512;
-    constexpr int PLANES = (int)sizeof(R) * (T::GYN + T::GZN);
     constexpr int BUFB = (int)sizeof(TT) * TNP;
-    constexpr int NB_FIT = (BUDGET - PLANES - 16 * NT * (int)sizeof(R)) / BUFB;
+    constexpr int NB_FIT = (BUDGET - 16 * NT * (int)sizeof(R)) / BUFB;
     constexpr int NBUF = !DMA ? 1 : (WAVES > 1 || NB_FIT < 3) ? 3 : (NB_FIT > 7 ? 7 : NB_FIT);
     constexpr int DIST = NBUF - 1;  // fields in flight ahead of the staged one
     static_assert(!DMA || DIST * NR <= 63, "outstanding loads beyond the vmcnt range");
-    constexpr int PARK_FIT = (BUDGET - PLANES - NBUF * BUFB) / (NT * (int)sizeof(R));
+    constexpr int PARK_FIT = (BUDGET - NBUF * BUFB) / (NT * (int)sizeof(R));
     constexpr int NPARK = PARK_FIT < 0 ? 0 : (PARK_FIT > 16 ? 16 : PARK_FIT);
     __shared__ __attribute__((aligned(16))) TT tiles[NBUF * TNP];
     __shared__ __attribute__((aligned(16))) R park[(NPARK > 0 ? NPARK : 1) * NT];
@@ -345,23 +333,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
     const int cofs = (tz + 3) * SXY + (ty + 3) * SX + (tx + 3);
     const TT* tb = tiles;  // tile of the staged field
     const TT* t = tb + cofs;
-    constexpr int PX = T::PX;
-    const R* ty_c = gyt + (tz * BY + ty) * PX + (tx + 2);        // own slot in the D1_y plane
-    const R* tz_c = gzt + (tz * (BY + 4) + ty + 2) * PX + (tx + 2);  // own slot in the D1_z plane
-    // tile offsets of the D1-plane slots this thread fills (the same for every field)
-    int gy_src[T::NGY], gz_src[T::NGZ];
-#pragma unroll
-    for (int r = 0; r < T::NGY; ++r) {
-        const int e = tid + r * NT;
-        const int x = e % PX, y = (e / PX) % BY, z = e / (PX * BY);
-        gy_src[r] = x < BX + 4 ? (z + 3) * SXY + (y + 3) * SX + (x + 1) : -1;  // -1: row padding
-    }
-#pragma unroll
-    for (int r = 0; r < T::NGZ; ++r) {
-        const int e = tid + r * NT;
-        const int x = e % PX, y = (e / PX) % (BY + 4), z = e / (PX * (BY + 4));
-        gz_src[r] = x < BX + 4 ? (z + 3) * SXY + (y + 1) * SX + (x + 1) : -1;
-    }
 
     // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD one
     // contiguous chunk of the brick sequence and let its resident blocks
@@ -442,8 +413,9 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
         // per round a wave moves 64 pairs of doubles into consecutive LDS.
         // Not every tile element is read.  The one-direction stencils (first,
         // second, upwind and dissipation differences) reach +-3 cells along
-        // one axis; the mixed second derivatives of the 11 fields that fill D1
-        // planes also reach the edges of the tile with both offsets <= 2.
+        // one axis; the mixed second derivatives of the 11 fields that need
+        // them (gt, W, alpha, beta) also reach the edges of the tile with both
+        // offsets <= 2.
         // Pairs outside that set (the tile's corners) are not fetched: their
         // lanes load the tile-centre pair instead, a line the same load
         // fetches anyway, so the corners cost no extra L2 or HBM traffic.
@@ -491,7 +463,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
         auto dma_issue = [&](int i, int k) {
             const double* src = B.u_in + seq(i) * sf;
             TT* dst = tilebuf(k) + 2 * 64 * wave;
-            // sequence positions of gt, W, alpha and beta (the fields with D1 planes)
+            // sequence positions of gt, W, alpha and beta (the fields with mixed derivatives)
             const bool mixed = i < 6 || i == 9 || i == 10 || (i >= 13 && i < 16);
 #pragma unroll
             for (int r = 0; r < NR; ++r) lds_dma16(src + (mixed ? doff[r] : doff1[r]), (lds_void*)(dst + 2 * NT * r));
@@ -615,40 +587,23 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
             d[1] = (R(8) * q.y.b1 - q.y.b2) * fc.i12h[1];
             d[2] = (R(8) * q.z.b1 - q.z.b2) * fc.i12h[2];
         };
-        // Fill the D1_y / D1_z planes of the staged field (unscaled 4th-order
-        // first differences, the inner factor of the mixed derivatives), so
-        // that each mixed derivative needs 4 LDS reads instead of 16.
-        auto d1_planes = [&]() {
-            auto u1 = [&](int c, int st) {
-                return R(TT(8) * (tb[c + st] - tb[c - st]) - (tb[c + 2 * st] - tb[c - 2 * st]));
-            };
-#pragma unroll
-            for (int r = 0; r < T::NGY; ++r) {
-                const int e = tid + r * NT;
-                if ((r + 1 < T::NGY || e < T::GYN) && gy_src[r] >= 0) gyt[e] = u1(gy_src[r], SX);
-            }
-#pragma unroll
-            for (int r = 0; r < T::NGZ; ++r) {
-                const int e = tid + r * NT;
-                if ((r + 1 < T::NGZ || e < T::GZN) && gz_src[r] >= 0) gzt[e] = u1(gz_src[r], SXY);
-            }
-            if constexpr (DMA) {
-                __builtin_amdgcn_s_waitcnt(LGKM0);
-                bar();  // no memory fence: the next fields' loads stay in flight
-            } else {
-                __syncthreads();
-            }
+        // Mixed second difference of the staged field straight from the tile:
+        // the 4th-order first difference along sa of the 4th-order first
+        // difference along sb (16 LDS reads, unscaled).  No intermediate
+        // plane, so no barrier between filling and reading one.
+        auto mixd = [&](int sa, int sb) {
+            auto u1 = [&](int c) { return R(TT(8) * (t[c + sb] - t[c - sb]) - (t[c + 2 * sb] - t[c - 2 * sb])); };
+            return R(8) * (u1(sa) - u1(-sa)) - (u1(2 * sa) - u1(-2 * sa));
         };
-        auto outer = [&](const R* g, int st) { return R(8) * (g[st] - g[-st]) - (g[2 * st] - g[-2 * st]); };
-        // gradient and Hessian of the staged field (mixed terms from the D1 planes)
+        // gradient and Hessian of the staged field
         auto grad_hess = [&](const P3& q, R* d, R* dd) {
             grad(q, d);
             dd[0] = (R(16) * q.x.a1 - q.x.a2) * fc.i12h2[0];
             dd[3] = (R(16) * q.y.a1 - q.y.a2) * fc.i12h2[1];
             dd[5] = (R(16) * q.z.a1 - q.z.a2) * fc.i12h2[2];
-            dd[1] = outer(ty_c, 1) * fc.imix[0];
-            dd[2] = outer(tz_c, 1) * fc.imix[1];
-            dd[4] = outer(tz_c, PX) * fc.imix[2];
+            dd[1] = mixd(1, SX) * fc.imix[0];
+            dd[2] = mixd(1, SXY) * fc.imix[1];
+            dd[4] = mixd(SX, SXY) * fc.imix[2];
         };
 
         // The right-hand side of each field is completed as soon as its inputs
@@ -666,7 +621,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 stage_field(q);
-                d1_planes();
                 const P3 pq = field_pairs();
                 put_lds(P_AKGT + q, advko(pq));
                 R dd[6];
@@ -809,7 +763,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
         R W, dW[3], W2R[6], ak_w;
         {
             stage_field(9);
-            d1_planes();
             W = tval(F_W);
             const P3 pq = field_pairs();
             ak_w = advko(pq);
@@ -840,7 +793,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
         R al, ak_al, Ric, Lapa, Xtf[6];
         {
             stage_field(10);
-            d1_planes();
             al = tval(F_AL);
             const P3 pq = field_pairs();
             ak_al = advko(pq);
@@ -915,11 +867,17 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
             for (int j = 0; j < 3; ++j) dkt[j] += d[j];
             K = Kh + R(2) * Th;
             if constexpr (MON) {
-                // -(2/3) gt^ij d_j K, and H = R - At_ij At^ij + (2/3) K^2
-                const MonCopy<R, 3> dt(d);
+                // -(2/3) gt^ij d_j K, and H = R - At_ij At^ij + (2/3) K^2.
+                // The monitor forms its own d Theta from opaque copies of the
+                // differences: a second use of the right-hand side's d Theta
+                // products would keep the compiler from fusing them into the
+                // sums 2 d Khat + d Theta, and change the stage's bits.
+                const R tdif[6] = {pt.x.b1, pt.x.b2, pt.y.b1, pt.y.b2, pt.z.b1, pt.z.b2};
+                const MonCopy<R, 6> db(tdif);
                 const MonCopy<R, 6> g6(gu);
 #pragma unroll
-                for (int j = 0; j < 3; ++j) dK[j] += R(2) * dt.v[j];
+                for (int j = 0; j < 3; ++j)
+                    dK[j] += R(2) * ((R(8) * db.v[2 * j] - db.v[2 * j + 1]) * fc.i12h[j]);
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     mp[a] -= R(2.0 / 3.0) * (g6.v[S(a, 0)] * dK[0] + g6.v[S(a, 1)] * dK[1] + g6.v[S(a, 2)] * dK[2]);
@@ -948,7 +906,6 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 stage_field(13 + a);
-                d1_planes();
                 const P3 pq = field_pairs();
                 put_lds(P_AKBE + a, advko(pq));
                 R dd[6];

@@ -266,9 +266,9 @@ def test_library_shares_torch_hip_runtime():
 
 
 def test_constraints_workspace_size(L):
-    # one partial per 8x8x8 brick of the active box, four constraints each
-    assert L.z4c_constraints_workspace(256, 256, 256) == 4 * 32 * 32 * 32
-    assert L.z4c_constraints_workspace(9, 8, 9) == 4 * 2 * 1 * 2
+    # one partial per 8x8x4 brick of the active box, four constraints each
+    assert L.z4c_constraints_workspace(256, 256, 256) == 4 * 32 * 32 * 64
+    assert L.z4c_constraints_workspace(9, 8, 9) == 4 * 2 * 1 * 3
     assert L.z4c_constraints_workspace(0, 8, 8) == 0
 
 
@@ -431,9 +431,9 @@ def test_missing_library_fails_loudly():
 
 def test_constraints_noalloc_validation(L):
     """The allocation-free monitor refuses boxes beyond its fixed array (more
-    than Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS bricks of 8^3) and bad arguments
+    than Z4C_CONSTRAINTS_NOALLOC_MAX_BLOCKS bricks of 8x8x4) and bad arguments
     before any HIP call."""
-    n = 520  # 65^3 = 274625 bricks > 262144
+    n = 520  # 65 x 65 x 130 = 549250 bricks > 524288
     sf = (n + 6) ** 3
     args = (sf, n, n, n, 3, 0.1, 0.1, 0.1, None)
     assert L.z4c_constraints_noalloc(FAKE, None, FAKE2, *args) == z4c.EINVAL

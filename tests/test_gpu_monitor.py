@@ -65,13 +65,24 @@ def test_monitor_stage_parity(oz, case, stage):
         g, u, _ = I.config_punctures(32)
     dt = 0.25 * min(g.h)
     (mon, plain), u_used = _run(u, g, dt, stage)
+    m = g.active_mask()
+    for nm, a, b in (("u_out", mon[0], plain[0]), ("acc", mon[1], plain[1])):
+        for f in range(a.shape[0]):
+            x, y = a[f][m], b[f][m]
+            nd = int(np.count_nonzero(x != y))
+            if nd:
+                i = int(np.argmax(np.abs(x - y)))
+                print(f"{nm} field {f}: {nd} of {x.size} active points differ, max |d| {abs(x[i] - y[i]):.3e} "
+                      f"at {x[i]!r} vs {y[i]!r}")
+        ng = int(np.count_nonzero(~((a == b) | (np.isnan(a) & np.isnan(b)))[:, ~m]))
+        if ng:
+            print(f"{nm}: {ng} ghost entries differ")
     # the stage is untouched by the monitor (both outputs start as NaN: the
     # ghosts of a periodic or copy box are not written by a stage)
     assert np.array_equal(mon[0], plain[0], equal_nan=True) and np.array_equal(mon[1], plain[1], equal_nan=True)
     assert np.all(np.isfinite(mon[0][:, g.active_mask()]))
     c, n = mon[2], mon[3]
     cr, nr, sc, sn = _oracle(oz, u_used, g)
-    m = g.active_mask()
     e = normrel(c, cr, m)
     en = np.abs(n - nr) / np.maximum(np.abs(nr), 1e-300)
     print("H, M^i normrel:", " ".join(f"{x:.1e}" for x in e), " oracle sensitivity:",

@@ -53,7 +53,7 @@ def test_noalloc_matches_workspace_two_calls_smaller_second():
 
 
 def test_noalloc_full_size_norms_match():
-    """The headline box size (256^3 punctures, 32768 bricks)."""
+    """The headline box size (256^3 punctures, 65536 bricks of 8x8x4)."""
     print("case: z4c_constraints_noalloc 256^3 punctures norms", flush=True)
     g, u0, _ = I.config_punctures(256)
     u = to_dev(u0)

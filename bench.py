@@ -294,7 +294,7 @@ def cpu_baseline(I, n=256):
     ng = g.ng
     nall = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     runs = {}
-    for nth, planes in ((1, 8), (nall, 64)):
+    for nth, planes in ((1, 24), (nall, 192)):
         k0 = ng + n // 2 - planes // 2
         K, J, X = np.meshgrid(np.arange(k0, k0 + planes), np.arange(ng, ng + n), np.arange(ng, ng + n), indexing="ij")
         pts = np.stack([X.ravel(), J.ravel(), K.ravel()], axis=1).astype(np.int32)

@@ -393,6 +393,7 @@ def main():
             "kernel": "fused_stage", "ms_per_launch": [round(x, 4) for x in ms],
             "ms_per_launch_mean": round(sum(ms) / 4, 4),
             "alg_bytes_per_launch": bytes_stage, "alg_bytes_per_launch_mean": sum(bytes_stage) // 4,
+            "kernel_resources": z4c.tile_resources(params.precision, best),
             "kernel_source_sha256": digest[:16]}
 
     extras = {}
@@ -407,7 +408,9 @@ def main():
         pm = z4c.default_params(precision=z4c.MIXED)
         sec_m, best_m, src_m, fin_m = run([box], pm, None)
         extras["mixed"] = {"value": active * args.steps / sec_m, "ms_per_step": 1e3 * sec_m / args.steps,
-                           "tile": list(best_m.as_tuple()), "tune_source": src_m, "finite": fin_m}
+                           "tile": list(best_m.as_tuple()), "tune_source": src_m, "finite": fin_m,
+                           "kernel_resources": z4c.tile_resources(pm.precision, best_m),
+                           "fp64_kernel_resources": z4c.tile_resources(params.precision, best)}
         ge, ue, dte = I.config_punctures_equatorial(args.n)
         sec_e, best_e, src_e, fin_e = run([I.Box(ge, ue, None, dte)], params, None)
         extras["equatorial"] = {"value": ge.active * args.steps / sec_e, "ms_per_step": 1e3 * sec_e / args.steps,

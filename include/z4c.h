@@ -231,6 +231,16 @@ int z4c_tile_get(int precision, int index, z4c_tile* out);
  * compiled. */
 int z4c_select_tile(int precision, const z4c_tile* tile);
 
+/* Resources of the compiled kernel of one tile shape (the LDS-DMA form that
+ * boxes with 16-byte aligned rows run; tile->persistent is ignored), as the
+ * HIP runtime reports them for the current device: resident waves per SIMD
+ * (occupancy), static LDS bytes per block, scratch (register spill) bytes per
+ * lane.  Outputs are host ints.  Z4C_EINVAL for an unknown precision or a
+ * NULL argument, Z4C_EUNSUPPORTED if the shape is not compiled, Z4C_EHIP if
+ * the runtime query fails.  Enqueues nothing. */
+int z4c_tile_resources(int precision, const z4c_tile* tile, int* waves_per_simd, int* lds_bytes,
+                       int* scratch_bytes);
+
 /* Where a plan's tile shape came from (z4c_plan_tile, z4c_autotune). */
 typedef enum {
     Z4C_TILE_DEFAULT = 0, /* the library default (8x8x8 bricks, two waves per SIMD, persistent) */

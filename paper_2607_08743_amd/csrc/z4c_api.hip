@@ -440,6 +440,20 @@ int z4c_select_tile(int precision, const z4c_tile* tile)
     return Z4C_OK;
 }
 
+int z4c_tile_resources(int precision, const z4c_tile* tile, int* waves_per_simd, int* lds_bytes, int* scratch_bytes)
+{
+    if (precision != Z4C_FP64 && precision != Z4C_MIXED) return fail(Z4C_EINVAL, "unknown precision");
+    if (!tile || !waves_per_simd || !lds_bytes || !scratch_bytes)
+        return fail(Z4C_EINVAL, "tile and the three outputs must be non-NULL");
+    const int idx = find_tile(precision, tile);
+    if (idx < 0) return fail(Z4C_EUNSUPPORTED, "no compiled tile of that shape");
+    const TileEntry* t = nullptr;
+    tile_table(&t);
+    const hipError_t e = t[idx].resources(waves_per_simd, lds_bytes, scratch_bytes);
+    if (e != hipSuccess) return hip_fail(e, "kernel attribute query");
+    return Z4C_OK;
+}
+
 int rhs_z4c(const double* u, double* rhs, long sf, int nx, int ny, int nz, int ng, double dx, double dy, double dz,
             double x0, double y0, double z0, int bc, const z4c_params* p, void* stream)
 {

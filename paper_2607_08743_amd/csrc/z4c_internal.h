@@ -86,6 +86,9 @@ struct TileEntry {
     // enqueue the fused kernel over every brick of `set`
     hipError_t (*launch)(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent,
                          hipStream_t s);
+    // resources of the shape's LDS-DMA kernel (the one aligned boxes run):
+    // resident waves per SIMD, static LDS bytes per block, scratch bytes per lane
+    hipError_t (*resources)(int* waves_per_simd, int* lds_bytes, int* scratch_bytes);
 };
 
 int tile_table(const TileEntry** out);  // returns the number of entries

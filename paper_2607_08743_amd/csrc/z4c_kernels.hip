@@ -1299,8 +1299,25 @@ hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, in
 // ------------------------------------------------------------------------
 // Table of compiled tile shapes (first entry of each precision = default)
 // ------------------------------------------------------------------------
+template <typename R, int BX, int BY, int BZ, int WV>
+hipError_t tile_resources(int* waves_per_simd, int* lds_bytes, int* scratch_bytes)
+{
+    const void* fn = reinterpret_cast<const void*>(&fused_stage<R, BX, BY, BZ, WV, true, false>);
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    int per = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fused_stage<R, BX, BY, BZ, WV, true, false>,
+                                                          BX * BY * BZ, 0)) != hipSuccess)
+        return e;
+    *waves_per_simd = per * (BX * BY * BZ / 64) / 4;  // four SIMDs per compute unit
+    *lds_bytes = (int)fa.sharedSizeBytes;
+    *scratch_bytes = (int)fa.localSizeBytes;
+    return hipSuccess;
+}
+
 #define Z4C_TILE(R, PREC, BX, BY, BZ, WV) \
-    {{BX, BY, BZ, WV, 0}, PREC, &launch_fused<R, BX, BY, BZ, WV>}
+    {{BX, BY, BZ, WV, 0}, PREC, &launch_fused<R, BX, BY, BZ, WV>, &tile_resources<R, BX, BY, BZ, WV>}
 
 static const TileEntry kTiles[] = {
     Z4C_TILE(double, Z4C_FP64, 8, 8, 4, 1),

@@ -95,6 +95,7 @@ def lib(path: str = LIB_PATH):
     L.z4c_tile_count.argtypes = [i]
     L.z4c_tile_get.argtypes = [i, i, ctypes.POINTER(Tile)]
     L.z4c_select_tile.argtypes = [i, ctypes.POINTER(Tile)]
+    L.z4c_tile_resources.argtypes = [i, ctypes.POINTER(Tile), ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.z4c_plan_create.argtypes = [ctypes.POINTER(Box), i, pp, ctypes.POINTER(Tile), ctypes.c_char_p,
                                   ctypes.POINTER(vp)]
     L.z4c_plan_tile.argtypes = [vp, ctypes.POINTER(Tile), ctypes.POINTER(i)]
@@ -120,6 +121,7 @@ def lib(path: str = LIB_PATH):
     L.z4c_last_error.argtypes = []
     L.z4c_last_error.restype = ctypes.c_char_p
     for name in ("rhs_z4c", "rk4_substep", "rk4_substep_monitor", "apply_ghosts", "z4c_tile_count", "z4c_tile_get", "z4c_select_tile",
+                 "z4c_tile_resources",
                  "z4c_plan_create", "z4c_plan_step", "z4c_plan_autotune", "z4c_plan_destroy", "z4c_constraints",
                  "z4c_plan_tile", "z4c_autotune", "z4c_tune_lookup", "z4c_constraints_noalloc",
                  "z4c_hier_create", "z4c_hier_advance", "z4c_hier_destroy", "z4c_hier_set_moving", "z4c_hier_puncture"):
@@ -286,6 +288,15 @@ def tiles(precision: int = FP64):
 
 def select_tile(precision: int, tile: Tile = None):
     check(lib().z4c_select_tile(precision, None if tile is None else ctypes.byref(tile)), "z4c_select_tile")
+
+
+def tile_resources(precision: int, tile: Tile) -> dict:
+    """z4c_tile_resources: occupancy (resident waves per SIMD), static LDS
+    bytes per block and scratch bytes per lane of a compiled tile shape."""
+    w, s, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().z4c_tile_resources(precision, ctypes.byref(tile), ctypes.byref(w), ctypes.byref(s), ctypes.byref(x)),
+          "z4c_tile_resources")
+    return {"waves_per_simd": w.value, "lds_bytes": s.value, "scratch_bytes_per_lane": x.value}
 
 
 class Stepper:

@@ -49,6 +49,18 @@ def test_tiles_enumerate(L):
     assert L.z4c_tile_get(z4c.FP64, 999, ctypes.byref(bad)) == z4c.EINVAL
 
 
+def test_tile_resources_validation(L):
+    """z4c_tile_resources refuses bad arguments before any HIP call."""
+    w, s, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    good = z4c.Tile(8, 8, 8, 2, 1)
+    assert L.z4c_tile_resources(7, ctypes.byref(good), ctypes.byref(w), ctypes.byref(s), ctypes.byref(x)) == z4c.EINVAL
+    assert L.z4c_tile_resources(z4c.FP64, None, ctypes.byref(w), ctypes.byref(s), ctypes.byref(x)) == z4c.EINVAL
+    assert L.z4c_tile_resources(z4c.FP64, ctypes.byref(good), None, ctypes.byref(s), ctypes.byref(x)) == z4c.EINVAL
+    bad = z4c.Tile(3, 3, 3, 1, 0)
+    assert L.z4c_tile_resources(z4c.FP64, ctypes.byref(bad), ctypes.byref(w), ctypes.byref(s),
+                                ctypes.byref(x)) == z4c.EUNSUPPORTED
+
+
 def _rhs(L, p, u=FAKE, r=FAKE2, sf=100000, n=(8, 8, 8), ng=3, h=(0.1, 0.1, 0.1), bc=0):
     return L.rhs_z4c(u, r, sf, n[0], n[1], n[2], ng, h[0], h[1], h[2], 0.0, 0.0, 0.0, bc, ctypes.byref(p), None)
 

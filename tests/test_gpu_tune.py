@@ -57,3 +57,17 @@ def test_plan_default_on_key_miss(tmp_path):
     tile, src = p.tile()
     assert src == "default" and tile.as_tuple() == (8, 8, 8, 2, 1)
     p.close()
+
+
+def test_tile_resources_of_the_benchmark_shapes():
+    """z4c_tile_resources reports what the compiler built: the 8x8x8 two-wave
+    shapes hold two waves per SIMD (one 512-thread block per compute unit);
+    the FP64 form spills a few registers, the mixed form none."""
+    print("case: tile resources 8x8x8x2 FP64 and mixed", flush=True)
+    t = z4c.Tile(8, 8, 8, 2, 1)
+    r64 = z4c.tile_resources(z4c.FP64, t)
+    rmx = z4c.tile_resources(z4c.MIXED, t)
+    print(r64, rmx)
+    assert r64["waves_per_simd"] == 2 and rmx["waves_per_simd"] == 2
+    assert 0 < r64["lds_bytes"] <= 163840 and 0 < rmx["lds_bytes"] <= 163840
+    assert r64["scratch_bytes_per_lane"] > 0 and rmx["scratch_bytes_per_lane"] == 0

@@ -122,7 +122,10 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2, 8))
     const long chunk = (long)gridDim.x / 8;
     const long w = (long)(blockIdx.x % 8) * chunk + blockIdx.x / 8;
     if (w >= nbk) return;  // the whole block: no barrier is left waiting
-    const int bxi = (int)(w % B.nb[0]), byi = (int)((w / B.nb[0]) % B.nb[1]), bzi = (int)(w / ((long)B.nb[0] * B.nb[1]));
+    // brick order x fastest, then z, then y: the resident blocks of an XCD
+    // (two per CU) take whole x rows of consecutive z layers, so the z halos,
+    // the largest part of a thin 8x8x4 brick's tile, are fetched through one L2
+    const int bxi = (int)(w % B.nb[0]), bzi = (int)((w / B.nb[0]) % B.nb[2]), byi = (int)(w / ((long)B.nb[0] * B.nb[2]));
     const int ng = B.ng;
     const int Nx = B.n[0] + 2 * ng, Ny = B.n[1] + 2 * ng, Nz = B.n[2] + 2 * ng;
     const int i0 = bxi * CX, j0 = byi * CY, k0 = bzi * CZ;

@@ -211,15 +211,17 @@ def test_persistent_dma_register_bitwise(prec):
     torch.cuda.empty_cache()
 
 
-def test_plan_persistent_128_stages(oz):
-    """The benchmark's launch: a persistent plan (tile 8x8x8x2, 4096 bricks
-    per launch against 256 resident blocks) over the 128^3 puncture box,
-    one RK4 step replayed from the captured graph.  Stages 3 and 4 are read
-    back from the plan's own buffers (B holds u2, A holds u3, the
-    accumulator acc3) and checked against the oracle at sampled points; the
-    whole step is bitwise equal to the non-persistent single-box path."""
-    print("case: persistent plan 128^3 punctures vs oracle stages 3, 4 and vs single-box path", flush=True)
-    g, u, dt = I.config_punctures(128)
+@pytest.mark.parametrize("n", [128, 256])
+def test_plan_persistent_stages(oz, n):
+    """The benchmark's launch: a persistent plan (tile 8x8x8x2; 4096 and
+    32768 bricks per launch against 256 resident blocks) over the n^3
+    puncture box (256^3 is the benchmark's own box), one RK4 step replayed
+    from the captured graph.  Stages 3 and 4 are read back from the plan's
+    own buffers (B holds u2, A holds u3, the accumulator acc3) and checked
+    against the oracle at sampled points; the whole step is bitwise equal to
+    the non-persistent single-box path."""
+    print(f"case: persistent plan {n}^3 punctures vs oracle stages 3, 4 and vs single-box path", flush=True)
+    g, u, dt = I.config_punctures(n)
     ozp = _ozp(oz, z4c.default_params())
     plan = z4c.Plan([I.Box(g, u, None, dt)], tile=PERSISTENT)
     plan.step(1, use_graph=True)
@@ -227,9 +229,10 @@ def test_plan_persistent_128_stages(oz):
     new, a_h, b_h, acc_h = to_host(plan.u[0]), to_host(a), to_host(b), to_host(acc)
     plan.close()
     del plan, a, b, acc
-    pts = evolved_points(g, sample=3000, seed=128)
-    check_stage(oz, ozp, g, 3, dt, b_h, u, None, a_h, None, pts, "plan 128^3")
-    check_stage(oz, ozp, g, 4, dt, a_h, None, acc_h, new, None, pts, "plan 128^3")
+    torch.cuda.empty_cache()
+    pts = evolved_points(g, sample=3000, seed=n)
+    check_stage(oz, ozp, g, 3, dt, b_h, u, None, a_h, None, pts, f"plan {n}^3")
+    check_stage(oz, ozp, g, 4, dt, a_h, None, acc_h, new, None, pts, f"plan {n}^3")
     del a_h, b_h, acc_h
     st = z4c.Stepper(g, u, dt)  # default tile: not persistent
     st.step(1)

@@ -39,8 +39,8 @@ TUNE_CACHE = os.path.join(ROOT, "paper_2607_08743_amd", "tune_cache.jsonl")
 # Keyed by the SHA-256 of the kernel source the counters were taken on: once
 # the source changes the figure no longer applies and `traffic` is null.
 MEASURED_TRAFFIC = {
-    "7c3bc424c4abf32fafed4eee2ace5390a927b6e6e6ef1563d7f9c53c4503f886": {"tile": (8, 8, 8, 2, 1), "n": 256, "bytes_per_launch": 21963500000,
-        "fetch_bytes": 15830100000, "write_bytes": 6133400000,
+    "8677e60113e02e1541cdfb8989bb2611ead4496d8524874d49dcb9052834dd4e": {"tile": (8, 8, 8, 2, 1), "n": 256, "bytes_per_launch": 21961500000,
+        "fetch_bytes": 15856000000, "write_bytes": 6105500000,
         "profile": "profiles/fused_stage_256cube_punctures_fp64.md"},
 }
 

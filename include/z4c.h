@@ -131,8 +131,10 @@ int rk4_substep(int stage, double dt, const double* u_in, const double* u_n, dou
  *   c      device, NULL or 4 fields of stride sf (H, M^x, M^y, M^z); ghost entries set to 0
  *   norms  device, 4 doubles
  *   ws     device workspace of ws_len >= z4c_monitor_workspace(nx, ny, nz) doubles
- *          (per-wave partial sums; the norms sum them in a fixed order, so they
- *          are bitwise reproducible, though not bitwise those of z4c_constraints,
+ *          (an upper bound; one record of four sums per wave of the launch,
+ *          each wave summing its bricks in the order it walks them, and the
+ *          norms sum the records in a fixed order: bitwise reproducible run
+ *          to run on one device, though not bitwise those of z4c_constraints,
  *          whose reduction tree differs)
  * c, norms and ws must not overlap each other or the state arrays.  Other
  * arguments, aliasing rules and errors as for rk4_substep. */

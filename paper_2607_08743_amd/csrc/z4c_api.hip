@@ -537,7 +537,7 @@ long z4c_monitor_workspace(int nx, int ny, int nz)
 {
     if (nx < 1 || ny < 1 || nz < 1) return 0;
     const int n[3] = {nx, ny, nz};
-    return monitor_bricks(n) * 8 * 4;
+    return monitor_records_max(n) * 4;
 }
 
 int rk4_substep_monitor(int stage, double dt, const double* u_in, const double* u_n, double* acc, double* u_out,
@@ -589,12 +589,13 @@ int rk4_substep_monitor(int stage, double dt, const double* u_in, const double* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pending HIP error before rk4_substep_monitor");
     if (c && (e = launch_zero(c, 4 * sf, s)) != hipSuccess) return hip_fail(e, "rk4_substep_monitor zero fill");
-    if ((e = launch_stage_monitor(set, pd, MODE_STAGE, stage, MonDev{c, ws}, s)) != hipSuccess)
+    long records = 0;
+    if ((e = launch_stage_monitor(set, pd, MODE_STAGE, stage, MonDev{c, ws}, s, &records)) != hipSuccess)
         return hip_fail(e, "rk4_substep_monitor fused launch");
     if ((bc == Z4C_BC_SOMMERFELD || bc == Z4C_BC_EQUATORIAL) &&
         (e = launch_sommerfeld(set, pd, MODE_STAGE, stage, s)) != hipSuccess)
         return hip_fail(e, "rk4_substep_monitor Sommerfeld launch");
-    if ((e = launch_norms(ws, need / 4, 1.0 / ((double)nx * ny * nz), norms, s)) != hipSuccess)
+    if ((e = launch_norms(ws, records, 1.0 / ((double)nx * ny * nz), norms, s)) != hipSuccess)
         return hip_fail(e, "rk4_substep_monitor norms");
     return Z4C_OK;
 }

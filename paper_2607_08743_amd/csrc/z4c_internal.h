@@ -69,12 +69,15 @@ enum Mode : int { MODE_RHS = 0, MODE_STAGE = 1 };
 // Outputs of the constraint monitor fused into a stage (unused otherwise).
 struct MonDev {
     double* c;     // NULL or 4 fields of the box's stride: H, M^x, M^y, M^z at the active points
-    double* part;  // per (brick, wave): sums of H^2, (M^x)^2, (M^y)^2, (M^z)^2
+    double* part;  // per wave of the grid: sums of H^2, (M^x)^2, (M^y)^2, (M^z)^2 over its bricks
 };
 // a float64 stage (or RHS) of one box with the monitor of its input; bricks
-// of 8^3, eight waves each (monitor_bricks(n) * 8 * 4 doubles of part)
+// of 8^3, eight waves each.  part takes at most monitor_records_max(n) * 4
+// doubles; *records is the number the launch writes.
 long monitor_bricks(const int n[3]);
-hipError_t launch_stage_monitor(const BoxSet& set, const ParamsDev& p, int mode, int stage, MonDev mon, hipStream_t s);
+long monitor_records_max(const int n[3]);
+hipError_t launch_stage_monitor(const BoxSet& set, const ParamsDev& p, int mode, int stage, MonDev mon, hipStream_t s,
+                                long* records);
 // fixed-order sum of n partial rows of 4 and the four L2 norms sqrt(sum / cells)
 hipError_t launch_norms(const double* partial, long n, double inv_cells, double* norms, hipStream_t s);
 hipError_t launch_zero(double* x, long n, hipStream_t s);

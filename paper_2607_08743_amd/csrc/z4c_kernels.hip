@@ -236,6 +236,58 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     }
 }
 
+// finish_point over one of two field subsets: METRIC = gt and At (with the
+// enforcement), else the 13 others
+template <bool METRIC, typename KF>
+__device__ __forceinline__ void finish_subset(const BoxDev& B, int mode, int stage, KF kf, size_t p)
+{
+    constexpr int NS = METRIC ? 12 : 13;
+    auto fld = [](int r) {
+        if (METRIC) return r < 6 ? F_GT + r : F_AT + (r - 6);
+        return r == 0 ? F_W : r == 1 ? F_KH : r < 5 ? F_GAM + (r - 2) : r == 5 ? F_TH : r == 6 ? F_AL
+             : r < 10 ? F_BE + (r - 7) : F_BB + (r - 10);
+    };
+    const size_t sf = (size_t)B.sf;
+    if (mode == MODE_RHS) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r) B.u_out[fld(r) * sf + p] = kf(fld(r));
+        return;
+    }
+    const double dt = B.dt;
+    const double c = stage == 3 ? dt : (stage == 4 ? dt / 6.0 : 0.5 * dt);
+    const double* base = stage == 1 ? B.u_in : (stage == 4 ? B.acc : B.u_n);
+    const bool upd = stage == 2 || stage == 3;
+    double gt[6], At[6];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+        if (r % 5 == 0) __asm__ volatile("" ::: "memory");
+        const int f = fld(r);
+        const double k = kf(f);
+        const double u0 = base[f * sf + p];
+        const double v = u0 + c * k;
+        if (stage == 1)
+            B.acc[f * sf + p] = u0 + (dt / 6.0) * k;
+        else if (upd)
+            B.acc[f * sf + p] = B.acc[f * sf + p] + (dt / 3.0) * k;
+        if (METRIC) {
+            if (r < 6)
+                gt[r] = v;
+            else
+                At[r - 6] = v;
+        } else {
+            B.u_out[f * sf + p] = v;
+        }
+    }
+    if constexpr (METRIC) {
+        enforce(gt, At);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            B.u_out[(F_GT + q) * sf + p] = gt[q];
+            B.u_out[(F_AT + q) * sf + p] = At[q];
+        }
+    }
+}
+
 // ------------------------------------------------------------------------
 // Fused right-hand side + RK4 substep over bricks of active points.
 // ------------------------------------------------------------------------
@@ -314,6 +366,9 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
     constexpr int NPARK = PARK_FIT < 0 ? 0 : (PARK_FIT > 16 ? 16 : PARK_FIT);
     __shared__ __attribute__((aligned(16))) TT tiles[NBUF * TNP];
     __shared__ __attribute__((aligned(16))) R park[(NPARK > 0 ? NPARK : 1) * NT];
+    // MON: per-wave running sums of H^2 and (M^i)^2 over the bricks the wave
+    // walks; only lane 0 of the wave reads or writes its four slots
+    __shared__ double mon_acc[MON ? (NT / 64) * 4 : 1];
     // Buffer k of the tile.  The offset is made opaque to the compiler, so
     // that it adds it to the per-lane offsets when used instead of keeping
     // one precomputed address per buffer and lane offset live in registers.
@@ -339,6 +394,12 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
     // walk it NS bricks at a time: bricks processed together, and in
     // consecutive rounds, are neighbours (x fastest, then y), so most of
     // their halos come from that XCD's L2.
+    if constexpr (MON) {
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) mon_acc[(tid >> 6) * 4 + m] = 0.0;
+        }
+    }
     const long G = gridDim.x;
     const long b = blockIdx.x;
     const long total = set.brick_begin[set.nbox];
@@ -1011,15 +1072,23 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
                 m2[a] = wave_sum(valid ? M * M : 0.0);
             }
             if ((tid & 63) == 0) {
-                double* out = mon.part + ((size_t)w * (NT / 64) + (size_t)(tid >> 6)) * 4;
-                out[0] = mon_h2;
-                out[1] = m2[0];
-                out[2] = m2[1];
-                out[3] = m2[2];
+                double* a = mon_acc + (tid >> 6) * 4;
+                a[0] += mon_h2;
+                a[1] += m2[0];
+                a[2] += m2[1];
+                a[3] += m2[2];
             }
         }
         if (!valid) continue;  // no barrier below this point
         finish_point<true>(B, mode, stage, [&](int f) { return k[f]; }, p);
+    }
+    if constexpr (MON) {
+        // one record per wave of the grid, in brick order within the wave
+        if ((tid & 63) == 0) {
+            double* out = mon.part + ((size_t)blockIdx.x * (NT / 64) + (size_t)(tid >> 6)) * 4;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) out[m] = mon_acc[(tid >> 6) * 4 + m];
+        }
     }
 }
 
@@ -1037,7 +1106,7 @@ inline bool dma_compatible(const BoxSet& set)
 
 template <typename R, int BX, int BY, int BZ, int WAVES, bool DMA, bool MON = false>
 hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int stage, int persistent, hipStream_t s,
-                          MonDev mon = MonDev{})
+                          MonDev mon = MonDev{}, long* grid_out = nullptr)
 {
     const long total = set.brick_begin[set.nbox];
     if (total <= 0) return hipSuccess;
@@ -1056,6 +1125,7 @@ hipError_t launch_variant(const BoxSet& set, const ParamsDev& p, int mode, int s
         if (grid > cap) grid = cap;
     }
     grid = (grid + 7) / 8 * 8;  // whole XCD rounds (idle blocks exit at once)
+    if (grid_out) *grid_out = grid;
     hipLaunchKernelGGL((fused_stage<R, BX, BY, BZ, WAVES, DMA, MON>), dim3((unsigned)grid), dim3(BX * BY * BZ), 0, s,
                        *run, p, mode, stage, mon);
     return hipGetLastError();
@@ -1073,12 +1143,20 @@ hipError_t launch_fused(const BoxSet& set, const ParamsDev& p, int mode, int sta
 }  // namespace
 
 // One float64 stage with the constraint monitor of its input (single box,
-// 8x8x8 bricks with two waves per SIMD, persistent).
+// 8x8x8 bricks with two waves per SIMD, persistent).  The launch leaves one
+// record of four sums per wave of its grid (*records of them); the grid never
+// exceeds the bricks rounded up to a multiple of 8.
 long monitor_bricks(const int n[3]) { return (long)((n[0] + 7) / 8) * ((n[1] + 7) / 8) * ((n[2] + 7) / 8); }
-hipError_t launch_stage_monitor(const BoxSet& set, const ParamsDev& p, int mode, int stage, MonDev mon, hipStream_t s)
+long monitor_records_max(const int n[3]) { return (monitor_bricks(n) + 7) / 8 * 8 * 8; }
+hipError_t launch_stage_monitor(const BoxSet& set, const ParamsDev& p, int mode, int stage, MonDev mon, hipStream_t s,
+                                long* records)
 {
-    if (dma_compatible(set)) return launch_variant<double, 8, 8, 8, 2, true, true>(set, p, mode, stage, 1, s, mon);
-    return launch_variant<double, 8, 8, 8, 2, false, true>(set, p, mode, stage, 1, s, mon);
+    long grid = 0;
+    hipError_t e = dma_compatible(set)
+                       ? launch_variant<double, 8, 8, 8, 2, true, true>(set, p, mode, stage, 1, s, mon, &grid)
+                       : launch_variant<double, 8, 8, 8, 2, false, true>(set, p, mode, stage, 1, s, mon, &grid);
+    *records = grid * 8;
+    return e;
 }
 
 namespace {
@@ -1230,6 +1308,9 @@ __device__ __forceinline__ double dsomm(const double* u, size_t p, int i, int N,
 // of a Sommerfeld box; those at and above the symmetry plane of an
 // equatorial box): d_t f = -(x^i/r) d_i f - (f - f_flat)/r (paper Sec.
 // 2.2.2), then the same RK4 stage update and enforcement as the interior.
+// Two threads per ghost point (blockIdx.y): one takes gt and At, whose
+// enforcement needs all twelve, the other the 13 remaining fields, which
+// doubles the loads in flight of this latency-bound update.
 __global__ void __launch_bounds__(256) sommerfeld_ghosts(BoxSet set, int mode, int stage)
 {
     const long w = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1255,7 +1336,10 @@ __global__ void __launch_bounds__(256) sommerfeld_ghosts(BoxSet set, int mode, i
                         + (z * ir) * dsomm(u, p, k, Nz, (long)Nx * Ny, B.h[2]);
         return -dr - (u[p] - flat_of(f)) * ir;
     };
-    finish_point<false>(B, mode, stage, kf, p);
+    if (blockIdx.y == 0)
+        finish_subset<true>(B, mode, stage, kf, p);
+    else
+        finish_subset<false>(B, mode, stage, kf, p);
 }
 
 __global__ void __launch_bounds__(256) zero_ghost_rhs(BoxSet set)
@@ -1291,7 +1375,7 @@ hipError_t launch_sommerfeld(const BoxSet& set, const ParamsDev& p, int mode, in
     const long total = set.shell_begin[set.nbox];
     if (total <= 0) return hipSuccess;
     const dim3 grid((unsigned)((total + 255) / 256));
-    hipLaunchKernelGGL(sommerfeld_ghosts, grid, dim3(256), 0, s, set, mode, stage);
+    hipLaunchKernelGGL(sommerfeld_ghosts, dim3(grid.x, 2), dim3(256), 0, s, set, mode, stage);
     if (mode == MODE_RHS) hipLaunchKernelGGL(zero_ghost_rhs, grid, dim3(256), 0, s, set);
     return hipGetLastError();
 }

@@ -177,11 +177,11 @@ __device__ __forceinline__ void enforce(double* gt, double* At)
     for (int q = 0; q < 6; ++q) At[q] -= gt[q] * tr;
 }
 
-// Write the RK4 stage (or the raw right-hand side) of one point; kf(f)
-// returns the right-hand side of field f.  Fields outside gt/At are stored as
-// soon as they are updated; the 12 metric and curvature values wait for the
-// enforcement.
-template <bool BULK, typename KF>
+// Write the RK4 stage (or the raw right-hand side) of one point of the fused
+// kernel; kf(f) returns the right-hand side of field f.  Fields outside gt/At
+// are stored as soon as they are updated; the 12 metric and curvature values
+// wait for the enforcement.
+template <typename KF>
 __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stage, KF kf, size_t p)
 {
     const size_t sf = (size_t)B.sf;
@@ -195,32 +195,28 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     // stage 1 and 4 update u_in and acc, stages 2 and 3 update u_n (and acc)
     const double* base = stage == 1 ? B.u_in : (stage == 4 ? B.acc : B.u_n);
     const bool upd = stage == 2 || stage == 3;
-    // BULK: every load is issued before the first is used (one round trip
-    // per point; the caller has the registers to spare); otherwise five
-    // fields at a time.  The empty asm keeps the loads from being hoisted
-    // above this point, into code that has no registers for them.
-    double b0[BULK ? NF : 1], b1[BULK ? NF : 1];
+    // Every load is issued before the first is used (one round trip per
+    // point; the caller has the registers to spare).  The empty asm keeps the
+    // loads from being hoisted above this point, into code that has no
+    // registers for them.
+    double b0[NF], b1[NF];
     __asm__ volatile("" ::: "memory");
-    if constexpr (BULK) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) b0[f] = base[f * sf + p];
-        if (upd) {
+    for (int f = 0; f < NF; ++f) b0[f] = base[f * sf + p];
+    if (upd) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) b1[f] = B.acc[f * sf + p];
-        }
+        for (int f = 0; f < NF; ++f) b1[f] = B.acc[f * sf + p];
     }
     double gt[6], At[6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        if constexpr (!BULK)
-            if (f % 5 == 0) __asm__ volatile("" ::: "memory");
         const double k = kf(f);
-        const double u0 = BULK ? b0[f] : base[f * sf + p];
+        const double u0 = b0[f];
         const double v = u0 + c * k;
         if (stage == 1)
             B.acc[f * sf + p] = u0 + (dt / 6.0) * k;
         else if (upd)
-            B.acc[f * sf + p] = (BULK ? b1[f] : B.acc[f * sf + p]) + (dt / 3.0) * k;
+            B.acc[f * sf + p] = b1[f] + (dt / 3.0) * k;
         if (f >= F_GT && f < F_GT + 6)
             gt[f - F_GT] = v;
         else if (f >= F_AT && f < F_AT + 6)
@@ -236,8 +232,10 @@ __device__ __forceinline__ void finish_point(const BoxDev& B, int mode, int stag
     }
 }
 
-// finish_point over one of two field subsets: METRIC = gt and At (with the
-// enforcement), else the 13 others
+// The stage update of finish_point for the Sommerfeld ghosts, over one of two
+// field subsets: METRIC = gt and At (with the enforcement), else the 13
+// others; loads five fields at a time (the empty asm keeps later fields' loads
+// from being hoisted, which would cost registers this kernel's occupancy needs)
 template <bool METRIC, typename KF>
 __device__ __forceinline__ void finish_subset(const BoxDev& B, int mode, int stage, KF kf, size_t p)
 {
@@ -1080,7 +1078,7 @@ fused_stage(BoxSet set, ParamsDev prm, int mode, int stage, MonDev mon)
             }
         }
         if (!valid) continue;  // no barrier below this point
-        finish_point<true>(B, mode, stage, [&](int f) { return k[f]; }, p);
+        finish_point(B, mode, stage, [&](int f) { return k[f]; }, p);
     }
     if constexpr (MON) {
         // one record per wave of the grid, in brick order within the wave

@@ -322,7 +322,7 @@ def main():
     ap.add_argument("--tile", default="", help="bx,by,bz,waves,persistent (skip the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for the HBM byte counters)")
-    ap.add_argument("--only", choices=["bbh_moving", "bbh_moving_equatorial"], default="",
+    ap.add_argument("--only", choices=["bbh_moving", "bbh_moving_equatorial", "constraints"], default="",
                     help="run only this extra measurement and print its JSON")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="tuning cache file (JSON lines); empty string: time every shape, persist nothing")
@@ -342,6 +342,10 @@ def main():
     from paper_2607_08743_amd import z4c
 
     torch.cuda.set_device(0)
+    if args.only == "constraints":
+        g, u0, _ = I.config_punctures(args.n)
+        print(json.dumps({"constraints": constraint_monitor_rate(z4c, torch, g, u0, args.n)}), flush=True)
+        return
     if args.only:
         print(json.dumps({args.only: bbh_moving_rate(z4c, I, torch, equatorial=args.only.endswith("equatorial"))}),
               flush=True)

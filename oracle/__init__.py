@@ -36,8 +36,10 @@ something other than itself):
   differentiated exactly: this pins the computed Gamma_d in the
   Lie-derivative terms and the kappa3 terms.
 
-Parity unpinned (no physics pin distinguishes the alternatives; both paths
-must agree): ``lapse_uses_K`` (1+log with Khat or Khat + 2 Theta).
+* the lapse trace: with zero shift, lapse_uses_K = 1 keeps alpha - ln det
+  gamma constant (d_t alpha = tr(gamma^-1 d_t gamma) from the ADM metric
+  evolution) on data with Theta != 0; the default (Khat) exceeds that by
+  4 alpha Theta.
 """
 from __future__ import annotations
 

@@ -103,6 +103,45 @@ def test_lapse_flag_uses_full_trace(oz):
     np.testing.assert_allclose(r1[18][m], -2 * (0.01 + 2 * 0.02))
 
 
+def test_lapse_flag_against_volume_element(oz):
+    """1+log slicing driven by the trace of the extrinsic curvature keeps
+    alpha - ln(det gamma) constant along the normal: with zero shift,
+    d_t alpha = d_t ln det gamma = tr(gamma^-1 d_t gamma), the latter from the
+    ADM metric evolution d_t gamma = -2 alpha K.  On data with Theta != 0
+    (Khat = K - 2 Theta) lapse_uses_K = 1 obeys that to rounding (the lapse
+    and W rows are pointwise at zero shift); the default (Khat) exceeds it by
+    4 alpha Theta, the Z4c choice of keeping Theta out of the slicing.  The W
+    row, the volume element itself, follows the physical trace under both."""
+    prim = A.generic_prim()
+    st = A.conformal_state_fn(prim)
+
+    def theta(x):
+        return 0.05 * (torch.sin(x[0] - 2 * x[2]) + 0.4 * torch.cos(x[1]))
+
+    def state(x):
+        u = st(x)
+        th = theta(x).reshape(1)
+        return torch.cat([u[:7], u[7:8] - 2.0 * th, u[8:17], th, u[18:]])
+
+    def expected(x):
+        g, K, a, _, _ = prim(x)
+        dlog = torch.trace(torch.linalg.solve(g, -2.0 * a * K))  # d_t ln det gamma
+        W = torch.linalg.det(g) ** (-1.0 / 6.0)
+        return torch.stack([-W * dlog / 6.0, dlog, dlog + 4.0 * a * theta(x)])
+
+    g = I.centered_grid(8, 1.0 / 8, center=(0.3, -0.2, 0.1), bc=I.BC_COPY)
+    u = A.evaluate(state, g)
+    m = g.active_mask()
+    X, Y, Z = g.coords()
+    xs = torch.tensor(np.stack([X[m], Y[m], Z[m]], axis=1), dtype=torch.float64)
+    ex = torch.vmap(expected)(xs).numpy().T
+    assert np.abs(4.0 * u[18][m] * u[17][m]).min() > 1e-3  # the two slicings differ here
+    for flag, row in ((1, 1), (0, 2)):
+        r = oz.rhs(u, g.as_dict(), oz.params(ko_sigma=0.0, lapse_uses_K=flag))
+        np.testing.assert_allclose(r[0][m], ex[0], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(r[18][m], ex[row], rtol=0, atol=1e-14)
+
+
 @pytest.mark.parametrize("kappa3", [0.0, 1.0])
 def test_gt_shift_terms_with_constraint_violation(oz, kappa3):
     """The shift terms of the Gt equation on data with Gt != Gt_d (a

@@ -114,14 +114,15 @@ def _perturb_curvature(u, g):
     return v
 
 
-@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("n", [128, 256, 320])
 def test_constraints_full_size_sampled(oz, n):
     """At the benchmark sizes: the full-box GPU constraints at sampled 8^3
     blocks (corners, where the stencils reach the Sommerfeld ghosts, the
     punctures and the centre) against the oracle run on a cut-out of the
     stored state that holds those blocks plus their 3-cell stencil margin.
     The puncture data carry a smooth perturbation of the extrinsic
-    curvature, so that all four constraints are non-zero."""
+    curvature, so that all four constraints are non-zero.  At 320^3 the
+    later fields of the state start beyond 2^32 bytes."""
     print(f"case: constraints perturbed punctures {n}^3 sampled blocks", flush=True)
     g, u, _ = I.config_punctures(n)
     u = _perturb_curvature(u, g)

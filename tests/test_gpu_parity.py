@@ -13,6 +13,7 @@ from paper_2607_08743_amd import z4c
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
+THETA = 17  # field index of Theta
 
 
 def gpu_rhs(u, g, params=None):
@@ -171,11 +172,13 @@ def test_pi_symmetry_noisy_plane_wave_bitwise():
     assert pi_mirror_equal(to_host(st.u), I.PI_PARITY)
 
 
-@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("n", [128, 256, 320])
 def test_full_size_sampled(oz, n):
     """Full workload size, launch configuration of the benchmark: the
     right-hand side and the first RK4 stage at sampled points (corners,
-    faces, ghosts, punctures' neighbourhood and random interior points)."""
+    faces, ghosts, punctures' neighbourhood and random interior points).
+    At 320^3 one state array holds 6.9 GB, so the byte offsets of the later
+    fields pass 2^32."""
     print(f"case: full size {n}^3 sampled parity", flush=True)
     g, u, dt = I.config_punctures(n)
     N = g.shape[1:]
@@ -194,7 +197,21 @@ def test_full_size_sampled(oz, n):
     r_h, out_h = to_host(r), to_host(out)
     sel = (slice(None), pts[:, 2], pts[:, 1], pts[:, 0])
     ref_r = oz.rhs_points(u, g.as_dict(), pts).T
-    assert normrel(r_h[sel], ref_r).max() <= TOL
+    e = normrel(r_h[sel], ref_r)
+    # Theta's right-hand side on these data is alpha/2 times the Hamiltonian
+    # constraint of data that solve it: a cancellation whose own one-ulp
+    # sensitivity (the oracle's, on inputs perturbed by one ulp) is 2e-8 to
+    # 6e-8 norm-relative at 256^3 and 320^3.  It is held to that; every other
+    # field to the flat bar.
+    rng_u = np.random.default_rng(1)
+    u_p = u + np.spacing(u) * rng_u.choice([-1.0, 1.0], size=u.shape)
+    sens = normrel(oz.rhs_points(u_p, g.as_dict(), pts).T, ref_r)
+    del u_p
+    print("rhs per-field normrel:", " ".join(f"{x:.1e}" for x in e), flush=True)
+    print("Theta: normrel", f"{e[THETA]:.2e}", "oracle one-ulp sensitivity", f"{sens[THETA]:.2e}", flush=True)
+    others = np.arange(25) != THETA
+    assert e[others].max() <= TOL, e
+    assert e[THETA] <= max(TOL, sens[THETA]), (e[THETA], sens[THETA])
     ref_s = oz.stage_points(u, u, 0.5 * dt, g.as_dict(), pts).T
     assert normrel(out_h[sel], ref_s).max() <= TOL
     del du, r, acc, out

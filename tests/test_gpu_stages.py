@@ -211,11 +211,12 @@ def test_persistent_dma_register_bitwise(prec):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("n", [128, 256, 320])
 def test_plan_persistent_stages(oz, n):
-    """The benchmark's launch: a persistent plan (tile 8x8x8x2; 4096 and
-    32768 bricks per launch against 256 resident blocks) over the n^3
-    puncture box (256^3 is the benchmark's own box), one RK4 step replayed
+    """The benchmark's launch: a persistent plan (tile 8x8x8x2; 4096, 32768
+    and 64000 bricks per launch against 256 resident blocks) over the n^3
+    puncture box (256^3 is the benchmark's own box; at 320^3 each state array
+    passes 2^32 bytes), one RK4 step replayed
     from the captured graph.  Stages 3 and 4 are read back from the plan's
     own buffers (B holds u2, A holds u3, the accumulator acc3) and checked
     against the oracle at sampled points; the whole step is bitwise equal to

@@ -206,12 +206,12 @@ __global__ void __launch_bounds__(CNT) __attribute__((amdgpu_waves_per_eu(2, 8))
         dma_issue(cseq(0), 0);
         dma_issue(cseq(1), 1);
     }
+    // (no pin on the gradient: the Hessian that follows it reuses its LDS
+    // reads of the axis neighbours)
     auto grad = [&](double* d) {
         d[0] = cd1(t, 1, i12h[0]);
         d[1] = cd1(t, SX, i12h[1]);
         d[2] = cd1(t, SXY, i12h[2]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) keep(d[c]);
     };
     // second derivatives; the memory clobbers keep the compiler from issuing
     // the LDS reads of all six at once (each read holds two registers until

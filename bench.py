@@ -356,7 +356,7 @@ def main():
                     help="tuning cache file (JSON lines); empty string: time every shape, persist nothing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -55,7 +55,7 @@ typedef enum {
     Z4C_EINVAL = -1,       /* invalid argument (nothing enqueued) */
     Z4C_EHIP = -2,         /* the HIP runtime reported an error */
     Z4C_ENOMEM = -3,       /* device or host allocation failed (plan and hierarchy APIs only) */
-    Z4C_EUNSUPPORTED = -4  /* valid request this build cannot serve (e.g. no such tile) */
+    Z4C_EUNSUPPORTED = -4  /* valid request the compiled library cannot serve (e.g. no such tile) */
 } z4c_status;
 
 typedef enum {
@@ -305,7 +305,7 @@ int z4c_autotune(const z4c_box* boxes, int nbox, const z4c_params* p, const char
 /* Host-only cache query: the cached shape for architecture `arch` (e.g.
  * "gfx950"), precision, and the box count and bucket of `boxes` (only their
  * extents n are read).  Returns 1 and fills *tile on a hit, 0 on a miss (also
- * for a missing file or a shape this build does not compile), Z4C_EINVAL for
+ * for a missing file or a shape the library does not compile), Z4C_EINVAL for
  * a corrupt file or invalid arguments.  Makes no HIP call. */
 int z4c_tune_lookup(const char* tune_cache_path, const char* arch, const z4c_box* boxes, int nbox, int precision,
                     z4c_tile* tile);

@@ -137,3 +137,88 @@ def test_hierarchy_box64_50_steps_fp64_and_mixed_vs_oracle(oz):
     print("mixed error / change vs oracle:", " ".join(f"{n}={x:.1e}" for n, x in zip(I.FIELD_NAMES, rel)))
     assert np.all(np.isfinite(got[z4c.MIXED]))
     assert np.all(rel[dev > 1e-8] < 1e-3), rel
+
+
+@pytest.mark.parametrize("n", [(18, 13, 11), (17, 12, 10)])
+def test_mixed_all_tiles_bitwise(oz, n):
+    """Every compiled mixed-precision tile shape, persistent or not, gives the
+    same bits on a ragged box of several bricks (the per-point arithmetic does
+    not depend on the brick shape): 18 x 13 x 11 takes the LDS-DMA staging
+    (float64 tiles), 17 x 12 x 10 (odd row length) the register staging
+    (float32 tiles).  The result is at float32 rounding level against the
+    float64 oracle."""
+    print(f"case: mixed rhs ragged {n}, every mixed tile", flush=True)
+    g = I.centered_grid(n, (0.1, 0.12, 0.09), bc=I.BC_PERIODIC)
+    u = I.random_strong_field_state(g, seed=13)
+    du = to_dev(u)
+    z4c.apply_ghosts(du, g)
+    oz.apply_ghosts(u, g.as_dict())
+    outs = []
+    try:
+        for t in z4c.tiles(z4c.MIXED):
+            z4c.select_tile(z4c.MIXED, t)
+            r = torch.empty_like(du)
+            z4c.rhs_z4c(du, r, g, _mixed())
+            outs.append((t.as_tuple(), to_host(r)))
+    finally:
+        z4c.select_tile(z4c.MIXED, None)
+    assert len(outs) > 1
+    for shape, r in outs[1:]:
+        assert np.array_equal(r, outs[0][1]), shape
+    ref = oz.rhs(u, g.as_dict())
+    m = g.active_mask()
+    floor = 1e-3 * np.abs(ref[:, m]).max()
+    e = _field_errors(outs[0][1][:, m], ref[:, m], floor)
+    print(" ".join(f"{nm}={x:.1e}" for nm, x in zip(I.FIELD_NAMES, e)))
+    assert e.max() < 1e-3, e
+
+
+def test_mixed_benchmark_shape_256_sampled(oz):
+    """The 256^3 puncture box in mixed precision with the benchmark's tile
+    for it (8x8x4 bricks, two waves, not persistent): the right-hand side and
+    the first RK4 stage at sampled points against the float64 oracle, at
+    float32 rounding level, and bitwise equal to the persistent 8x8x8 shape."""
+    print("case: mixed 256^3 punctures, tile 8x8x4x2 vs oracle at sampled points", flush=True)
+    g, u, dt = I.config_punctures(256)
+    N = g.shape[1:]
+    rng = np.random.default_rng(7)
+    pts = [rng.integers(0, N[0], size=(1200, 3))]
+    ng = g.ng
+    edge = [0, ng - 1, ng, N[0] // 2, N[0] - ng - 1, N[0] - ng, N[0] - 1]
+    pts.append(np.array([(a, b, c) for a in edge for b in edge for c in edge[::2]]))
+    pts = np.concatenate(pts).astype(np.int32)
+    sel = (slice(None), pts[:, 2], pts[:, 1], pts[:, 0])
+    du = to_dev(u)
+    res = {}
+    try:
+        for t in (z4c.Tile(8, 8, 4, 2, 0), z4c.Tile(8, 8, 8, 2, 1)):
+            z4c.select_tile(z4c.MIXED, t)
+            r = torch.empty_like(du)
+            z4c.rhs_z4c(du, r, g, _mixed())
+            acc = torch.empty_like(du)
+            out = torch.empty_like(du)
+            z4c.rk4_substep(1, dt, du, None, acc, out, g, _mixed())
+            res[t.as_tuple()] = (to_host(r)[sel], to_host(out)[sel], to_host(acc)[sel])
+            del r, acc, out
+    finally:
+        z4c.select_tile(z4c.MIXED, None)
+    a, b = res[(8, 8, 4, 2, 0)], res[(8, 8, 8, 2, 1)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    gd = g.as_dict()
+    ref_r = oz.rhs_points(u, gd, pts).T
+    floor = 1e-3 * np.abs(ref_r).max()
+    e = _field_errors(a[0], ref_r, floor)
+    print("rhs:", " ".join(f"{nm}={x:.1e}" for nm, x in zip(I.FIELD_NAMES, e)))
+    assert e.max() < 1e-3, e
+    ref_s = oz.stage_points(u, u, 0.5 * dt, gd, pts).T
+    base = u[sel]
+    moved = np.abs(ref_s - base).max(axis=1)
+    err = np.abs(a[1] - ref_s).max(axis=1)
+    # relative to how far each field moved, floored at 1e-3 of the largest
+    # move (Theta's right-hand side is a cancellation on these data)
+    rel = err / np.maximum(moved, 1e-3 * moved.max())
+    print("stage 1:", " ".join(f"{nm}={x:.1e}" for nm, x in zip(I.FIELD_NAMES, rel)))
+    assert rel.max() < 1e-3, rel
+    del du
+    torch.cuda.empty_cache()

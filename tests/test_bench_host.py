@@ -35,3 +35,31 @@ def test_more_than_one_gpu_is_refused():
                          text=True, timeout=300)
     assert out.returncode == 2
     assert "one GPU" in out.stdout
+
+
+def test_measured_traffic_belongs_to_the_committed_kernel():
+    """The HBM traffic the bench line reports was counted on the kernel source
+    that is committed (the figure is keyed by the source's SHA-256), with the
+    headline tile and box, and fetched plus written bytes add up."""
+    b = _bench()
+    digest = b.kernel_source_digest()
+    assert digest in b.MEASURED_TRAFFIC, "kernel source changed since the traffic counters were taken"
+    m = b.MEASURED_TRAFFIC[digest]
+    assert tuple(m["tile"]) == (8, 8, 8, 2, 1) and m["n"] == 256
+    assert m["bytes_per_launch"] == m["fetch_bytes"] + m["write_bytes"]
+    assert os.path.exists(os.path.join(ROOT, m["profile"]))
+    with open(os.path.join(ROOT, m["profile"])) as f:
+        assert digest[:16] in f.read()
+
+
+def test_committed_tune_cache_covers_the_benchmark_workloads():
+    """The committed tuning cache holds a shape for every benchmark workload
+    (256^3 and 128^3 boxes and the equatorial half box in float64, 256^3 in
+    mixed precision, the 9-box hierarchy in both), so the bench line takes
+    its tiles from it instead of timing them."""
+    import json
+    with open(os.path.join(ROOT, "paper_2607_08743_amd", "tune_cache.jsonl")) as f:
+        keys = {(e["arch"], e["precision"], e["nbox"], e["bucket"]) for e in map(json.loads, filter(str.strip, f))}
+    for key in (("gfx950", 0, 1, 24), ("gfx950", 0, 1, 21), ("gfx950", 0, 1, 23), ("gfx950", 1, 1, 24),
+                ("gfx950", 0, 9, 23), ("gfx950", 1, 9, 23)):
+        assert key in keys, key

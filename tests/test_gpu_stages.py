@@ -242,6 +242,43 @@ def test_plan_persistent_stages(oz, n):
     torch.cuda.empty_cache()
 
 
+def test_plan_persistent_equatorial_benchmark_box(oz):
+    """The benchmark's equatorial workload: the z >= 0 half (256 x 256 x 128
+    cells) of the 256^3 puncture box, reflection at z = 0 and Sommerfeld
+    elsewhere, in a persistent plan (8x8x8 bricks, two waves), one RK4 step
+    replayed from the graph.  Stages 3 and 4 against the oracle at sampled
+    points (the plane's layers among them); the step bitwise equal to the
+    non-persistent single-box path."""
+    print("case: persistent plan, equatorial half of the 256^3 punctures", flush=True)
+    g, u, dt = I.config_punctures_equatorial(256)
+    ozp = _ozp(oz, z4c.default_params())
+    plan = z4c.Plan([I.Box(g, u, None, dt)], tile=PERSISTENT)
+    plan.step(1, use_graph=True)
+    a, b, acc, _ = plan._keep[0]
+    new, a_h, b_h, acc_h = to_host(plan.u[0]), to_host(a), to_host(b), to_host(acc)
+    plan.close()
+    del plan, a, b, acc
+    torch.cuda.empty_cache()
+    ng = g.ng
+    pts = evolved_points(g, sample=3000, seed=3)
+    plane = np.array([(i, j, k) for i in (ng, 64, 200, g.n[0] + ng - 1) for j in (ng, 128, g.n[1] + ng - 1)
+                      for k in (ng, ng + 1, ng + 2)], dtype=pts.dtype)
+    pts = np.concatenate([pts, plane])
+    check_stage(oz, ozp, g, 3, dt, b_h, u, None, a_h, None, pts, "equatorial plan")
+    check_stage(oz, ozp, g, 4, dt, a_h, None, acc_h, new, None, pts, "equatorial plan")
+    del a_h, b_h, acc_h
+    st = z4c.Stepper(g, u, dt)  # default tile: not persistent
+    st.step(1)
+    got = to_host(st.u)
+    # the plan leaves the mirrored layers to the next step's fill; compare
+    # what both paths evolve
+    m = np.zeros(g.shape[1:], dtype=bool)
+    m[ng:] = True
+    assert np.array_equal(got[:, m], new[:, m])
+    del st
+    torch.cuda.empty_cache()
+
+
 def test_plan_graph_stages_three_boxes(oz):
     """Three copy boxes of uneven size in one plan, graph replays: stages 3
     and 4 of every box at every step against the oracle (all active points)."""

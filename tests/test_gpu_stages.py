@@ -66,26 +66,50 @@ def _at(u, pts):
 
 def check_stage(oz, ozp, g, stage, dt, src, un, acc_prev, out, acc, pts, label):
     """Stage output and accumulator of one substep against the oracle on the
-    GPU's own inputs (host arrays), at the points pts."""
+    GPU's own inputs (host arrays), at the points pts.  The bar is 1e-12 per
+    field, norm-relative; a field above it is held instead to the oracle's
+    own one-ulp sensitivity for the same evaluation (its inputs perturbed by
+    one ulp), where that is larger: a field whose stage values are a
+    cancellation (Theta on puncture data, which starts at 0 and moves by dt
+    times alpha/2 times the Hamiltonian constraint of data that solve it)."""
     gd = g.as_dict()
     c = {1: 0.5 * dt, 2: 0.5 * dt, 3: dt, 4: dt / 6.0}[stage]
     base = {1: src, 2: un, 3: un, 4: acc_prev}[stage]
     ref = oz.stage_points(src, base, c, gd, pts, ozp).T
     e = normrel(_at(out, pts), ref)
-    worst = [e.max()]
-    if stage < 4 and acc is not None:
+    has_acc = stage < 4 and acc is not None
+    if has_acc:
         k = oz.rhs_points(src, gd, pts, ozp).T
-        ref_acc = _at(src, pts) + (dt / 6.0) * k if stage == 1 else _at(acc_prev, pts) + (dt / 3.0) * k
+        accb = src if stage == 1 else acc_prev
+        ref_acc = _at(accb, pts) + (dt / 6.0 if stage == 1 else dt / 3.0) * k
         ea = normrel(_at(acc, pts), ref_acc)
-        worst.append(ea.max())
-        assert ea.max() <= TOL, (label, stage, "acc", ea)
-    print(f"{label} stage {stage}: max per-field normrel output {worst[0]:.2e}"
-          + (f", acc {worst[1]:.2e}" if len(worst) > 1 else ""), flush=True)
-    assert e.max() <= TOL, (label, stage, "u_out", e)
+    bound = bound_acc = np.full(e.shape, TOL)
+    if e.max() > TOL or (has_acc and ea.max() > TOL):
+        rng = np.random.default_rng(0)
+
+        def pert(x):
+            return x + np.spacing(x) * rng.choice([-1.0, 1.0], size=x.shape)
+        src_p = pert(src)
+        base_p = src_p if base is src else pert(base)
+        bound = np.maximum(TOL, normrel(oz.stage_points(src_p, base_p, c, gd, pts, ozp).T, ref))
+        if has_acc:
+            accb_p = src_p if stage == 1 else pert(acc_prev)
+            k_p = oz.rhs_points(src_p, gd, pts, ozp).T
+            ref_acc_p = _at(accb_p, pts) + (dt / 6.0 if stage == 1 else dt / 3.0) * k_p
+            bound_acc = np.maximum(TOL, normrel(ref_acc_p, ref_acc))
+        del src_p, base_p
+        over = np.nonzero((e > TOL) | ((ea > TOL) if has_acc else False))[0]
+        print(f"{label} stage {stage}: fields above 1e-12 {list(over)}: normrel {e[over]}, "
+              f"oracle one-ulp sensitivity {bound[over]}", flush=True)
+    print(f"{label} stage {stage}: max per-field normrel output {e.max():.2e}"
+          + (f", acc {ea.max():.2e}" if has_acc else ""), flush=True)
+    if has_acc:
+        assert np.all(ea <= bound_acc), (label, stage, "acc", ea, bound_acc)
+    assert np.all(e <= bound), (label, stage, "u_out", e, bound)
     # the stage moved the state by much more than the tolerance (non-trivial comparison)
     moved = normrel(ref, _at(base, pts))
     assert moved.max() > 1e3 * TOL, (label, stage, moved)
-    return max(worst)
+    return max(e.max(), ea.max()) if has_acc else e.max()
 
 
 def stage_chain(oz, g, u0, dt, nsteps, params=None, shell=None, pts=None, label=""):
@@ -296,6 +320,27 @@ def test_plan_graph_stages_three_boxes(oz):
             check_stage(oz, ozp, bx.grid, 3, bx.dt, to_host(b), un, None, to_host(a), None, pts, lab)
             check_stage(oz, ozp, bx.grid, 4, bx.dt, to_host(a), None, to_host(acc), to_host(ub), None, pts, lab)
     plan.close()
+
+
+def test_plan_nine_boxes_benchmark_sizes(oz):
+    """The benchmark's 9-box workload (copy boxes of 160^3 down to 64^3, 13.5 M
+    active cells) in one persistent plan (8x8x8 bricks, two waves), one step
+    replayed from the graph: stages 3 and 4 of every box against the oracle
+    at sampled points."""
+    print("case: plan of the 9 benchmark boxes (160^3 .. 64^3), persistent, graph, stages 3 and 4", flush=True)
+    boxes = I.config_hierarchy()
+    ozp = _ozp(oz, z4c.default_params())
+    old = [bx.state for bx in boxes]
+    plan = z4c.Plan(boxes, tile=PERSISTENT)
+    plan.step(1, use_graph=True)
+    for k, (bx, un, ub, keep) in enumerate(zip(boxes, old, plan.u, plan._keep)):
+        a, b, acc, _ = keep
+        pts = evolved_points(bx.grid, sample=600, seed=k)
+        lab = f"plan box {bx.grid.n[0]}^3"
+        check_stage(oz, ozp, bx.grid, 3, bx.dt, to_host(b), un, None, to_host(a), None, pts, lab)
+        check_stage(oz, ozp, bx.grid, 4, bx.dt, to_host(a), None, to_host(acc), to_host(ub), None, pts, lab)
+    plan.close()
+    torch.cuda.empty_cache()
 
 
 def _covered(gp, children):
